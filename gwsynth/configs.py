@@ -24,7 +24,8 @@ class Config:
     eps_naf: float        # NAF eigenvalue threshold (strict ">")
     max_keep: int         # cap on kept NAFs (0 = no cap)
     naf_target: int       # NAF count the tensor scale is tuned to give
-    tau: float            # singular-value decay s_j = exp(-j / tau)
+    tau: float            # singular-value decay s_j = exp(-j / tau); 0 = derived
+                          # from naf_target (gwsynth.problem.decay_length)
     n_lt: int             # Laplace points
     n_freq: int           # imaginary-frequency integration points
     n_pade: int           # Pade points
@@ -63,19 +64,19 @@ TINY = Config(name="tiny", n_occ=10, n_fc=2, n_virt=40, n_aux=150,
 
 # ~1000 basis functions (a water cluster of ~25 molecules in size).
 MEDIUM = Config(name="medium", n_occ=100, n_fc=30, n_virt=900, n_aux=3000,
-                eps_naf=1e-2, max_keep=0, naf_target=1500, tau=400.0,
+                eps_naf=1e-2, max_keep=0, naf_target=1500, tau=0.0,
                 n_lt=10, n_freq=60, n_pade=16, n_qp_occ=5, n_qp_virt=5,
                 seed=2)
 
 # ~2500 basis functions.
 LARGE = Config(name="large", n_occ=300, n_fc=80, n_virt=2200, n_aux=7000,
-               eps_naf=1e-2, max_keep=0, naf_target=3500, tau=7000 / 7.5,
+               eps_naf=1e-2, max_keep=0, naf_target=3500, tau=0.0,
                n_lt=12, n_freq=80, n_pade=16, n_qp_occ=10, n_qp_virt=10,
                seed=3)
 
 # ~7400 basis functions (the size of the BODIPY tetramer).
 PAPER = Config(name="paper", n_occ=950, n_fc=250, n_virt=6700, n_aux=20000,
-               eps_naf=1e-2, max_keep=0, naf_target=9000, tau=20000 / 7.5,
+               eps_naf=1e-2, max_keep=0, naf_target=9000, tau=0.0,
                n_lt=14, n_freq=100, n_pade=16, n_qp_occ=5, n_qp_virt=5,
                seed=4)
 

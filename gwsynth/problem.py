@@ -12,12 +12,13 @@ Recipe (all draws seeded; orbital indices are absolute, 0 = lowest):
   s_j = exp(-j / tau).
   - ``exact_orthonormal`` (the tiny molecule): V has exactly orthonormal
     rows over every unique orbital pair (frozen core included), c = 1.
-  - otherwise V_j(pq) = G_j(pq) / sqrt(n_norm) with G a counter-based
+  - otherwise V_j(pq) = G_j(pq) / sqrt(n_all) with G a counter-based
     (SplitMix64) uniform on [-sqrt 3, sqrt 3] keyed on (pair, j), so any
-    block of rows can be generated on its own and blocks agree.  n_norm is
-    the number of ordered non-virtual-virtual active pairs, o^2 + 2 o v.
-    The scale c puts the expected K-metric eigenvalue 2 c^2 s_j^2 equal to
-    ``eps_naf`` midway between j = naf_target - 1 and j = naf_target.
+    block of rows can be generated on its own and blocks agree; n_all is
+    the number of unordered pairs over all orbitals, so the rows are nearly
+    orthonormal over the pairs as in the tiny molecule, and c = 1.  Unless
+    the configuration fixes tau, it is chosen so that about naf_target
+    natural auxiliary functions exceed eps_naf (see ``decay_length``).
 
 Only the blocks the hot path reads are materialised, over active orbitals:
 ``R_oo`` [o][o][A], ``R_ov`` [o*v][A] (i-major: row i*v + a) and ``R_qp``
@@ -27,6 +28,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -90,6 +92,22 @@ def _energies(cfg: Config, rng: np.random.Generator) -> np.ndarray:
     return np.concatenate([core, occ, virt])
 
 
+def decay_length(cfg: Config) -> float:
+    """Decay length tau of s_j = exp(-j / tau).  With unit-variance pair
+    functions normalised over all n_all orbital pairs (c = 1, as for the tiny
+    molecule), the NAF metric has expected eigenvalues
+    2 f exp(-2 j / tau), f = (o^2 + 2 o v) / n_all; tau puts the eigenvalue
+    midway between j = naf_target - 1 and naf_target at eps_naf (1e-2 when
+    eps_naf is 0), unless the configuration fixes tau."""
+    if cfg.tau > 0:
+        return cfg.tau
+    o, v = cfg.n_act_occ, cfg.n_virt
+    n_tot = cfg.n_occ + cfg.n_virt
+    f = (o * o + 2 * o * v) / (n_tot * (n_tot + 1) / 2.0)
+    eps = cfg.eps_naf if cfg.eps_naf > 0 else 1e-2
+    return (2 * cfg.naf_target - 1) / math.log(2 * f / eps)
+
+
 def _haar(n: int, rng: np.random.Generator) -> np.ndarray:
     z = rng.standard_normal((n, n))
     q, r = np.linalg.qr(z)
@@ -111,8 +129,8 @@ class _RowSource:
         A = cfg.n_aux
         self.n_tot = cfg.n_occ + cfg.n_virt
         self.U = _haar(A, rng)
-        s = np.exp(-np.arange(A) / cfg.tau)
         if cfg.exact_orthonormal:
+            s = np.exp(-np.arange(A) / cfg.tau)
             n_pairs = self.n_tot * (self.n_tot + 1) // 2
             if n_pairs < A:
                 raise ValueError("exact_orthonormal needs n_pairs >= n_aux")
@@ -122,29 +140,37 @@ class _RowSource:
             self.all_rows = (vt * (self.c * s)[None, :]) @ self.U.T
         else:
             o, v = cfg.n_act_occ, cfg.n_virt
-            self.n_norm = float(o * o + 2 * o * v)
-            x = cfg.naf_target
-            self.c = math.sqrt(cfg.eps_naf / (2.0 * math.exp(-(2 * x - 1) / cfg.tau))) \
-                if cfg.eps_naf > 0 else math.sqrt(1e-2 / (2.0 * math.exp(-(2 * x - 1) / cfg.tau)))
-            self.colscale = (self.c / math.sqrt(self.n_norm)) * s * math.sqrt(3.0)
+            n_all = self.n_tot * (self.n_tot + 1) / 2.0
+            self.c = 1.0
+            self.tau = decay_length(cfg)
+            s = np.exp(-np.arange(A) / self.tau)
+            self.colscale = (self.c / math.sqrt(n_all)) * s * math.sqrt(3.0)
             self.key = _seed_key(cfg.seed)
             self.all_rows = None
 
+    def _g_block(self, idx: np.ndarray) -> np.ndarray:
+        A = self.cfg.n_aux
+        j = np.arange(A, dtype=np.uint64)
+        ctr = idx.astype(np.uint64)[:, None] * np.uint64(A) + j[None, :]
+        return (2.0 * splitmix64_uniform(self.key, ctr) - 1.0) * self.colscale[None, :]
+
     def rows(self, p: np.ndarray, q: np.ndarray, dtype=np.float64,
-             chunk: int = 2048) -> np.ndarray:
+             block: int = 16384, sub: int = 1024) -> np.ndarray:
         """B rows for orbital pairs (p[r], q[r]) (absolute indices)."""
+        import concurrent.futures
         idx = _pair_index(np.asarray(p), np.asarray(q), self.n_tot)
         if self.all_rows is not None:
             return self.all_rows[idx].astype(dtype)
         A = self.cfg.n_aux
         out = np.empty((idx.size, A), dtype=dtype)
-        j = np.arange(A, dtype=np.uint64)
         UT = self.U.T
-        for s0 in range(0, idx.size, chunk):
-            sl = idx[s0:s0 + chunk].astype(np.uint64)
-            ctr = sl[:, None] * np.uint64(A) + j[None, :]
-            g = 2.0 * splitmix64_uniform(self.key, ctr) - 1.0
-            out[s0:s0 + chunk] = (g * self.colscale[None, :]) @ UT
+        workers = min(16, os.cpu_count() or 1)
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+            for b0 in range(0, idx.size, block):
+                bi = idx[b0:b0 + block]
+                parts = list(ex.map(self._g_block,
+                                    [bi[s0:s0 + sub] for s0 in range(0, bi.size, sub)]))
+                out[b0:b0 + bi.size] = np.concatenate(parts) @ UT
         return out
 
 

@@ -1,0 +1,277 @@
+/*
+ * gwlt.h -- C ABI of the MI355X (gfx950) LT-AC G0W0 hot path.
+ *
+ * The operations follow Toelle, Niemeyer & Neugebauer, "Accelerating
+ * Analytic-Continuation GW Calculations with a Laplace Transformation and
+ * Natural Auxiliary Functions" (LT-GW).  Each entry point names the passage
+ * that defines what it computes.
+ *
+ * Conventions (apply to every call unless stated otherwise)
+ *   - Row-major storage, auxiliary (RI) index fastest.
+ *   - Orbital indices are absolute (0 = lowest orbital, frozen core first).
+ *     "Active" orbitals are those above the n_fc frozen-core orbitals.
+ *   - Occupied-virtual rows are i-major: row (i - i0) * n_virt + a, so
+ *     occupied chunks are contiguous.
+ *   - Three-index tensors are FP64 for GW_FP64 and FP32 for GW_FP32 and
+ *     GW_BF16X3 (the BF16 hi/lo split happens in the kernels' tile loads,
+ *     never in storage).  Matrices M, K, U are always FP64.
+ *   - Complex numbers are interleaved (re, im) FP64 pairs.
+ *   - "device" pointers are HIP device memory owned by the caller and
+ *     borrowed until the work enqueued by the call has completed on the
+ *     context's stream.  "host" arrays are read (or written) during the call
+ *     and may be reused as soon as it returns.
+ *   - Calls are asynchronous on the context's stream unless they return host
+ *     results (gw_naf_compress with finalize, gw_qp_solve, gw_g0w0), which
+ *     synchronise the stream before returning.
+ *   - Every call returns a gw_status and never throws or aborts.  Argument
+ *     errors are detected before anything is enqueued; the message is
+ *     available from gw_last_error.  Errors raised by device work (a
+ *     non-positive-definite pivot in the screening, a failed eigensolver)
+ *     are reported by the next synchronising call or gw_sync.
+ *   - One context per host thread; a context holds its workspace (device
+ *     memory grown on demand) and is not thread-safe.
+ */
+#ifndef GWLT_H
+#define GWLT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GW_OK = 0,
+  GW_EINVAL = 1,          /* invalid argument (null pointer, bad size)      */
+  GW_ENOMEM = 2,          /* device allocation failed                      */
+  GW_EDEVICE = 3,         /* HIP runtime or device error                   */
+  GW_ENOTSPD = 4,         /* 1 - Pi not positive definite in the screening */
+  GW_EPADE = 5,           /* Pade nodes coincide                           */
+  GW_ENOCONV = 6,         /* an iterative solver did not converge          */
+  GW_EUNSUPPORTED = 7     /* precision or mode not implemented             */
+} gw_status;
+
+typedef enum {
+  GW_FP64 = 0,            /* FP64 throughout                               */
+  GW_FP32 = 1,            /* contractions on FP32 MFMA, FP64 screening     */
+  GW_BF16X3 = 2           /* contractions as hi*hi + hi*lo + lo*hi BF16
+                             MFMA products with FP32 accumulation          */
+} gw_precision;
+
+typedef struct gw_ctx_s* gw_ctx;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The stream is borrowed. */
+gw_status gw_create(gw_ctx* out, int device, void* hip_stream);
+/* Release the context and its workspace (waits for its stream first). */
+gw_status gw_destroy(gw_ctx ctx);
+/* Switch the stream later calls enqueue on. */
+gw_status gw_set_stream(gw_ctx ctx, void* hip_stream);
+/* Wait for the stream; report deferred device-side errors. */
+gw_status gw_sync(gw_ctx ctx);
+/* Message of the last failure on ctx (ctx may be NULL: the calling thread's
+ * last failure of a context-free call).  Valid until the next call. */
+const char* gw_last_error(gw_ctx ctx);
+const char* gw_status_string(gw_status s);
+
+/* Kernel timing.  While enabled, HIP events bracket the hot kernels on the
+ * context's stream (the polarizability SYRK "syrk_f32"/"syrk_f64", the
+ * self-energy contraction "bwb_f32"/"bwb_f64", the screening sweep
+ * "screen_sweep", the NAF transform "naf_gemm_f32"/"naf_gemm_f64" and the
+ * eigensolver "naf_eig").  gw_profile_get (synchronises) returns, for one
+ * name, the summed event time (ms), the number of launches and the summed
+ * algorithmic flops and bytes of those launches; zeros if none ran.
+ * Enabling or disabling clears the accumulated figures. */
+gw_status gw_profile_enable(gw_ctx ctx, int enable);
+gw_status gw_profile_get(gw_ctx ctx, const char* kernel, double* total_ms,
+                         int64_t* launches, double* flops, double* bytes);
+
+/* ------------------------------------------------- a1: frozen core, bounds */
+
+/* Sec. 3 (computational details).  From all orbital energies eps[n_occ +
+ * n_virt] (host, ascending within the occupied and the virtual block) and
+ * the number n_fc of frozen-core orbitals: the Fermi level, taken as the
+ * HOMO-LUMO midpoint (the paper leaves it undefined), and the interval of
+ * the Laplace variable y = w^2 + (e_a - e_i)^2: y_min = (e_LUMO - e_HOMO)^2 +
+ * omega_min^2 (omega_min the smallest integration frequency) and y_max =
+ * max((e_vmax - e_i,min)^2, 1e4) over active occupied i.  Host only. */
+gw_status gw_prepare(int n_occ, int n_fc, int n_virt, const double* eps,
+                     double omega_min, double* eps_F, double* y_min,
+                     double* y_max);
+
+/* ------------------------------------------------------------ a3: grids */
+
+/* Modified Gauss-Legendre rule on [0, inf) (Sec. 2 after Eq. 7, Sec. 3):
+ * w_k = x0 (1 + t_k) / (1 - t_k), weight_k = 2 x0 v_k / (1 - t_k)^2 with
+ * (t_k, v_k) the n-point Gauss-Legendre rule; ascending w.  Host arrays of
+ * length n.  1 <= n <= 4096, x0 > 0. */
+gw_status gw_freq_grid_mgl(int n, double x0, double* omega, double* weight);
+
+/* Minimax Laplace grid (Eqs. 8-9, Sec. 3): points x[n_lt] and weights
+ * w[n_lt] (host, x ascending) minimising max |1/y - sum_m w_m exp(-x_m y)|
+ * on [y_min, y_max].  err_norm (may be NULL) receives the equioscillation
+ * level of the normalised problem on t = y / y_min in [1, y_max / y_min].
+ * 1 <= n_lt <= 16, 0 < y_min < y_max.  GW_ENOCONV if the Remez exchange
+ * fails. */
+gw_status gw_lt_grid_minimax(int n_lt, double y_min, double y_max,
+                             double* x, double* w, double* err_norm);
+
+/* Minimax of 1/t on [1, R] by n_lt exponentials (the normalised problem
+ * behind gw_lt_grid_minimax): alpha (ascending), omega host [n_lt], err the
+ * equioscillation level (may be NULL).  With a starting guess (alpha0,
+ * omega0, host [n_lt]) only the Remez exchange runs from it; with NULL the
+ * built-in table of converged solutions seeds it, falling back to a
+ * from-scratch start.  Used to regenerate that table. */
+gw_status gw_minimax_inverse(int n_lt, double R, const double* alpha0,
+                             const double* omega0, double* alpha,
+                             double* omega, double* err);
+
+/* ------------------------------------------------------------- a2: NAF */
+
+/* Natural auxiliary functions, Eqs. 11-13.  Adds the metric contribution
+ * of one chunk of rows, K += s (R_oo^T R_oo + 2 R_ov^T R_ov) with s = 2
+ * (closed shell; the virtual-virtual block is omitted, Sec. 2), into
+ * K (device [n_aux][n_aux] FP64; overwritten instead when accumulate == 0).
+ * R_oo (device [n_oo_rows][n_aux]) holds the occupied-occupied rows of both
+ * orders (ij and ji); R_ov (device [n_ov_rows][n_aux]) the
+ * occupied-virtual rows; either may be NULL with zero rows.
+ * With finalize != 0 the call then diagonalises K in FP64 on the device
+ * (K is destroyed), keeps the eigenvectors whose eigenvalue is > eps_naf
+ * (strict), at most max_keep of them when max_keep > 0, and writes
+ *   U       device [n_aux][n_aux] FP64: row p holds the eigenvector of the
+ *           p-th largest eigenvalue; rows 0 .. *n_naf-1 are the NAF basis
+ *           (U^T of Eq. 13),
+ *   *n_naf  host, number of kept functions (>= 1 unless all eigenvalues are
+ *           <= eps_naf, then 0),
+ *   eigvals host [n_aux] or NULL: eigenvalues in descending order.
+ * finalize synchronises the stream. */
+gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
+                          int64_t n_oo_rows, const void* R_oo,
+                          int64_t n_ov_rows, const void* R_ov, double* K,
+                          int accumulate, int finalize, double eps_naf,
+                          int max_keep, int* n_naf, double* U,
+                          double* eigvals);
+
+/* Eq. 13: R_out[r][q] = sum_P R_in[r][P] U[q][P] for q < n_naf.
+ * R_in device [n_rows][n_aux], R_out device [n_rows][n_naf], both FP64
+ * (GW_FP64) or FP32 (otherwise; the product is accumulated in FP32 MFMA
+ * with FP64 partial sums).  U as returned by gw_naf_compress. */
+gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int n_naf,
+                       const double* U, int64_t n_rows, const void* R_in,
+                       void* R_out);
+
+/* ----------------------------------------------- a4: LT polarizability */
+
+/* Eq. 10: for every Laplace point m,
+ *   M^m_PQ += sum_ia R_ia,P  w_m D_ia exp(-D_ia^2 x_m)  R_ia,Q,
+ * D_ia = eps_a[a] - eps_i[i], over one chunk of n_i active occupied
+ * orbitals.  x_lt, w_lt host [n_lt] (n_lt <= 32); eps_i host [n_i];
+ * eps_a host [n_virt]; R_chunk device [n_i * n_virt][n_naf] (i-major).
+ * M device [n_lt][n_naf][n_naf] FP64.  accumulate == 0 overwrites M,
+ * otherwise adds.  Only the lower triangle P >= Q is updated until a call
+ * with finalize != 0, which copies it onto the upper triangle (M is then
+ * exactly symmetric).  The scale is computed in FP64 and applied to one
+ * operand in the tile loads; FP32 and BF16x3 accumulate in FP32 within
+ * blocks of 256 rows and in FP64 across blocks. */
+gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_naf,
+                               int n_lt, const double* x_lt,
+                               const double* w_lt, int n_i, int n_virt,
+                               const double* eps_i, const double* eps_a,
+                               const void* R_chunk, int accumulate,
+                               int finalize, double* M);
+
+/* ------------------------------------------------ a5 + a6: screening */
+
+/* Eqs. 2 and 10: for each frequency j (omega host [n_w]),
+ *   Pi_j = -2 s sum_m exp(-omega_j^2 x_m) M^m   (s = 2),
+ *   W_hat_j = (1 - Pi_j)^-1 - 1,
+ * with the inverse formed in FP64 by a blocked symmetric Gauss-Jordan
+ * sweep.  M device [n_lt][n_naf][n_naf] FP64 (symmetric); x_lt host.
+ * W_hat device [n_w][n_naf][n_naf], FP64 for GW_FP64, FP32 otherwise
+ * (rounded from the FP64 result); both triangles are written.
+ * A non-positive pivot (1 - Pi not positive definite) is reported as
+ * GW_ENOTSPD by the next synchronising call. */
+gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_lt,
+                    const double* x_lt, const double* M, int n_w,
+                    const double* omega, void* W_hat);
+
+/* ------------------------------------- a7 + a8: diagonal self-energy */
+
+/* Eq. 2 then Eq. 7.  For every QP state n (row block of R_qp) and active
+ * orbital m:  W_nm(i omega_j) = R_nm^T W_hat_j R_nm  (the B.W.B
+ * contraction, on MFMA), then
+ *   Sigma_n(e_F + i wp_k) = -(1/pi) sum_j w_omega_j sum_m
+ *        a / (a^2 + omega_j^2) W_nm(i omega_j),  a = i wp_k + eps_F - eps_m,
+ * in FP64.  R_qp device [n_qp][n_mo][n_naf] (m over active orbitals);
+ * eps_mo host [n_mo] (active orbital energies); omega, w_omega host [n_w];
+ * W_hat as written by gw_screen; omega_pade host [n_pade].
+ * sigma_iw device [n_qp][n_pade] complex; accumulate != 0 adds this
+ * frequency batch to it.  W_nm: optional device [n_w][n_qp][n_mo] FP64
+ * output (NULL to skip). */
+gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
+                        int n_mo, const double* eps_mo, double eps_F,
+                        const void* R_qp, int n_w, const double* omega,
+                        const double* w_omega, const void* W_hat,
+                        int n_pade, const double* omega_pade, int accumulate,
+                        double* sigma_iw, double* W_nm);
+
+/* ------------------------------------------------ a9: Pade + QP solve */
+
+/* Sec. 2 and Sec. 3: Thiele continued-fraction Pade approximant through
+ * (i omega_pade_k, Sigma_n(e_F + i omega_pade_k)) (Vidberg-Serene), then the
+ * fixed point E = eps_n + Re Sigma_n(E - eps_F + i eta) + static_n from
+ * E = eps_n, stopping when |dE| < tol or after max_iter steps; FP64 on the
+ * device.  eps_n, static_n (NULL = 0) host [n_qp]; sigma_iw device as from
+ * gw_sigma_diag.  Outputs host [n_qp]: eps_qp, z_factor (may be NULL;
+ * Z = 1 / (1 - dRe Sigma/dE) at the solution), status (0 converged,
+ * 1 not converged within max_iter, 2 non-finite).  GW_EPADE when two
+ * Pade nodes coincide.  Synchronises the stream. */
+gw_status gw_qp_solve(gw_ctx ctx, int n_qp, const double* eps_n,
+                      const double* static_n, double eps_F, int n_pade,
+                      const double* omega_pade, const double* sigma_iw,
+                      double eta, double tol, int max_iter, double* eps_qp,
+                      double* z_factor, int* status);
+
+/* ------------------------------------------------- the whole G0W0 step */
+
+typedef struct {
+  int n_occ, n_fc, n_virt, n_aux;   /* orbital and auxiliary counts       */
+  int n_lt, n_freq, n_pade, n_qp;   /* grid sizes and number of QP states */
+  double eps_naf;                   /* NAF threshold (strict ">")         */
+  int max_keep;                     /* NAF cap, 0 = none                  */
+  double x0;                        /* modified GL scale (Ha), e.g. 0.5   */
+  double eta;                       /* real-axis broadening (Ha)          */
+  double tol;                       /* QP convergence (Ha)                */
+  int max_iter;                     /* QP iterations                      */
+  int freq_batch;                   /* frequencies per screening batch,
+                                       0 = all at once                    */
+} gw_params;
+
+typedef struct {
+  int n_naf;                        /* kept natural auxiliary functions   */
+  double lt_err_norm;               /* minimax level of the Laplace grid  */
+  double t_naf_ms, t_chi_ms, t_screen_ms, t_sigma_ms, t_qp_ms, t_total_ms;
+} gw_stats;
+
+/* One LT-AC G0W0 evaluation (a1-a9 in order): NAF compression of the raw
+ * tensors, grids, LT polarizability, screening, self-energy and QP energies.
+ * eps host [n_occ + n_virt]; qp host [n_qp] absolute indices of active QP
+ * orbitals; static_n host [n_qp] or NULL.  Raw tensors on the device over
+ * active orbitals: R_oo [o][o][n_aux], R_ov [o * n_virt][n_aux],
+ * R_qp [n_qp][o + n_virt][n_aux] (o = n_occ - n_fc), FP64 for GW_FP64 and
+ * FP32 otherwise.  Outputs host [n_qp]: eps_qp, z_factor (or NULL),
+ * status; sigma_iw host [n_qp][n_pade] complex or NULL; stats or NULL.
+ * Device intermediates live in the context's workspace.  Synchronises. */
+gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* params,
+                  const double* eps, const int* qp, const double* static_n,
+                  const void* R_oo, const void* R_ov, const void* R_qp,
+                  double* eps_qp, double* z_factor, int* status,
+                  double* sigma_iw, gw_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWLT_H */

@@ -1,0 +1,232 @@
+// Context lifetime, workspace, staging and error reporting.
+#include <cstdarg>
+
+#include "common.hpp"
+
+static thread_local std::string g_free_err;   // errors of context-free calls
+
+namespace gw {
+
+gw_status fail(gw_ctx ctx, gw_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf; else g_free_err = buf;
+  return st;
+}
+
+void clear_error(gw_ctx ctx) {
+  if (ctx) ctx->err.clear(); else g_free_err.clear();
+}
+
+gw_status hip_check(gw_ctx ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GW_OK;
+  return fail(ctx, e == hipErrorOutOfMemory ? GW_ENOMEM : GW_EDEVICE,
+              "%s: %s", what, hipGetErrorString(e));
+}
+
+gw_status launch_check(gw_ctx ctx, const char* what) {
+  return hip_check(ctx, hipGetLastError(), what);
+}
+
+void* ws_get(gw_ctx ctx, WsSlot slot, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (ctx->ws_bytes[slot] >= bytes) return ctx->ws[slot];
+  if (ctx->ws[slot]) {
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess ||
+        hipFree(ctx->ws[slot]) != hipSuccess) {
+      fail(ctx, GW_EDEVICE, "workspace release failed");
+      ctx->ws[slot] = nullptr;
+      ctx->ws_bytes[slot] = 0;
+      return nullptr;
+    }
+    ctx->ws[slot] = nullptr;
+    ctx->ws_bytes[slot] = 0;
+  }
+  size_t want = (bytes + 4095) & ~size_t(4095);
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(ctx, GW_ENOMEM, "workspace allocation of %zu bytes failed", want);
+    return nullptr;
+  }
+  ctx->ws[slot] = p;
+  ctx->ws_bytes[slot] = want;
+  return p;
+}
+
+const void* stage(gw_ctx ctx, const void* host, size_t bytes) {
+  size_t need = (bytes + 255) & ~size_t(255);
+  if (need > kStageBytes) {
+    fail(ctx, GW_EINVAL, "host array of %zu bytes exceeds the staging ring", bytes);
+    return nullptr;
+  }
+  if (ctx->stage_off + need > kStageBytes) {
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      fail(ctx, GW_EDEVICE, "stream synchronisation failed");
+      return nullptr;
+    }
+    ctx->stage_off = 0;
+  }
+  unsigned char* dev = static_cast<unsigned char*>(ctx->ws[WS_STAGE]);
+  std::memcpy(ctx->stage_host + ctx->stage_off, host, bytes);
+  if (hipMemcpyAsync(dev + ctx->stage_off, ctx->stage_host + ctx->stage_off,
+                     bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
+    fail(ctx, GW_EDEVICE, "staging copy failed");
+    return nullptr;
+  }
+  const void* out = dev + ctx->stage_off;
+  ctx->stage_off += need;
+  return out;
+}
+
+gw_status check_flags(gw_ctx ctx) {
+  int h[4] = {0, 0, 0, 0};
+  GW_HIP(ctx, hipMemcpyAsync(h, ctx->d_flags, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (h[0] != 0) {
+    GW_HIP(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof h, ctx->stream));
+    GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return fail(ctx, GW_ENOTSPD,
+                "1 - Pi is not positive definite at frequency index %d", h[0] - 1);
+  }
+  return GW_OK;
+}
+
+int prof_begin(gw_ctx ctx) {
+  if (!ctx->prof) return -1;
+  ProfEvent e;
+  if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return -1;
+  hipEventRecord(e.a, ctx->stream);
+  ctx->prof_pending.push_back(e);
+  return (int)ctx->prof_pending.size() - 1;
+}
+
+void prof_end(gw_ctx ctx, int idx, const char* name, double flops, double bytes) {
+  if (idx < 0 || idx >= (int)ctx->prof_pending.size()) return;
+  ProfEvent& e = ctx->prof_pending[idx];
+  e.name = name;
+  e.flops = flops;
+  e.bytes = bytes;
+  hipEventRecord(e.b, ctx->stream);
+}
+
+static void prof_resolve(gw_ctx ctx) {
+  for (ProfEvent& e : ctx->prof_pending) {
+    float ms = 0.f;
+    if (!e.name.empty() && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      ProfStat& s = ctx->prof_stats[e.name];
+      s.ms += ms;
+      s.flops += e.flops;
+      s.bytes += e.bytes;
+      s.launches += 1;
+    }
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  ctx->prof_pending.clear();
+}
+
+}  // namespace gw
+
+extern "C" {
+
+gw_status gw_profile_enable(gw_ctx ctx, int enable) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_profile_enable: ctx is NULL");
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  gw::prof_resolve(ctx);
+  ctx->prof_stats.clear();
+  ctx->prof = enable != 0;
+  return GW_OK;
+}
+
+gw_status gw_profile_get(gw_ctx ctx, const char* kernel, double* total_ms, int64_t* launches,
+                         double* flops, double* bytes) {
+  if (!ctx || !kernel) return gw::fail(ctx, GW_EINVAL, "gw_profile_get: NULL argument");
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  gw::prof_resolve(ctx);
+  auto it = ctx->prof_stats.find(kernel);
+  const ProfStat z{};
+  const ProfStat& s = it == ctx->prof_stats.end() ? z : it->second;
+  if (total_ms) *total_ms = s.ms;
+  if (launches) *launches = s.launches;
+  if (flops) *flops = s.flops;
+  if (bytes) *bytes = s.bytes;
+  return GW_OK;
+}
+
+gw_status gw_create(gw_ctx* out, int device, void* hip_stream) {
+  if (!out) return gw::fail(nullptr, GW_EINVAL, "gw_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return gw::fail(nullptr, GW_EINVAL, "gw_create: no HIP device %d", device);
+  if (hipSetDevice(device) != hipSuccess)
+    return gw::fail(nullptr, GW_EDEVICE, "gw_create: hipSetDevice failed");
+  gw_ctx c = new gw_ctx_s();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->stage_host), kStageBytes) != hipSuccess ||
+      !gw::ws_get(c, WS_STAGE, kStageBytes) ||
+      hipMalloc(reinterpret_cast<void**>(&c->d_flags), 4 * sizeof(int)) != hipSuccess ||
+      hipMemset(c->d_flags, 0, 4 * sizeof(int)) != hipSuccess) {
+    gw_destroy(c);
+    return gw::fail(nullptr, GW_ENOMEM, "gw_create: allocation failed");
+  }
+  *out = c;
+  return GW_OK;
+}
+
+void gw_release_rocblas(void* h);  // naf.hip
+
+gw_status gw_destroy(gw_ctx ctx) {
+  if (!ctx) return GW_OK;
+  hipSetDevice(ctx->device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream); else hipDeviceSynchronize();
+  for (int i = 0; i < WS_COUNT; ++i)
+    if (ctx->ws[i]) hipFree(ctx->ws[i]);
+  if (ctx->d_flags) hipFree(ctx->d_flags);
+  if (ctx->stage_host) hipHostFree(ctx->stage_host);
+  if (ctx->rocblas) gw_release_rocblas(ctx->rocblas);
+  for (auto& e : ctx->prof_pending) {
+    hipEventDestroy(e.a);
+    hipEventDestroy(e.b);
+  }
+  delete ctx;
+  return GW_OK;
+}
+
+gw_status gw_set_stream(gw_ctx ctx, void* hip_stream) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_set_stream: ctx is NULL");
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return GW_OK;
+}
+
+gw_status gw_sync(gw_ctx ctx) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_sync: ctx is NULL");
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return gw::check_flags(ctx);
+}
+
+const char* gw_last_error(gw_ctx ctx) {
+  return ctx ? ctx->err.c_str() : g_free_err.c_str();
+}
+
+const char* gw_status_string(gw_status s) {
+  switch (s) {
+    case GW_OK: return "GW_OK";
+    case GW_EINVAL: return "GW_EINVAL";
+    case GW_ENOMEM: return "GW_ENOMEM";
+    case GW_EDEVICE: return "GW_EDEVICE";
+    case GW_ENOTSPD: return "GW_ENOTSPD";
+    case GW_EPADE: return "GW_EPADE";
+    case GW_ENOCONV: return "GW_ENOCONV";
+    case GW_EUNSUPPORTED: return "GW_EUNSUPPORTED";
+  }
+  return "GW_UNKNOWN";
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// Natural auxiliary functions (Eqs. 11-13).
+//
+//  * Metric: K = s (R_oo^T R_oo + 2 R_ov^T R_ov), s = 2, with the virtual-
+//    virtual block omitted (Sec. 2), on the scaled-SYRK kernels with a
+//    constant scale.
+//  * Eigendecomposition of K in FP64 on the device (rocSOLVER syevd), then
+//    the kept eigenvectors (eigenvalue > eps_NAF, at most max_keep) are
+//    copied in descending order into U (row p = p-th eigenvector).
+//  * Transform R~ = R U (Eq. 13): a GEMM with both operands contiguous along
+//    the auxiliary index; FP32 MFMA with FP64 partial sums every 256 terms,
+//    or FP64 MFMA.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int BM = 128;
+constexpr int NT = 256;
+
+inline int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
+// U[p][:] = eigenvector of the p-th largest eigenvalue.  syevd leaves the
+// eigenvectors in the rows of V (column-major output of a symmetric input)
+// in ascending order.
+__global__ void reorder_kernel(const double* __restrict__ V, int n, double* __restrict__ U) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = idx / n, c = idx % n;
+    U[idx] = V[(int64_t)(n - 1 - p) * n + c];
+  }
+}
+
+struct GemmArgs {
+  const void* A;      // [rows][K]
+  const double* B;    // [ncols][K] FP64
+  void* C;            // [rows][ncols]
+  int64_t rows;
+  int K;
+  int ncols;
+  int row_tiles, col_tiles;
+};
+
+constexpr int BK = 32;
+constexpr int LDK = BK + 1;
+
+// C[r][c] = sum_k A[r][k] B[c][k] on FP32 MFMA, FP64 flush every 256 k.
+__global__ __launch_bounds__(NT, 1) void nt_gemm_f32_kernel(GemmArgs g) {
+  __shared__ float As[BM][LDK];
+  __shared__ float Bs[BM][LDK];
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int ct = (int)(lid % g.col_tiles);
+  const int rt = (int)(lid / g.col_tiles);
+  const int64_t row0 = (int64_t)rt * BM;
+  const int col0 = ct * BM;
+  const float* A = static_cast<const float*>(g.A);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+  f32x16 acc[2][2];
+  double acc64[2][2][16];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { acc[i][j][r] = 0.f; acc64[i][j][r] = 0.0; }
+  const int nk = (g.K + BK - 1) / BK;
+  for (int it = 0; it < nk; ++it) {
+    const int k0 = it * BK;
+    // 128 rows x 32 k per operand; thread: rows (tid >> 3) + 32 h, k (tid & 7) * 4
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int r = (tid >> 3) + 32 * h, k = k0 + (tid & 7) * 4;
+      const int64_t ar = row0 + r;
+      const int bc = col0 + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        As[r][(tid & 7) * 4 + e] = (ar < g.rows && k + e < g.K) ? A[ar * g.K + k + e] : 0.f;
+        Bs[r][(tid & 7) * 4 + e] =
+            (bc < g.ncols && k + e < g.K) ? (float)g.B[(int64_t)bc * g.K + k + e] : 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int kr = kk * 2 + (lane >> 5);
+      const float a0 = As[wy * 64 + (lane & 31)][kr];
+      const float a1 = As[wy * 64 + 32 + (lane & 31)][kr];
+      const float b0 = Bs[wx * 64 + (lane & 31)][kr];
+      const float b1 = Bs[wx * 64 + 32 + (lane & 31)][kr];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if ((it + 1) % 8 == 0 || it + 1 == nk) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            acc64[i][j][r] += (double)acc[i][j][r];
+            acc[i][j][r] = 0.f;
+          }
+    }
+    __syncthreads();
+  }
+  float* C = static_cast<float*>(g.C);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = row0 + wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = col0 + wx * 64 + j * 32 + (lane & 31);
+        if (row < g.rows && col < g.ncols) C[row * g.ncols + col] = (float)acc64[i][j][r];
+      }
+}
+
+constexpr int BK64 = 16;
+constexpr int LDK64 = BK64 + 2;
+
+__global__ __launch_bounds__(NT, 1) void nt_gemm_f64_kernel(GemmArgs g) {
+  __shared__ double As[BM][LDK64];
+  __shared__ double Bs[BM][LDK64];
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int ct = (int)(lid % g.col_tiles);
+  const int rt = (int)(lid / g.col_tiles);
+  const int64_t row0 = (int64_t)rt * BM;
+  const int col0 = ct * BM;
+  const double* A = static_cast<const double*>(g.A);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int nk = (g.K + BK64 - 1) / BK64;
+  for (int it = 0; it < nk; ++it) {
+    const int k0 = it * BK64;
+    // 128 rows x 16 k; thread: rows (tid >> 3) + 32 h, k (tid & 7) * 2
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int r = (tid >> 3) + 32 * h, k = k0 + (tid & 7) * 2;
+      const int64_t ar = row0 + r;
+      const int bc = col0 + r;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        As[r][(tid & 7) * 2 + e] = (ar < g.rows && k + e < g.K) ? A[ar * g.K + k + e] : 0.0;
+        Bs[r][(tid & 7) * 2 + e] = (bc < g.ncols && k + e < g.K) ? g.B[(int64_t)bc * g.K + k + e] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK64 / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        af[i] = As[wy * 64 + i * 16 + (lane & 15)][kr];
+        bf[i] = Bs[wx * 64 + i * 16 + (lane & 15)][kr];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* C = static_cast<double*>(g.C);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + wy * 64 + i * 16 + (lane >> 4) + 4 * r;
+        const int col = col0 + wx * 64 + j * 16 + (lane & 15);
+        if (row < g.rows && col < g.ncols) C[row * g.ncols + col] = acc[i][j][r];
+      }
+}
+
+}  // namespace
+
+extern "C" void gw_release_rocblas(void* h) {
+  if (h) rocblas_destroy_handle(static_cast<rocblas_handle>(h));
+}
+
+extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
+                                     int64_t n_oo_rows, const void* R_oo, int64_t n_ov_rows,
+                                     const void* R_ov, double* K, int accumulate, int finalize,
+                                     double eps_naf, int max_keep, int* n_naf, double* U,
+                                     double* eigvals) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_naf_compress: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_naf_compress: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_aux >= 1 && n_oo_rows >= 0 && n_ov_rows >= 0 && max_keep >= 0,
+             "gw_naf_compress: bad sizes");
+  GW_REQUIRE(ctx, K && (n_oo_rows == 0 || R_oo) && (n_ov_rows == 0 || R_ov),
+             "gw_naf_compress: NULL argument");
+  GW_REQUIRE(ctx, !finalize || (n_naf && U), "gw_naf_compress: finalize needs n_naf and U");
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  // FP32- and BF16x3-path tensors are stored in FP32: FP32 MFMA metric.
+  const gw_precision mp = prec == GW_FP64 ? GW_FP64 : GW_FP32;
+  if (n_oo_rows > 0)
+    GW_TRY(gw::syrk_launch(ctx, mp, R_oo, n_oo_rows, n_aux, n_aux, 1, nullptr, 2.0, K, accumulate));
+  if (n_ov_rows > 0)
+    GW_TRY(gw::syrk_launch(ctx, mp, R_ov, n_ov_rows, n_aux, n_aux, 1, nullptr, 4.0, K,
+                           accumulate || n_oo_rows > 0));
+  if (n_oo_rows == 0 && n_ov_rows == 0 && !accumulate)
+    GW_HIP(ctx, hipMemsetAsync(K, 0, (size_t)n_aux * n_aux * sizeof(double), ctx->stream));
+  if (!finalize) return GW_OK;
+
+  GW_TRY(gw::mirror_lower(ctx, K, 1, n_aux));
+  if (!ctx->rocblas) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+      return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocblas_create_handle failed");
+    ctx->rocblas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(ctx->rocblas);
+  rocblas_set_stream(h, ctx->stream);
+  double* ws = static_cast<double*>(gw::ws_get(ctx, WS_EIG, (2 * (size_t)n_aux + 8) * sizeof(double)));
+  if (!ws) return GW_ENOMEM;
+  double* d_eval = ws;
+  double* d_e = ws + n_aux;
+  rocblas_int* d_info = reinterpret_cast<rocblas_int*>(ws + 2 * n_aux);
+  const int pe = gw::prof_begin(ctx);
+  rocblas_status rs = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_lower, n_aux, K,
+                                       n_aux, d_eval, d_e, d_info);
+  if (rs != rocblas_status_success)
+    return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocsolver_dsyevd failed (%d)", (int)rs);
+  gw::prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
+  hipLaunchKernelGGL(reorder_kernel, dim3(grid_for((int64_t)n_aux * n_aux, 256)), dim3(256), 0,
+                     ctx->stream, K, n_aux, U);
+  GW_TRY(gw::launch_check(ctx, "reorder_kernel"));
+  std::vector<double> ev(n_aux);
+  rocblas_int info = 0;
+  GW_HIP(ctx, hipMemcpyAsync(ev.data(), d_eval, n_aux * sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  GW_HIP(ctx, hipMemcpyAsync(&info, d_info, sizeof info, hipMemcpyDeviceToHost, ctx->stream));
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (info != 0)
+    return gw::fail(ctx, GW_ENOCONV, "gw_naf_compress: eigensolver info = %d", (int)info);
+  int keep = 0;
+  for (int i = n_aux - 1; i >= 0; --i) {
+    if (ev[i] > eps_naf) ++keep; else break;
+  }
+  if (max_keep > 0) keep = std::min(keep, max_keep);
+  *n_naf = keep;
+  if (eigvals)
+    for (int i = 0; i < n_aux; ++i) eigvals[i] = ev[n_aux - 1 - i];
+  return GW_OK;
+}
+
+extern "C" gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int n_naf,
+                                  const double* U, int64_t n_rows, const void* R_in,
+                                  void* R_out) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_naf_apply: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_naf_apply: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_aux >= 1 && n_naf >= 1 && n_naf <= n_aux && n_rows >= 0,
+             "gw_naf_apply: bad sizes (n_aux=%d n_naf=%d)", n_aux, n_naf);
+  GW_REQUIRE(ctx, U && (n_rows == 0 || (R_in && R_out)), "gw_naf_apply: NULL argument");
+  if (n_rows == 0) return GW_OK;
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  const int rt = (int)((n_rows + BM - 1) / BM), ct = (n_naf + BM - 1) / BM;
+  GemmArgs g{R_in, U, R_out, n_rows, n_aux, n_naf, rt, ct};
+  const int64_t grid = (int64_t)rt * ct;
+  const int pi = gw::prof_begin(ctx);
+  if (prec == GW_FP64)
+    hipLaunchKernelGGL(nt_gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, g);
+  else
+    hipLaunchKernelGGL(nt_gemm_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, g);
+  gw::prof_end(ctx, pi, prec == GW_FP64 ? "naf_gemm_f64" : "naf_gemm_f32",
+               2.0 * (double)n_rows * n_aux * (double)n_naf, 0.0);
+  return gw::launch_check(ctx, "naf transform");
+}

@@ -1,0 +1,392 @@
+// Diagonal self-energy: W_nm(i w_j) = R_nm^T W^_j R_nm (Eq. 2) on MFMA, then
+// the imaginary-axis quadrature of Eq. 7 in FP64.
+//
+// The contraction is a GEMM Y = R_qp W^_j (rows: the Q*M pairs (n, m);
+// columns: the auxiliary index) whose epilogue takes the row-wise dot
+// product of each output tile with the matching columns of R_qp, so Y never
+// reaches memory.  Each 64-column slice of a tile writes one FP64 partial
+// per row; a second kernel sums the partials in a fixed order.
+//
+//  FP32:   v_mfma_f32_32x32x2f32, operands FP32, tile 128 x 128 x 32.
+//  FP64:   v_mfma_f64_16x16x4f64, operands FP64, tile 128 x 128 x 16.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int BM = 128;
+constexpr int NT = 256;
+
+inline int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
+struct BwbArgs {
+  const void* R;      // [rows][N]
+  const void* W;      // [F][N][N]
+  int64_t rows;
+  int N;
+  int F;
+  int row_tiles;
+  int col_tiles;
+  double* part;       // [F][2 * col_tiles][rows]
+};
+
+__device__ __forceinline__ void decode(const BwbArgs& a, int& j, int& ct, int& rt) {
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  rt = (int)(lid % a.row_tiles);
+  ct = (int)((lid / a.row_tiles) % a.col_tiles);
+  j = (int)(lid / ((int64_t)a.row_tiles * a.col_tiles));
+}
+
+// ------------------------------------------------------------------ FP32
+constexpr int BK32 = 32;
+constexpr int LDA32 = BK32 + 1;
+
+__global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a) {
+  __shared__ float As[2][BM][LDA32];
+  __shared__ float Bs[2][BK32][BM];
+  int j, ct, rt;
+  decode(a, j, ct, rt);
+  const float* R = static_cast<const float*>(a.R);
+  const float* W = static_cast<const float*>(a.W) + (int64_t)j * a.N * a.N;
+  const int64_t row0 = (int64_t)rt * BM;
+  const int col0 = ct * BM;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][jj][r] = 0.f;
+
+  // A loader: rows (tid >> 3) + 32 h, k offset (tid & 7) * 4
+  // B loader: rows (tid >> 5) + 8 h, col offset (tid & 31) * 4
+  float4 ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int64_t row = row0 + (tid >> 3) + 32 * h;
+      const int k = k0 + (tid & 7) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < a.rows) {
+        const int64_t off = row * a.N + k;
+        const float* p = R + off;
+        if (k + 3 < a.N && (off & 3) == 0) v = *reinterpret_cast<const float4*>(p);
+        else {
+          if (k + 0 < a.N) v.x = p[0];
+          if (k + 1 < a.N) v.y = p[1];
+          if (k + 2 < a.N) v.z = p[2];
+          if (k + 3 < a.N) v.w = p[3];
+        }
+      }
+      ra[h] = v;
+      const int kr = k0 + (tid >> 5) + 8 * h;
+      const int c = col0 + (tid & 31) * 4;
+      float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (kr < a.N) {
+        const int64_t off = (int64_t)kr * a.N + c;
+        const float* p = W + off;
+        if (c + 3 < a.N && (off & 3) == 0) u = *reinterpret_cast<const float4*>(p);
+        else {
+          if (c + 0 < a.N) u.x = p[0];
+          if (c + 1 < a.N) u.y = p[1];
+          if (c + 2 < a.N) u.z = p[2];
+          if (c + 3 < a.N) u.w = p[3];
+        }
+      }
+      rb[h] = u;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int r = (tid >> 3) + 32 * h, k = (tid & 7) * 4;
+      As[buf][r][k + 0] = ra[h].x;
+      As[buf][r][k + 1] = ra[h].y;
+      As[buf][r][k + 2] = ra[h].z;
+      As[buf][r][k + 3] = ra[h].w;
+      *reinterpret_cast<float4*>(&Bs[buf][(tid >> 5) + 8 * h][(tid & 31) * 4]) = rb[h];
+    }
+  };
+
+  const int nk = (a.N + BK32 - 1) / BK32;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload((it + 1) * BK32);
+#pragma unroll
+    for (int kk = 0; kk < BK32 / 2; ++kk) {
+      const int kr = kk * 2 + (lane >> 5);
+      const float a0 = As[cur][wy * 64 + (lane & 31)][kr];
+      const float a1 = As[cur][wy * 64 + 32 + (lane & 31)][kr];
+      const float b0 = Bs[cur][kr][wx * 64 + (lane & 31)];
+      const float b1 = Bs[cur][kr][wx * 64 + 32 + (lane & 31)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: per-row dot product with R[row][col] over this wave's 64 columns
+  double* part = a.part + ((int64_t)j * 2 * a.col_tiles + 2 * ct + wx) * a.rows;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int lrow = wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int64_t row = row0 + lrow;
+      double s = 0.0;
+      if (row < a.rows) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int col = col0 + wx * 64 + jj * 32 + (lane & 31);
+          if (col < a.N) s += (double)acc[i][jj][r] * (double)R[row * a.N + col];
+        }
+      }
+#pragma unroll
+      for (int off = 16; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+      if ((lane & 31) == 0 && row < a.rows) part[row] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ FP64
+constexpr int BK64 = 16;
+constexpr int LDA64 = BK64 + 2;
+
+__global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a) {
+  __shared__ double As[2][BM][LDA64];
+  __shared__ double Bs[2][BK64][BM];
+  int j, ct, rt;
+  decode(a, j, ct, rt);
+  const double* R = static_cast<const double*>(a.R);
+  const double* W = static_cast<const double*>(a.W) + (int64_t)j * a.N * a.N;
+  const int64_t row0 = (int64_t)rt * BM;
+  const int col0 = ct * BM;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // A loader: 128 rows x 16 doubles = 1024 double2 -> 4 per thread:
+  //   rows (tid >> 3) + 32 h, k offset (tid & 7) * 2
+  // B loader: 16 rows x 128 doubles = 1024 double2 -> 4 per thread:
+  //   rows (tid >> 6) + 4 h, col offset (tid & 63) * 2
+  double2 ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int64_t row = row0 + (tid >> 3) + 32 * h;
+      const int k = k0 + (tid & 7) * 2;
+      double2 v = make_double2(0.0, 0.0);
+      if (row < a.rows) {
+        const int64_t off = row * a.N + k;
+        const double* p = R + off;
+        if (k + 1 < a.N && (off & 1) == 0) v = *reinterpret_cast<const double2*>(p);
+        else {
+          if (k < a.N) v.x = p[0];
+          if (k + 1 < a.N) v.y = p[1];
+        }
+      }
+      ra[h] = v;
+      const int kr = k0 + (tid >> 6) + 4 * h;
+      const int c = col0 + (tid & 63) * 2;
+      double2 u = make_double2(0.0, 0.0);
+      if (kr < a.N) {
+        const int64_t off = (int64_t)kr * a.N + c;
+        const double* p = W + off;
+        if (c + 1 < a.N && (off & 1) == 0) u = *reinterpret_cast<const double2*>(p);
+        else {
+          if (c < a.N) u.x = p[0];
+          if (c + 1 < a.N) u.y = p[1];
+        }
+      }
+      rb[h] = u;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      *reinterpret_cast<double2*>(&As[buf][(tid >> 3) + 32 * h][(tid & 7) * 2]) = ra[h];
+      *reinterpret_cast<double2*>(&Bs[buf][(tid >> 6) + 4 * h][(tid & 63) * 2]) = rb[h];
+    }
+  };
+
+  const int nk = (a.N + BK64 - 1) / BK64;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload((it + 1) * BK64);
+#pragma unroll
+    for (int kk = 0; kk < BK64 / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        af[i] = As[cur][wy * 64 + i * 16 + (lane & 15)][kr];
+        bf[i] = Bs[cur][kr][wx * 64 + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[jj], acc[i][jj], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  double* part = a.part + ((int64_t)j * 2 * a.col_tiles + 2 * ct + wx) * a.rows;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lrow = wy * 64 + i * 16 + (lane >> 4) + 4 * r;
+      const int64_t row = row0 + lrow;
+      double s = 0.0;
+      if (row < a.rows) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int col = col0 + wx * 64 + jj * 16 + (lane & 15);
+          if (col < a.N) s += acc[i][jj][r] * R[row * a.N + col];
+        }
+      }
+#pragma unroll
+      for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+      if ((lane & 15) == 0 && row < a.rows) part[row] = s;
+    }
+  }
+}
+
+// W[j][row] = sum over column partials (fixed order); optional user copy.
+__global__ void w_reduce_kernel(const double* __restrict__ part, int n_part, int64_t rows,
+                                int F, double* __restrict__ W, double* __restrict__ W_user) {
+  const int64_t total = (int64_t)F * rows;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = idx / rows, r = idx % rows;
+    double v = 0.0;
+    for (int p = 0; p < n_part; ++p) v += part[(j * n_part + p) * rows + r];
+    W[idx] = v;
+    if (W_user) W_user[idx] = v;
+  }
+}
+
+// One workgroup per (QP state q, Pade node k):
+//   Sigma = -(1/pi) sum_j w_j sum_m a / (a^2 + w_j^2) W[j][q][m],
+//   a = i wp_k + e_F - e_m.
+__global__ __launch_bounds__(256) void sigma_quad_kernel(
+    const double* __restrict__ W, int F, int Q, int M, const double* __restrict__ eps_m,
+    double eps_f, const double* __restrict__ omega, const double* __restrict__ w_omega,
+    const double* __restrict__ omega_p, int Pd, int accumulate, double* __restrict__ sigma) {
+  __shared__ double sre[256], sim[256];
+  const int q = blockIdx.x / Pd, k = blockIdx.x % Pd;
+  const double wk = omega_p[k];
+  double re = 0.0, im = 0.0;
+  for (int idx = threadIdx.x; idx < F * M; idx += blockDim.x) {
+    const int j = idx / M, m = idx % M;
+    const double ar = eps_f - eps_m[m], ai = wk;          // a = ar + i ai
+    const double wj = omega[j];
+    // a^2 + w_j^2 = (ar^2 - ai^2 + wj^2) + i (2 ar ai)
+    const double dr = ar * ar - ai * ai + wj * wj, di = 2.0 * ar * ai;
+    const double den = dr * dr + di * di;
+    const double gr = (ar * dr + ai * di) / den, gi = (ai * dr - ar * di) / den;
+    const double f = w_omega[j] * W[((int64_t)j * Q + q) * M + m];
+    re += f * gr;
+    im += f * gi;
+  }
+  sre[threadIdx.x] = re;
+  sim[threadIdx.x] = im;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sre[threadIdx.x] += sre[threadIdx.x + s];
+      sim[threadIdx.x] += sim[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double c = -1.0 / 3.14159265358979323846;
+    double* out = sigma + 2 * ((int64_t)q * Pd + k);
+    if (accumulate) {
+      out[0] += c * sre[0];
+      out[1] += c * sim[0];
+    } else {
+      out[0] = c * sre[0];
+      out[1] = c * sim[0];
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
+                                   int n_mo, const double* eps_mo, double eps_F,
+                                   const void* R_qp, int n_w, const double* omega,
+                                   const double* w_omega, const void* W_hat, int n_pade,
+                                   const double* omega_pade, int accumulate,
+                                   double* sigma_iw, double* W_nm) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_sigma_diag: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_sigma_diag: unknown precision %d", (int)prec);
+  if (prec == GW_BF16X3)
+    return gw::fail(ctx, GW_EUNSUPPORTED, "gw_sigma_diag: BF16x3 not available");
+  GW_REQUIRE(ctx, n_naf >= 1 && n_qp >= 1 && n_mo >= 1 && n_w >= 1 && n_pade >= 1,
+             "gw_sigma_diag: bad sizes");
+  GW_REQUIRE(ctx, eps_mo && R_qp && omega && w_omega && W_hat && omega_pade && sigma_iw,
+             "gw_sigma_diag: NULL argument");
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  const int N = n_naf, F = n_w;
+  const int64_t rows = (int64_t)n_qp * n_mo;
+  const double* d_eps = gw::stage_t(ctx, eps_mo, n_mo);
+  const double* d_om = gw::stage_t(ctx, omega, n_w);
+  const double* d_wt = gw::stage_t(ctx, w_omega, n_w);
+  const double* d_op = gw::stage_t(ctx, omega_pade, n_pade);
+  if (!d_eps || !d_om || !d_wt || !d_op) return GW_EINVAL;
+  const int row_tiles = (int)((rows + BM - 1) / BM);
+  const int col_tiles = (N + BM - 1) / BM;
+  const int n_part = 2 * col_tiles;
+  double* part = static_cast<double*>(
+      gw::ws_get(ctx, WS_SIGMA_PART, (size_t)F * n_part * rows * sizeof(double)));
+  double* W = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_W, (size_t)F * rows * sizeof(double)));
+  if (!part || !W) return GW_ENOMEM;
+  BwbArgs a{R_qp, W_hat, rows, N, F, row_tiles, col_tiles, part};
+  const int64_t grid = (int64_t)F * row_tiles * col_tiles;
+  const int pi = gw::prof_begin(ctx);
+  if (prec == GW_FP64)
+    hipLaunchKernelGGL(bwb_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL(bwb_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
+  {
+    const double esz = prec == GW_FP64 ? 8.0 : 4.0;
+    gw::prof_end(ctx, pi, prec == GW_FP64 ? "bwb_f64" : "bwb_f32",
+                 2.0 * F * (double)rows * N * (double)N,
+                 (double)rows * N * esz + (double)F * N * (double)N * esz);
+  }
+  GW_TRY(gw::launch_check(ctx, "bwb kernel"));
+  hipLaunchKernelGGL(w_reduce_kernel, dim3(grid_for((int64_t)F * rows, 256)), dim3(256), 0,
+                     ctx->stream, part, n_part, rows, F, W, W_nm);
+  GW_TRY(gw::launch_check(ctx, "w_reduce_kernel"));
+  hipLaunchKernelGGL(sigma_quad_kernel, dim3(n_qp * n_pade), dim3(256), 0, ctx->stream, W, F,
+                     n_qp, n_mo, d_eps, eps_F, d_om, d_wt, d_op, n_pade, accumulate, sigma_iw);
+  return gw::launch_check(ctx, "sigma_quad_kernel");
+}

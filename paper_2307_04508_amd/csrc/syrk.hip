@@ -1,0 +1,447 @@
+// Scaled SYRK on MFMA: the Laplace-transformed polarizability matrices
+//   M^m_PQ = sum_r X_rP s_m(r) X_rQ,  s_m(ia) = w_m D_ia exp(-D_ia^2 x_m)
+// (Eq. 10) and, with a constant scale, the NAF metric of Eq. 11.
+//
+// X is [k_rows][N] row-major (rows = occupied-virtual pairs, aux contiguous).
+// Each workgroup computes one 128 x 128 lower-triangle tile of one matrix m
+// over one slice of rows (split-K); the per-row scale is multiplied into the
+// A operand while the tile is staged into LDS.  Partial tiles are written in
+// FP64 and summed in a fixed order by a second kernel, so results are
+// bitwise reproducible.
+//
+//  FP32 / BF16x3: v_mfma_f32_32x32x2f32 / v_mfma_f32_32x32x16_bf16, FP32
+//                 accumulators added into FP64 registers every 256 rows.
+//  FP64:          v_mfma_f64_16x16x4f64.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int BM = 128;             // tile edge (P and Q)
+constexpr int NT = 256;             // threads per workgroup (4 waves, 2 x 2)
+constexpr int FLUSH_ROWS = 256;     // FP32 -> FP64 flush interval (rows)
+
+struct SyrkArgs {
+  const void* X;
+  int64_t k_rows;
+  int N;
+  int64_t ld;           // row stride of X in elements (>= N)
+  int L;
+  const void* scale;    // [L][k_rows] (element type) or nullptr
+  double cscale;
+  int tiles_side;
+  int n_tiles;
+  int splits;
+  int64_t rows_per_split;
+  double* part;         // [splits][L][n_tiles][BM*BM]
+};
+
+__device__ __forceinline__ void tile_coords(int t, int& ti, int& tj) {
+  int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  ti = i;
+  tj = t - i * (i + 1) / 2;
+}
+
+// ------------------------------------------------------------------ FP32 MFMA
+constexpr int BK32 = 16;
+
+__global__ __launch_bounds__(NT, 1) void syrk_f32_kernel(SyrkArgs a) {
+  __shared__ float As[2][BK32][BM];
+  __shared__ float Bs[2][BK32][BM];
+
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int m = (int)(lid % a.L);
+  const int t = (int)((lid / a.L) % a.n_tiles);
+  const int s = (int)(lid / ((int64_t)a.L * a.n_tiles));
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int p0 = ti * BM, q0 = tj * BM;
+  const int64_t r0 = (int64_t)s * a.rows_per_split;
+  const int64_t r1 = min(r0 + a.rows_per_split, a.k_rows);
+
+  const float* X = static_cast<const float*>(a.X);
+  const float* scale = a.scale ? static_cast<const float*>(a.scale) + (int64_t)m * a.k_rows : nullptr;
+  const float csc = (float)a.cscale;
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int lrow = tid >> 5, lcol = (tid & 31) * 4;   // loader: rows lrow, lrow+8
+
+  f32x16 acc[2][2];
+  double acc64[2][2][16];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { acc[i][j][r] = 0.f; acc64[i][j][r] = 0.0; }
+    }
+
+  float4 ra[2], rb[2];
+  auto gload = [&](int64_t kb) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r = kb + lrow + 8 * h;
+      float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+      if (r < r1) {
+        const float sc = scale ? scale[r] : csc;
+        const int64_t rb = r * a.ld;
+        const float* row = X + rb;
+        const int pa = p0 + lcol, pb = q0 + lcol;
+        if (pa + 3 < a.N && ((rb + pa) & 3) == 0) {
+          va = *reinterpret_cast<const float4*>(row + pa);
+        } else {
+          if (pa + 0 < a.N) va.x = row[pa + 0];
+          if (pa + 1 < a.N) va.y = row[pa + 1];
+          if (pa + 2 < a.N) va.z = row[pa + 2];
+          if (pa + 3 < a.N) va.w = row[pa + 3];
+        }
+        if (pb + 3 < a.N && ((rb + pb) & 3) == 0) {
+          vb = *reinterpret_cast<const float4*>(row + pb);
+        } else {
+          if (pb + 0 < a.N) vb.x = row[pb + 0];
+          if (pb + 1 < a.N) vb.y = row[pb + 1];
+          if (pb + 2 < a.N) vb.z = row[pb + 2];
+          if (pb + 3 < a.N) vb.w = row[pb + 3];
+        }
+        va.x *= sc; va.y *= sc; va.z *= sc; va.w *= sc;
+      }
+      ra[h] = va;
+      rb[h] = vb;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      *reinterpret_cast<float4*>(&As[buf][lrow + 8 * h][lcol]) = ra[h];
+      *reinterpret_cast<float4*>(&Bs[buf][lrow + 8 * h][lcol]) = rb[h];
+    }
+  };
+
+  const int nk = (int)((r1 - r0 + BK32 - 1) / BK32);
+  constexpr int FLUSH_STAGES = FLUSH_ROWS / BK32;
+  if (nk > 0) {
+    gload(r0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload(r0 + (int64_t)(it + 1) * BK32);
+#pragma unroll
+    for (int kk = 0; kk < BK32 / 2; ++kk) {
+      const int kr = kk * 2 + (lane >> 5);
+      const float a0 = As[cur][kr][wy * 64 + (lane & 31)];
+      const float a1 = As[cur][kr][wy * 64 + 32 + (lane & 31)];
+      const float b0 = Bs[cur][kr][wx * 64 + (lane & 31)];
+      const float b1 = Bs[cur][kr][wx * 64 + 32 + (lane & 31)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    if ((it + 1) % FLUSH_STAGES == 0 || it + 1 == nk) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            acc64[i][j][r] += (double)acc[i][j][r];
+            acc[i][j][r] = 0.f;
+          }
+    }
+    __syncthreads();
+  }
+
+  double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = wx * 64 + j * 32 + (lane & 31);
+        out[row * BM + col] = acc64[i][j][r];
+      }
+}
+
+// ------------------------------------------------------------------ FP64 MFMA
+constexpr int BK64 = 16;
+
+__global__ __launch_bounds__(NT, 1) void syrk_f64_kernel(SyrkArgs a) {
+  __shared__ double As[2][BK64][BM];
+  __shared__ double Bs[2][BK64][BM];
+
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int m = (int)(lid % a.L);
+  const int t = (int)((lid / a.L) % a.n_tiles);
+  const int s = (int)(lid / ((int64_t)a.L * a.n_tiles));
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int p0 = ti * BM, q0 = tj * BM;
+  const int64_t r0 = (int64_t)s * a.rows_per_split;
+  const int64_t r1 = min(r0 + a.rows_per_split, a.k_rows);
+
+  const double* X = static_cast<const double*>(a.X);
+  const double* scale = a.scale ? static_cast<const double*>(a.scale) + (int64_t)m * a.k_rows : nullptr;
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+  // loader: 16 rows x 128 doubles per operand = 1024 double2; 4 per thread
+  const int lrow = tid >> 6, lcol = (tid & 63) * 2;   // rows lrow + 4h
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  double2 ra[4], rb[4];
+  auto gload = [&](int64_t kb) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int64_t r = kb + lrow + 4 * h;
+      double2 va = make_double2(0.0, 0.0), vb = va;
+      if (r < r1) {
+        const double sc = scale ? scale[r] : a.cscale;
+        const int64_t rb = r * a.ld;
+        const double* row = X + rb;
+        const int pa = p0 + lcol, pb = q0 + lcol;
+        if (pa + 1 < a.N && ((rb + pa) & 1) == 0) {
+          va = *reinterpret_cast<const double2*>(row + pa);
+        } else {
+          if (pa < a.N) va.x = row[pa];
+          if (pa + 1 < a.N) va.y = row[pa + 1];
+        }
+        if (pb + 1 < a.N && ((rb + pb) & 1) == 0) {
+          vb = *reinterpret_cast<const double2*>(row + pb);
+        } else {
+          if (pb < a.N) vb.x = row[pb];
+          if (pb + 1 < a.N) vb.y = row[pb + 1];
+        }
+        va.x *= sc; va.y *= sc;
+      }
+      ra[h] = va;
+      rb[h] = vb;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      *reinterpret_cast<double2*>(&As[buf][lrow + 4 * h][lcol]) = ra[h];
+      *reinterpret_cast<double2*>(&Bs[buf][lrow + 4 * h][lcol]) = rb[h];
+    }
+  };
+
+  const int nk = (int)((r1 - r0 + BK64 - 1) / BK64);
+  if (nk > 0) {
+    gload(r0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload(r0 + (int64_t)(it + 1) * BK64);
+#pragma unroll
+    for (int kk = 0; kk < BK64 / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        af[i] = As[cur][kr][wy * 64 + i * 16 + (lane & 15)];
+        bf[i] = Bs[cur][kr][wx * 64 + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wy * 64 + i * 16 + (lane >> 4) + 4 * r;
+        const int col = wx * 64 + j * 16 + (lane & 15);
+        out[row * BM + col] = acc[i][j][r];
+      }
+}
+
+// Sum the split-K partials in a fixed order into the lower triangle of out.
+__global__ void syrk_reduce_kernel(const double* __restrict__ part, int splits,
+                                   int L, int n_tiles, int N, double* __restrict__ out,
+                                   int accumulate) {
+  const int64_t per_tile = BM * BM;
+  const int64_t total = (int64_t)L * n_tiles * per_tile;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(idx % per_tile);
+    const int t = (int)((idx / per_tile) % n_tiles);
+    const int m = (int)(idx / (per_tile * n_tiles));
+    int ti, tj;
+    tile_coords(t, ti, tj);
+    const int p = ti * BM + e / BM, q = tj * BM + e % BM;
+    if (p >= N || q >= N || q > p) continue;
+    double v = 0.0;
+    for (int s = 0; s < splits; ++s)
+      v += part[(((int64_t)s * L + m) * n_tiles + t) * per_tile + e];
+    double* dst = out + ((int64_t)m * N + p) * N + q;
+    *dst = accumulate ? *dst + v : v;
+  }
+}
+
+__global__ void mirror_kernel(double* M, int L, int N) {
+  const int64_t total = (int64_t)L * N * N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(idx % N);
+    const int p = (int)((idx / N) % N);
+    const int64_t m = idx / ((int64_t)N * N);
+    if (q > p) M[(m * N + p) * N + q] = M[(m * N + q) * N + p];
+  }
+}
+
+template <typename T>
+__global__ void lt_scale_kernel(int L, const double* __restrict__ x,
+                                const double* __restrict__ w, int n_i, int n_virt,
+                                const double* __restrict__ eps_i,
+                                const double* __restrict__ eps_a, T* __restrict__ out) {
+  const int64_t k = (int64_t)n_i * n_virt;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < k * L;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx % k;
+    const int m = (int)(idx / k);
+    const int i = (int)(r / n_virt), aa = (int)(r % n_virt);
+    const double d = eps_a[aa] - eps_i[i];
+    out[idx] = (T)(w[m] * d * exp(-d * d * x[m]));
+  }
+}
+
+inline int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
+}  // namespace
+
+namespace gw {
+
+gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L, const double* d_x,
+                          const double* d_w, int n_i, int n_virt,
+                          const double* d_eps_i, const double* d_eps_a, void* scale) {
+  const int64_t n = (int64_t)L * n_i * n_virt;
+  if (prec == GW_FP64)
+    hipLaunchKernelGGL(lt_scale_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0,
+                       ctx->stream, L, d_x, d_w, n_i, n_virt, d_eps_i, d_eps_a,
+                       static_cast<double*>(scale));
+  else
+    hipLaunchKernelGGL(lt_scale_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0,
+                       ctx->stream, L, d_x, d_w, n_i, n_virt, d_eps_i, d_eps_a,
+                       static_cast<float*>(scale));
+  return launch_check(ctx, "lt_scale_kernel");
+}
+
+// Choose the split-K factor so the grid fills the 256 CUs evenly.
+static int choose_splits(int64_t k_rows, int64_t units) {
+  int best = 1;
+  double best_eff = 0;
+  for (int s = 1; s <= 16; ++s) {
+    if (s > 1 && k_rows / s < 1024) break;
+    const int64_t wg = units * s;
+    const double eff = (double)wg / (256.0 * (double)((wg + 255) / 256));
+    if (eff > best_eff + 0.02) { best_eff = eff; best = s; }
+  }
+  return best;
+}
+
+gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_rows,
+                      int N, int64_t ld, int L, const void* scale, double cscale,
+                      double* out, int accumulate) {
+  if (prec == GW_BF16X3) return fail(ctx, GW_EUNSUPPORTED, "BF16x3 SYRK not available");
+  const int T = (N + BM - 1) / BM;
+  const int n_tiles = T * (T + 1) / 2;
+  const int S = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
+  const int64_t align = prec == GW_FP64 ? BK64 : FLUSH_ROWS;
+  int64_t rps = (k_rows + S - 1) / S;
+  rps = (rps + align - 1) / align * align;
+  const size_t part_bytes = (size_t)S * L * n_tiles * BM * BM * sizeof(double);
+  double* part = static_cast<double*>(ws_get(ctx, WS_SYRK_PART, part_bytes));
+  if (!part) return GW_ENOMEM;
+  SyrkArgs a{X, k_rows, N, ld, L, scale, cscale, T, n_tiles, S, rps, part};
+  const int64_t grid = (int64_t)S * L * n_tiles;
+  const int pi = prof_begin(ctx);
+  if (prec == GW_FP64)
+    hipLaunchKernelGGL(syrk_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL(syrk_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
+  // algorithmic work: L lower-triangle products of 2 k flops each; X read
+  // once, the triangle written once
+  const double esz = prec == GW_FP64 ? 8.0 : 4.0;
+  prof_end(ctx, pi, prec == GW_FP64 ? "syrk_f64" : "syrk_f32",
+           (double)L * N * (N + 1.0) * (double)k_rows,
+           (double)k_rows * N * esz + (double)L * N * (N + 1.0) / 2.0 * 8.0);
+  GW_TRY(launch_check(ctx, "syrk kernel"));
+  const int64_t tot = (int64_t)L * n_tiles * BM * BM;
+  hipLaunchKernelGGL(syrk_reduce_kernel, dim3(grid_for(tot, 256)), dim3(256), 0,
+                     ctx->stream, part, S, L, n_tiles, N, out, accumulate);
+  return launch_check(ctx, "syrk_reduce_kernel");
+}
+
+gw_status mirror_lower(gw_ctx ctx, double* M, int L, int N) {
+  const int64_t tot = (int64_t)L * N * N;
+  hipLaunchKernelGGL(mirror_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, ctx->stream,
+                     M, L, N);
+  return launch_check(ctx, "mirror_kernel");
+}
+
+}  // namespace gw
+
+extern "C" gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_naf,
+                                          int n_lt, const double* x_lt,
+                                          const double* w_lt, int n_i, int n_virt,
+                                          const double* eps_i, const double* eps_a,
+                                          const void* R_chunk, int accumulate,
+                                          int finalize, double* M) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_polarizability_lt: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_polarizability_lt: unknown precision %d", (int)prec);
+  if (prec == GW_BF16X3)
+    return gw::fail(ctx, GW_EUNSUPPORTED, "gw_polarizability_lt: BF16x3 not available");
+  GW_REQUIRE(ctx, n_naf >= 1 && n_lt >= 1 && n_lt <= 32 && n_i >= 0 && n_virt >= 1,
+             "gw_polarizability_lt: bad sizes (n_naf=%d n_lt=%d n_i=%d n_virt=%d)",
+             n_naf, n_lt, n_i, n_virt);
+  GW_REQUIRE(ctx, x_lt && w_lt && M && eps_a && (n_i == 0 || (eps_i && R_chunk)),
+             "gw_polarizability_lt: NULL argument");
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  const int64_t k = (int64_t)n_i * n_virt;
+  const double* dx = gw::stage_t(ctx, x_lt, n_lt);
+  const double* dw = gw::stage_t(ctx, w_lt, n_lt);
+  const double* dei = n_i ? gw::stage_t(ctx, eps_i, n_i) : nullptr;
+  const double* dea = gw::stage_t(ctx, eps_a, n_virt);
+  if (!dx || !dw || !dea || (n_i && !dei)) return GW_EINVAL;
+  void* scale = nullptr;
+  if (k > 0) {
+    const size_t esz = prec == GW_FP64 ? 8 : 4;
+    scale = gw::ws_get(ctx, WS_SYRK_SCALE, (size_t)n_lt * k * esz);
+    if (!scale) return GW_ENOMEM;
+    GW_TRY(gw::lt_scale_launch(ctx, prec, n_lt, dx, dw, n_i, n_virt, dei, dea, scale));
+  }
+  GW_TRY(gw::syrk_launch(ctx, prec, R_chunk, k, n_naf, n_naf, n_lt, scale, 1.0, M, accumulate));
+  if (finalize) GW_TRY(gw::mirror_lower(ctx, M, n_lt, n_naf));
+  return GW_OK;
+}

@@ -1,0 +1,276 @@
+"""ctypes binding of the gwlt C ABI (include/gwlt.h): argument marshalling
+only.  Device arrays are torch tensors on the context's device (their data
+pointers are passed through); host arrays are numpy arrays.  Every function
+has the name of its C entry point and raises ``GwError`` on a non-OK status.
+There is no fallback: if libgwlt.so is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgwlt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} not found: build it with "
+                      "`python paper_2307_04508_amd/build.py`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_ENOTSPD, GW_EPADE, GW_ENOCONV, \
+    GW_EUNSUPPORTED = range(8)
+GW_FP64, GW_FP32, GW_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "bf16x3": GW_BF16X3}
+
+EXPORTS = ["gw_create", "gw_destroy", "gw_set_stream", "gw_sync", "gw_last_error",
+           "gw_status_string", "gw_prepare", "gw_freq_grid_mgl", "gw_lt_grid_minimax",
+           "gw_minimax_inverse", "gw_profile_enable", "gw_profile_get",
+           "gw_naf_compress", "gw_naf_apply", "gw_polarizability_lt", "gw_screen",
+           "gw_sigma_diag", "gw_qp_solve", "gw_g0w0"]
+
+c_int, c_i64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+P_DBL = ctypes.POINTER(ctypes.c_double)
+P_INT = ctypes.POINTER(ctypes.c_int)
+
+
+class GwParams(ctypes.Structure):
+    _fields_ = [("n_occ", c_int), ("n_fc", c_int), ("n_virt", c_int), ("n_aux", c_int),
+                ("n_lt", c_int), ("n_freq", c_int), ("n_pade", c_int), ("n_qp", c_int),
+                ("eps_naf", c_dbl), ("max_keep", c_int), ("x0", c_dbl), ("eta", c_dbl),
+                ("tol", c_dbl), ("max_iter", c_int), ("freq_batch", c_int)]
+
+
+class GwStats(ctypes.Structure):
+    _fields_ = [("n_naf", c_int), ("lt_err_norm", c_dbl), ("t_naf_ms", c_dbl),
+                ("t_chi_ms", c_dbl), ("t_screen_ms", c_dbl), ("t_sigma_ms", c_dbl),
+                ("t_qp_ms", c_dbl), ("t_total_ms", c_dbl)]
+
+
+_sig = {
+    "gw_create": [ctypes.POINTER(c_vp), c_int, c_vp],
+    "gw_destroy": [c_vp],
+    "gw_set_stream": [c_vp, c_vp],
+    "gw_sync": [c_vp],
+    "gw_profile_enable": [c_vp, c_int],
+    "gw_profile_get": [c_vp, ctypes.c_char_p, P_DBL, ctypes.POINTER(c_i64), P_DBL, P_DBL],
+    "gw_prepare": [c_int, c_int, c_int, P_DBL, c_dbl, P_DBL, P_DBL, P_DBL],
+    "gw_freq_grid_mgl": [c_int, c_dbl, P_DBL, P_DBL],
+    "gw_lt_grid_minimax": [c_int, c_dbl, c_dbl, P_DBL, P_DBL, P_DBL],
+    "gw_minimax_inverse": [c_int, c_dbl, P_DBL, P_DBL, P_DBL, P_DBL, P_DBL],
+    "gw_naf_compress": [c_vp, c_int, c_int, c_i64, c_vp, c_i64, c_vp, c_vp, c_int, c_int,
+                        c_dbl, c_int, P_INT, c_vp, P_DBL],
+    "gw_naf_apply": [c_vp, c_int, c_int, c_int, c_vp, c_i64, c_vp, c_vp],
+    "gw_polarizability_lt": [c_vp, c_int, c_int, c_int, P_DBL, P_DBL, c_int, c_int, P_DBL,
+                             P_DBL, c_vp, c_int, c_int, c_vp],
+    "gw_screen": [c_vp, c_int, c_int, c_int, P_DBL, c_vp, c_int, P_DBL, c_vp],
+    "gw_sigma_diag": [c_vp, c_int, c_int, c_int, c_int, P_DBL, c_dbl, c_vp, c_int, P_DBL,
+                      P_DBL, c_vp, c_int, P_DBL, c_int, c_vp, c_vp],
+    "gw_qp_solve": [c_vp, c_int, P_DBL, P_DBL, c_dbl, c_int, P_DBL, c_vp, c_dbl, c_dbl, c_int,
+                    P_DBL, P_DBL, P_INT],
+    "gw_g0w0": [c_vp, c_int, ctypes.POINTER(GwParams), P_DBL, P_INT, P_DBL, c_vp, c_vp, c_vp,
+                P_DBL, P_DBL, P_INT, P_DBL, ctypes.POINTER(GwStats)],
+}
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = c_int
+_lib.gw_last_error.argtypes = [c_vp]
+_lib.gw_last_error.restype = ctypes.c_char_p
+_lib.gw_status_string.argtypes = [c_int]
+_lib.gw_status_string.restype = ctypes.c_char_p
+
+
+class GwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.gw_status_string(status).decode()}: {msg}")
+        self.status = status
+
+
+def _check(st: int, ctx=None):
+    if st != GW_OK:
+        msg = _lib.gw_last_error(ctx.handle if ctx is not None else None)
+        raise GwError(st, msg.decode() if msg else "")
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _host(a, dtype=np.float64):
+    """Contiguous host array (kept alive by the caller's reference)."""
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _dp(a):
+    return a.ctypes.data_as(P_DBL) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(P_INT) if a is not None else None
+
+
+def _dev(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device arguments must be contiguous GPU tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A gwlt context bound to a device and a HIP stream (torch stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        h = c_vp()
+        _check(_lib.gw_create(ctypes.byref(h), device, c_vp(stream.cuda_stream)))
+        self.handle = h
+        self.device = device
+        self.stream = stream
+
+    def close(self):
+        if self.handle:
+            _lib.gw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gw_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+def gw_destroy(ctx: Context):
+    ctx.close()
+
+
+def gw_sync(ctx: Context):
+    _check(_lib.gw_sync(ctx.handle), ctx)
+
+
+def gw_profile_enable(ctx, enable: bool = True):
+    _check(_lib.gw_profile_enable(ctx.handle, int(enable)), ctx)
+
+
+def gw_profile_get(ctx, kernel: str):
+    """(total_ms, launches, flops, bytes) recorded for `kernel`."""
+    ms, fl, by, n = c_dbl(), c_dbl(), c_dbl(), c_i64()
+    _check(_lib.gw_profile_get(ctx.handle, kernel.encode(), ctypes.byref(ms), ctypes.byref(n),
+                               ctypes.byref(fl), ctypes.byref(by)), ctx)
+    return ms.value, n.value, fl.value, by.value
+
+
+def gw_prepare(n_occ, n_fc, n_virt, eps, omega_min):
+    e = _host(eps)
+    out = (c_dbl(), c_dbl(), c_dbl())
+    _check(_lib.gw_prepare(n_occ, n_fc, n_virt, _dp(e), omega_min, *map(ctypes.byref, out)))
+    return tuple(o.value for o in out)
+
+
+def gw_freq_grid_mgl(n: int, x0: float = 0.5):
+    om, wt = np.empty(n), np.empty(n)
+    _check(_lib.gw_freq_grid_mgl(n, x0, _dp(om), _dp(wt)))
+    return om, wt
+
+
+def gw_lt_grid_minimax(n_lt: int, y_min: float, y_max: float):
+    x, w, err = np.empty(n_lt), np.empty(n_lt), c_dbl()
+    _check(_lib.gw_lt_grid_minimax(n_lt, y_min, y_max, _dp(x), _dp(w), ctypes.byref(err)))
+    return x, w, err.value
+
+
+def gw_minimax_inverse(n_lt: int, R: float, alpha0=None, omega0=None):
+    a0 = None if alpha0 is None else _host(alpha0)
+    o0 = None if omega0 is None else _host(omega0)
+    al, om, err = np.empty(n_lt), np.empty(n_lt), c_dbl()
+    _check(_lib.gw_minimax_inverse(n_lt, R, _dp(a0), _dp(o0), _dp(al), _dp(om),
+                                   ctypes.byref(err)))
+    return al, om, err.value
+
+
+def gw_naf_compress(ctx, prec, n_aux, R_oo, R_ov, K, accumulate, finalize, eps_naf,
+                    max_keep, U, want_eigvals=True):
+    n_oo = 0 if R_oo is None else R_oo.numel() // n_aux
+    n_ov = 0 if R_ov is None else R_ov.numel() // n_aux
+    n_naf = c_int(0)
+    ev = np.empty(n_aux) if (finalize and want_eigvals) else None
+    _check(_lib.gw_naf_compress(ctx.handle, _prec(prec), n_aux, n_oo, _dev(R_oo), n_ov,
+                                _dev(R_ov), _dev(K), int(accumulate), int(finalize),
+                                float(eps_naf), int(max_keep), ctypes.byref(n_naf),
+                                _dev(U), _dp(ev)), ctx)
+    return n_naf.value, ev
+
+
+def gw_naf_apply(ctx, prec, n_aux, n_naf, U, R_in, R_out):
+    n_rows = R_in.numel() // n_aux
+    _check(_lib.gw_naf_apply(ctx.handle, _prec(prec), n_aux, n_naf, _dev(U), n_rows,
+                             _dev(R_in), _dev(R_out)), ctx)
+
+
+def gw_polarizability_lt(ctx, prec, n_naf, x_lt, w_lt, n_i, n_virt, eps_i, eps_a, R_chunk,
+                         accumulate, finalize, M):
+    x, w = _host(x_lt), _host(w_lt)
+    ei, ea = _host(eps_i), _host(eps_a)
+    _check(_lib.gw_polarizability_lt(ctx.handle, _prec(prec), n_naf, len(x), _dp(x), _dp(w),
+                                     n_i, n_virt, _dp(ei), _dp(ea), _dev(R_chunk),
+                                     int(accumulate), int(finalize), _dev(M)), ctx)
+
+
+def gw_screen(ctx, prec, n_naf, x_lt, M, omega, W_hat):
+    x, om = _host(x_lt), _host(omega)
+    _check(_lib.gw_screen(ctx.handle, _prec(prec), n_naf, len(x), _dp(x), _dev(M), len(om),
+                          _dp(om), _dev(W_hat)), ctx)
+
+
+def gw_sigma_diag(ctx, prec, n_naf, n_qp, n_mo, eps_mo, eps_F, R_qp, omega, w_omega, W_hat,
+                  omega_pade, accumulate, sigma_iw, W_nm=None):
+    e, om, wt, op = _host(eps_mo), _host(omega), _host(w_omega), _host(omega_pade)
+    _check(_lib.gw_sigma_diag(ctx.handle, _prec(prec), n_naf, n_qp, n_mo, _dp(e), float(eps_F),
+                              _dev(R_qp), len(om), _dp(om), _dp(wt), _dev(W_hat), len(op),
+                              _dp(op), int(accumulate), _dev(sigma_iw), _dev(W_nm)), ctx)
+
+
+def gw_qp_solve(ctx, eps_n, static_n, eps_F, omega_pade, sigma_iw, eta, tol=1e-6,
+                max_iter=100):
+    en = _host(eps_n)
+    st = None if static_n is None else _host(static_n)
+    op = _host(omega_pade)
+    q = len(en)
+    E, Z, S = np.empty(q), np.empty(q), np.empty(q, dtype=np.int32)
+    _check(_lib.gw_qp_solve(ctx.handle, q, _dp(en), _dp(st), float(eps_F), len(op), _dp(op),
+                            _dev(sigma_iw), float(eta), float(tol), int(max_iter), _dp(E),
+                            _dp(Z), _ip(S)), ctx)
+    return E, Z, S
+
+
+def gw_g0w0(ctx, prec, params: GwParams, eps, qp, static_n, R_oo, R_ov, R_qp,
+            want_sigma=True):
+    e = _host(eps)
+    q = _host(qp, np.int32)
+    st = None if static_n is None else _host(static_n)
+    n = params.n_qp
+    E, Z, S = np.empty(n), np.empty(n), np.empty(n, dtype=np.int32)
+    sig = np.empty(2 * n * params.n_pade) if want_sigma else None
+    stats = GwStats()
+    _check(_lib.gw_g0w0(ctx.handle, _prec(prec), ctypes.byref(params), _dp(e), _ip(q), _dp(st),
+                        _dev(R_oo), _dev(R_ov), _dev(R_qp), _dp(E), _dp(Z), _ip(S), _dp(sig),
+                        ctypes.byref(stats)), ctx)
+    sigma = None if sig is None else (sig[0::2] + 1j * sig[1::2]).reshape(n, params.n_pade)
+    return E, Z, S, sigma, stats
+
+
+def params_for(cfg, freq_batch: int = 0, tol: float = 1e-6, max_iter: int = 100) -> GwParams:
+    """gw_params from a workload description with the fields of gwsynth.Config."""
+    return GwParams(n_occ=cfg.n_occ, n_fc=cfg.n_fc, n_virt=cfg.n_virt, n_aux=cfg.n_aux,
+                    n_lt=cfg.n_lt, n_freq=cfg.n_freq, n_pade=cfg.n_pade, n_qp=cfg.n_qp,
+                    eps_naf=cfg.eps_naf, max_keep=cfg.max_keep, x0=cfg.x0, eta=cfg.eta,
+                    tol=tol, max_iter=max_iter, freq_batch=freq_batch)

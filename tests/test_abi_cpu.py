@@ -1,0 +1,82 @@
+"""CPU tests of the C ABI: the library loads and exports every declared
+symbol, the host-side grids (rows a1 and a3) match the oracle, and argument
+errors come back as status codes.  No device work is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from oracle import grids
+
+gwlt = pytest.importorskip("paper_2307_04508_amd.gwlt")
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gwlt.h")).read()
+    return sorted(set(re.findall(r"^(?:gw_status|const char\*)\s+(gw_\w+)\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(gwlt.LIB_PATH)
+    names = _declared_symbols()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(gwlt.EXPORTS)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 32, 33, 128])
+def test_mgl_grid_matches_oracle(n):
+    om, wt = gwlt.gw_freq_grid_mgl(n, 0.5)
+    o2, w2 = grids.modified_gauss_legendre(n, 0.5)
+    # nodes near t = 1 are amplified by 1 / (1 - t) under the mapping
+    assert np.allclose(om, o2, rtol=1e-10, atol=1e-15)
+    assert np.allclose(wt, w2, rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("k,lo,hi", [(8, 0.1225, 1e4), (10, 0.1225, 1e4), (12, 0.1225, 1e4),
+                                     (6, 0.05, 300.0), (4, 2.0, 1e3)])
+def test_minimax_grid_matches_oracle(k, lo, hi):
+    x, w, e = gwlt.gw_lt_grid_minimax(k, lo, hi)
+    xo, wo, eo = grids.lt_grid(k, lo, hi)
+    assert np.allclose(x, xo, rtol=1e-9)
+    assert np.allclose(w, wo, rtol=1e-9)
+    assert abs(e - eo) < 1e-9 * eo
+
+
+@pytest.mark.parametrize("k", [14, 16])
+def test_minimax_grid_equioscillates_large_k(k):
+    al, om, e = gwlt.gw_minimax_inverse(k, 8.16e4)
+    pts, vals = grids._extrema(8.16e4, al, om, k, n_grid=40000)
+    assert pts.size == 2 * k + 1
+    assert np.all(np.sign(vals[1:]) == -np.sign(vals[:-1]))
+    assert np.max(np.abs(vals)) - np.min(np.abs(vals)) < 1e-8 * e
+
+
+def test_prepare_matches_oracle(tiny_problem):
+    p = tiny_problem
+    c = p.cfg
+    eF, lo, hi = gwlt.gw_prepare(c.n_occ, c.n_fc, c.n_virt, p.eps, 0.01)
+    lo2, hi2 = grids.lt_bounds(p.eps, c.n_fc, c.n_occ, 0.01)
+    assert eF == pytest.approx(0.5 * (p.eps[c.n_occ - 1] + p.eps[c.n_occ]), abs=1e-15)
+    assert lo == pytest.approx(lo2, rel=1e-15) and hi == pytest.approx(hi2, rel=1e-15)
+
+
+def test_argument_errors_are_status_codes():
+    with pytest.raises(gwlt.GwError) as ei:
+        gwlt.gw_freq_grid_mgl(0, 0.5)
+    assert ei.value.status == gwlt.GW_EINVAL
+    with pytest.raises(gwlt.GwError) as ei:
+        gwlt.gw_lt_grid_minimax(17, 1.0, 10.0)
+    assert ei.value.status == gwlt.GW_EINVAL
+    with pytest.raises(gwlt.GwError):
+        gwlt.gw_prepare(3, 3, 5, np.zeros(8), 0.0)        # n_fc == n_occ
+    lib = gwlt._lib
+    assert lib.gw_polarizability_lt(None, 0, 1, 1, None, None, 0, 1, None, None, None, 0, 0,
+                                    None) == gwlt.GW_EINVAL
+    assert lib.gw_screen(None, 0, 1, 1, None, None, 1, None, None) == gwlt.GW_EINVAL
+    assert lib.gw_sync(None) == gwlt.GW_EINVAL
+    assert b"NULL" in lib.gw_last_error(None) or lib.gw_last_error(None) != b""

@@ -1,0 +1,345 @@
+"""GPU parity tests: every step of the hot path through the C ABI against the
+FP64 oracle on the same seeded inputs.
+
+Tolerances: FP64 paths to rounding (relative 1e-10 or tighter); the FP32
+Laplace matrices M^m to a relative Frobenius error of 1e-6 per point; QP
+energies to 1 meV against the oracle taking the same Laplace grid (the
+precision part), with the Laplace error itself (oracle Laplace form vs sum
+over states) reported next to it.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import HARTREE_MEV, ROOT
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from oracle import grids, naf, pade, rpa, sigma  # noqa: E402
+from oracle.g0w0 import g0w0_problem  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_04508_amd import gwlt
+    return gwlt
+
+
+@pytest.fixture(scope="module")
+def ctx(gw):
+    c = gw.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dt).contiguous()
+
+
+def rel_fro(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------ a4: chi
+
+def _lt_case(seed, o, v, N, L):
+    rng = np.random.default_rng(seed)
+    eps_i = -np.sort(rng.uniform(0.3, 20.0, o))[::-1]
+    eps_a = np.sort(rng.uniform(0.05, 5.0, v))
+    R = rng.standard_normal((o * v, N)) / np.sqrt(N)
+    x, w, _ = grids.lt_grid(L, (eps_a[0] - eps_i[-1]) ** 2, 1e4)
+    return eps_i, eps_a, R, x, w
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+@pytest.mark.parametrize("shape", [(8, 40, 150), (13, 389, 300), (3, 7, 129)])
+def test_polarizability_lt_matches_oracle(gw, ctx, prec, tol, shape):
+    o, v, N = shape
+    _say(f"polarizability {prec} o={o} v={v} N={N}")
+    eps_i, eps_a, R, x, w = _lt_case(11, o, v, N, 4)
+    d = (eps_a[None, :] - eps_i[:, None]).ravel()
+    ref = rpa.m_lt(R, d, x, w)
+    M = torch.full((4, N, N), float("nan"), dtype=torch.float64, device="cuda")
+    gw.gw_polarizability_lt(ctx, prec, N, x, w, o, v, eps_i, eps_a, dev(R, prec), 0, 1, M)
+    gw.gw_sync(ctx)
+    Mh = M.cpu().numpy()
+    assert np.all(np.isfinite(Mh))
+    assert np.array_equal(Mh, np.transpose(Mh, (0, 2, 1)))      # exactly symmetric
+    for m in range(4):
+        assert rel_fro(Mh[m], ref[m]) < tol, (m, rel_fro(Mh[m], ref[m]))
+
+
+def test_polarizability_chunks_accumulate(gw, ctx):
+    o, v, N = 10, 211, 140
+    eps_i, eps_a, R, x, w = _lt_case(5, o, v, N, 3)
+    d = (eps_a[None, :] - eps_i[:, None]).ravel()
+    ref = rpa.m_lt(R, d, x, w)
+    M = torch.zeros((3, N, N), dtype=torch.float64, device="cuda")
+    Rd = dev(R, "fp64")
+    gw.gw_polarizability_lt(ctx, "fp64", N, x, w, 4, v, eps_i[:4], eps_a, Rd[: 4 * v], 0, 0, M)
+    gw.gw_polarizability_lt(ctx, "fp64", N, x, w, 0, v, eps_i[:0], eps_a, None, 1, 0, M)
+    gw.gw_polarizability_lt(ctx, "fp64", N, x, w, 6, v, eps_i[4:], eps_a, Rd[4 * v:], 1, 1, M)
+    gw.gw_sync(ctx)
+    Mh = M.cpu().numpy()
+    for m in range(3):
+        assert rel_fro(Mh[m], ref[m]) < 1e-12
+
+
+def test_polarizability_empty_chunk_gives_zero(gw, ctx):
+    N = 64
+    M = torch.full((2, N, N), 7.0, dtype=torch.float64, device="cuda")
+    gw.gw_polarizability_lt(ctx, "fp32", N, [0.1, 1.0], [0.5, 0.5], 0, 5, np.zeros(0),
+                            np.ones(5), None, 0, 1, M)
+    gw.gw_sync(ctx)
+    assert torch.all(M == 0)
+
+
+def test_polarizability_rejects_bad_arguments(gw, ctx):
+    M = torch.zeros((1, 4, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(gw.GwError) as ei:
+        gw.gw_polarizability_lt(ctx, "fp64", 0, [1.0], [1.0], 1, 1, [0.0], [1.0],
+                                torch.zeros(1, 4, dtype=torch.float64, device="cuda"), 0, 1, M)
+    assert ei.value.status == gw.GW_EINVAL
+
+
+# ------------------------------------------------------------------ a5 + a6
+
+def _spd_m(seed, L, N):
+    rng = np.random.default_rng(seed)
+    M = np.empty((L, N, N))
+    for m in range(L):
+        X = rng.standard_normal((N + 20, N)) / np.sqrt(N) * 0.3 / (m + 1)
+        M[m] = X.T @ X
+    return M
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-7)])
+@pytest.mark.parametrize("N,F", [(150, 5), (333, 3), (64, 2), (1, 2)])
+def test_screen_matches_oracle(gw, ctx, prec, tol, N, F):
+    _say(f"screen {prec} N={N} F={F}")
+    L = 3
+    M = _spd_m(3, L, N)
+    x = np.array([0.05, 0.5, 3.0])
+    om, _ = grids.modified_gauss_legendre(F, 0.5)
+    ref = rpa.screen(rpa.pi_lt(M, x, om))
+    W = torch.zeros((F, N, N), dtype=torch.float64 if prec == "fp64" else torch.float32,
+                    device="cuda")
+    gw.gw_screen(ctx, prec, N, x, dev(M, "fp64"), om, W)
+    gw.gw_sync(ctx)
+    Wh = W.double().cpu().numpy()
+    for j in range(F):
+        assert rel_fro(Wh[j], ref[j]) < tol, (j, rel_fro(Wh[j], ref[j]))
+        assert np.array_equal(Wh[j], Wh[j].T)
+
+
+def test_screen_reports_non_spd(gw, ctx):
+    N = 70
+    M = -np.eye(N)[None] * 10.0          # 1 - Pi = 1 - 40 I: indefinite
+    W = torch.zeros((1, N, N), dtype=torch.float64, device="cuda")
+    gw.gw_screen(ctx, "fp64", N, np.array([0.1]), dev(M, "fp64"), np.array([0.2]), W)
+    with pytest.raises(gw.GwError) as ei:
+        gw.gw_sync(ctx)
+    assert ei.value.status == gw.GW_ENOTSPD
+    gw.gw_sync(ctx)                      # flag cleared
+
+
+# ------------------------------------------------------------------ a7 + a8
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-6)])
+def test_sigma_diag_matches_oracle(gw, ctx, tiny_problem, tiny_sos, prec, tol):
+    p, r = tiny_problem, tiny_sos
+    c = p.cfg
+    _say(f"sigma_diag {prec}")
+    What = rpa.screen(r.Pi)
+    W_ref = rpa.w_diag(r.Rt_qp, What)
+    eps_m = p.eps[c.n_fc:]
+    S_ref = sigma.sigma_iw(W_ref, eps_m, r.eps_f, r.omega, r.w_omega, r.omega_pade)
+    Q, Mo, N = r.Rt_qp.shape
+    F = len(r.omega)
+    sig = torch.zeros((Q, len(r.omega_pade), 2), dtype=torch.float64, device="cuda")
+    Wnm = torch.zeros((F, Q, Mo), dtype=torch.float64, device="cuda")
+    gw.gw_sigma_diag(ctx, prec, N, Q, Mo, eps_m, r.eps_f, dev(r.Rt_qp, prec), r.omega,
+                     r.w_omega, dev(What, prec), r.omega_pade, 0, sig, Wnm)
+    gw.gw_sync(ctx)
+    assert rel_fro(Wnm.cpu().numpy(), W_ref) < tol
+    s = sig.cpu().numpy()
+    S = s[..., 0] + 1j * s[..., 1]
+    assert np.max(np.abs(S - S_ref)) < tol * np.max(np.abs(S_ref)) * 10
+
+
+def test_sigma_diag_frequency_batches_accumulate(gw, ctx, tiny_problem, tiny_sos):
+    p, r = tiny_problem, tiny_sos
+    c = p.cfg
+    What = rpa.screen(r.Pi)
+    eps_m = p.eps[c.n_fc:]
+    Q, Mo, N = r.Rt_qp.shape
+    S_ref = sigma.sigma_iw(rpa.w_diag(r.Rt_qp, What), eps_m, r.eps_f, r.omega, r.w_omega,
+                           r.omega_pade)
+    sig = torch.zeros((Q, len(r.omega_pade), 2), dtype=torch.float64, device="cuda")
+    Rd = dev(r.Rt_qp, "fp64")
+    for j0, acc in ((0, 0), (13, 1)):
+        j1 = 13 if j0 == 0 else len(r.omega)
+        gw.gw_sigma_diag(ctx, "fp64", N, Q, Mo, eps_m, r.eps_f, Rd, r.omega[j0:j1],
+                         r.w_omega[j0:j1], dev(What[j0:j1], "fp64"), r.omega_pade, acc, sig)
+    gw.gw_sync(ctx)
+    s = sig.cpu().numpy()
+    assert np.max(np.abs(s[..., 0] + 1j * s[..., 1] - S_ref)) < 1e-12 * np.max(np.abs(S_ref))
+
+
+# ------------------------------------------------------------------ a9
+
+def test_qp_solve_matches_oracle(gw, ctx, tiny_problem, tiny_sos):
+    p, r = tiny_problem, tiny_sos
+    c = p.cfg
+    Q, Pd = r.sigma.shape
+    sig = torch.as_tensor(np.stack([r.sigma.real, r.sigma.imag], -1)).cuda().contiguous()
+    static = np.array([0.003, -0.002])
+    E, Z, S = gw.gw_qp_solve(ctx, p.eps[p.qp], static, r.eps_f, r.omega_pade, sig, c.eta,
+                             1e-10, 200)
+    zn = 1j * r.omega_pade
+    for q, n in enumerate(p.qp):
+        a = pade.thiele_coefficients(zn, r.sigma[q])
+        Eo, Zo, ok = pade.qp_solve(p.eps[n], static[q], r.eps_f, zn, a, c.eta, tol=1e-10,
+                                   max_iter=200)
+        assert S[q] == 0 and ok
+        assert abs(E[q] - Eo) < 1e-9
+        assert abs(Z[q] - Zo) < 1e-6
+
+
+def test_qp_solve_zero_sigma_and_errors(gw, ctx):
+    wp, _ = grids.modified_gauss_legendre(8, 0.5)
+    sig = torch.zeros((2, 8, 2), dtype=torch.float64, device="cuda")
+    E, Z, S = gw.gw_qp_solve(ctx, [-0.5, 0.2], [0.01, 0.0], -0.1, wp, sig, 1e-3)
+    assert np.allclose(E, [-0.49, 0.2], atol=1e-15) and np.all(S == 0) and np.allclose(Z, 1.0)
+    with pytest.raises(gw.GwError) as ei:
+        gw.gw_qp_solve(ctx, [-0.5], None, -0.1, np.array([0.1, 0.1]),
+                       torch.zeros((1, 2, 2), dtype=torch.float64, device="cuda"), 1e-3)
+    assert ei.value.status == gw.GW_EPADE
+    E, Z, S = gw.gw_qp_solve(ctx, [-0.5], None, -0.1, wp[:4],
+                             torch.ones((1, 4, 2), dtype=torch.float64, device="cuda"), 1e-3,
+                             1e-12, 1)
+    assert S[0] == 1                       # not converged in one step
+
+
+# ------------------------------------------------------------------ a2: NAF
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_naf_matches_oracle(gw, ctx, tiny_problem, prec):
+    p = tiny_problem
+    c = p.cfg
+    A = c.n_aux
+    _say(f"naf {prec}")
+    # reference from the inputs as the device sees them (FP32-rounded for FP32)
+    dt = np.float64 if prec == "fp64" else np.float32
+    R_oo = p.R_oo.astype(dt).astype(np.float64)
+    R_ov = p.R_ov.astype(dt).astype(np.float64)
+    K_ref = naf.naf_metric(R_oo, R_ov)
+    lam_ref, _ = naf.naf_basis(K_ref, 0.0)
+    eps_cut = 0.5 * (lam_ref[99] + lam_ref[100])
+    _, U_ref = naf.naf_basis(K_ref, eps_cut)
+    K = torch.zeros((A, A), dtype=torch.float64, device="cuda")
+    U = torch.zeros((A, A), dtype=torch.float64, device="cuda")
+    # metric alone (no finalize): lower triangle is the computed part
+    gw.gw_naf_compress(ctx, prec, A, dev(p.R_oo, prec), dev(p.R_ov, prec), K, 0, 0, 0.0, 0,
+                       None)
+    gw.gw_sync(ctx)
+    Kl = np.tril(K.cpu().numpy())
+    Kg = Kl + np.tril(Kl, -1).T
+    dK = np.linalg.norm(Kg - K_ref)
+    assert dK < (1e-13 if prec == "fp64" else 1e-7) * np.linalg.norm(K_ref)
+    K.zero_()
+    n, ev = gw.gw_naf_compress(ctx, prec, A, dev(p.R_oo, prec), dev(p.R_ov, prec), K, 0, 1,
+                               eps_cut, 0, U)
+    assert n == 100
+    # Weyl: |d lambda| <= ||dK||_2 <= ||dK||_F (plus the eigensolver's rounding)
+    assert np.max(np.abs(ev - lam_ref)) <= dK + 1e-12 * lam_ref[0]
+    Uh = U.cpu().numpy()[:n].T
+    assert np.allclose(Uh.T @ Uh, np.eye(n), atol=1e-12)
+    P, P_ref = Uh @ Uh.T, U_ref @ U_ref.T
+    # Davis-Kahan: ||dP||_F <= sqrt(2) ||dK||_F / gap at the cut
+    gap = lam_ref[99] - lam_ref[100]
+    assert np.linalg.norm(P - P_ref) <= np.sqrt(2) * (dK + 1e-12 * lam_ref[0]) / (0.5 * gap)
+    # transform: Gram matrix of the transformed rows is basis independent
+    Rout = torch.zeros((p.R_ov.shape[0], n), dtype=torch.float64 if prec == "fp64" else
+                       torch.float32, device="cuda")
+    gw.gw_naf_apply(ctx, prec, A, n, U, dev(p.R_ov, prec), Rout)
+    gw.gw_sync(ctx)
+    Ro = Rout.double().cpu().numpy()
+    G, G_ref = Ro @ Ro.T, (R_ov @ U_ref) @ (R_ov @ U_ref).T
+    assert rel_fro(G, G_ref) < (1e-10 if prec == "fp64" else 1e-4)
+    # max_keep cap
+    K.zero_()
+    n2, _ = gw.gw_naf_compress(ctx, prec, A, dev(p.R_oo, prec), dev(p.R_ov, prec), K, 0, 1,
+                               0.0, 37, U)
+    assert n2 == 37
+
+
+# ------------------------------------------------------------------ whole step
+
+def _lt_grid_for(prob, omega0):
+    c = prob.cfg
+    lo, hi = grids.lt_bounds(prob.eps, c.n_fc, c.n_occ, omega0)
+    return grids.lt_grid(c.n_lt, lo, hi)
+
+
+@pytest.mark.parametrize("prec,tol_mev", [("fp64", 1e-4), ("fp32", 0.1)])
+def test_g0w0_tiny(gw, ctx, tiny_problem, tiny_sos, prec, tol_mev):
+    p = tiny_problem
+    c = p.cfg
+    _say(f"g0w0 tiny {prec}")
+    x, w, _ = _lt_grid_for(p, tiny_sos.omega[0])
+    lt = g0w0_problem(p, lt=(x, w))
+    params = gw.params_for(c, tol=1e-10, max_iter=200)
+    E, Z, S, sig, st = gw.gw_g0w0(ctx, prec, params, p.eps, p.qp, None, dev(p.R_oo, prec),
+                                  dev(p.R_ov, prec), dev(p.R_qp, prec))
+    assert np.all(S == 0) and st.n_naf == c.n_aux
+    err_prec = np.abs(E - lt.eps_qp) * HARTREE_MEV
+    err_lt = np.abs(lt.eps_qp - tiny_sos.eps_qp) * HARTREE_MEV
+    _say(f"  precision part {err_prec} meV, Laplace part {err_lt} meV")
+    assert np.all(err_prec < tol_mev)
+    assert np.max(np.abs(sig - lt.sigma)) < 1e-5 * np.max(np.abs(lt.sigma))
+
+
+def _golden(name):
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} missing")
+    return json.load(open(path))
+
+
+@pytest.fixture(scope="module")
+def medium_problem():
+    from gwsynth import get_config, make_problem
+    return make_problem(get_config("medium"), dtype=np.float32)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_g0w0_medium_matches_golden(gw, ctx, medium_problem, prec):
+    g = _golden("medium")
+    p = medium_problem
+    c = p.cfg
+    _say(f"g0w0 medium {prec}")
+    params = gw.params_for(c)
+    E, Z, S, sig, st = gw.gw_g0w0(ctx, prec, params, p.eps, p.qp, None, dev(p.R_oo, prec),
+                                  dev(p.R_ov, prec), dev(p.R_qp, prec))
+    assert st.n_naf == g["n_naf"]
+    err_prec = np.abs(E - np.array(g["eps_qp_lt"])) * HARTREE_MEV
+    err_lt = np.abs(np.array(g["eps_qp_lt"]) - np.array(g["eps_qp_sos"])) * HARTREE_MEV
+    _say(f"  N={st.n_naf} precision part max {err_prec.max():.2e} meV, "
+         f"Laplace part max {err_lt.max():.2e} meV, status {S}")
+    assert np.all(S == 0)
+    assert np.all(err_prec < 1.0)
+    S_ref = np.array(g["sigma_lt_re"]) + 1j * np.array(g["sigma_lt_im"])
+    assert np.max(np.abs(sig - S_ref)) < 1e-4 * np.max(np.abs(S_ref))
