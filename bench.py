@@ -129,12 +129,12 @@ def main():
     t1 = time.perf_counter()
     wall = (t1 - t0) / args.steps
     log(f"timed {args.steps} steps: {wall * 1e3:.1f} ms/step, N_NAF={st.n_naf}")
-    kname = "syrk_f32" if args.prec == "fp32" else "syrk_f64"
+    kname = "chi_syrk_f32" if args.prec == "fp32" else "chi_syrk_f64"
     bname = "bwb_f32" if args.prec == "fp32" else "bwb_f64"
     chi = kernel_rate(gw, ctx, kname)
     bwb = kernel_rate(gw, ctx, bname)
     others = {n: kernel_rate(gw, ctx, n) for n in
-              ("screen_sweep", "naf_eig", "naf_gemm_f32", "naf_gemm_f64")}
+              ("naf_syrk", "screen_sweep", "naf_eig", "naf_gemm_f32", "naf_gemm_f64")}
     gw.gw_profile_enable(ctx, False)
     stage_ms = {"naf": st.t_naf_ms, "chi": st.t_chi_ms, "screen": st.t_screen_ms,
                 "sigma": st.t_sigma_ms, "qp": st.t_qp_ms, "total": st.t_total_ms}

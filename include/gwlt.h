@@ -77,7 +77,7 @@ const char* gw_last_error(gw_ctx ctx);
 const char* gw_status_string(gw_status s);
 
 /* Kernel timing.  While enabled, HIP events bracket the hot kernels on the
- * context's stream (the polarizability SYRK "syrk_f32"/"syrk_f64", the
+ * context's stream (the polarizability SYRK "chi_syrk_f32"/"chi_syrk_f64", the NAF metric "naf_syrk", the
  * self-energy contraction "bwb_f32"/"bwb_f64", the screening sweep
  * "screen_sweep", the NAF transform "naf_gemm_f32"/"naf_gemm_f64" and the
  * eigensolver "naf_eig").  gw_profile_get (synchronises) returns, for one
@@ -155,12 +155,13 @@ gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
                           double* eigvals);
 
 /* Eq. 13: R_out[r][q] = sum_P R_in[r][P] U[q][P] for q < n_naf.
- * R_in device [n_rows][n_aux], R_out device [n_rows][n_naf], both FP64
+ * R_in device [n_rows][n_aux], R_out device [n_rows][ld_out] (ld_out = 0
+ * means n_naf; columns n_naf .. ld_out-1 are set to zero), both FP64
  * (GW_FP64) or FP32 (otherwise; the product is accumulated in FP32 MFMA
  * with FP64 partial sums).  U as returned by gw_naf_compress. */
 gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int n_naf,
                        const double* U, int64_t n_rows, const void* R_in,
-                       void* R_out);
+                       void* R_out, int64_t ld_out);
 
 /* ----------------------------------------------- a4: LT polarizability */
 
@@ -168,7 +169,9 @@ gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int n_naf,
  *   M^m_PQ += sum_ia R_ia,P  w_m D_ia exp(-D_ia^2 x_m)  R_ia,Q,
  * D_ia = eps_a[a] - eps_i[i], over one chunk of n_i active occupied
  * orbitals.  x_lt, w_lt host [n_lt] (n_lt <= 32); eps_i host [n_i];
- * eps_a host [n_virt]; R_chunk device [n_i * n_virt][n_naf] (i-major).
+ * eps_a host [n_virt]; R_chunk device [n_i * n_virt][ld_R] (i-major; ld_R
+ * >= n_naf is the row stride, 0 means n_naf; rows padded to a multiple of
+ * 128 columns take the kernel's unguarded load path).
  * M device [n_lt][n_naf][n_naf] FP64.  accumulate == 0 overwrites M,
  * otherwise adds.  Only the lower triangle P >= Q is updated until a call
  * with finalize != 0, which copies it onto the upper triangle (M is then
@@ -179,8 +182,8 @@ gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_naf,
                                int n_lt, const double* x_lt,
                                const double* w_lt, int n_i, int n_virt,
                                const double* eps_i, const double* eps_a,
-                               const void* R_chunk, int accumulate,
-                               int finalize, double* M);
+                               const void* R_chunk, int64_t ld_R,
+                               int accumulate, int finalize, double* M);
 
 /* ------------------------------------------------ a5 + a6: screening */
 
@@ -204,7 +207,8 @@ gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_lt,
  * contraction, on MFMA), then
  *   Sigma_n(e_F + i wp_k) = -(1/pi) sum_j w_omega_j sum_m
  *        a / (a^2 + omega_j^2) W_nm(i omega_j),  a = i wp_k + eps_F - eps_m,
- * in FP64.  R_qp device [n_qp][n_mo][n_naf] (m over active orbitals);
+ * in FP64.  R_qp device [n_qp][n_mo][ld_R] (m over active orbitals; row
+ * stride ld_R >= n_naf, 0 means n_naf);
  * eps_mo host [n_mo] (active orbital energies); omega, w_omega host [n_w];
  * W_hat as written by gw_screen; omega_pade host [n_pade].
  * sigma_iw device [n_qp][n_pade] complex; accumulate != 0 adds this
@@ -212,7 +216,8 @@ gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_lt,
  * output (NULL to skip). */
 gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
                         int n_mo, const double* eps_mo, double eps_F,
-                        const void* R_qp, int n_w, const double* omega,
+                        const void* R_qp, int64_t ld_R, int n_w,
+                        const double* omega,
                         const double* w_omega, const void* W_hat,
                         int n_pade, const double* omega_pade, int accumulate,
                         double* sigma_iw, double* W_nm);

@@ -96,7 +96,7 @@ void prof_end(gw_ctx ctx, int idx, const char* name, double flops, double bytes)
 gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X,
                       int64_t k_rows, int N, int64_t ld, int L,
                       const void* scale, double cscale, double* out,
-                      int accumulate);
+                      int accumulate, const char* prof_name);
 gw_status mirror_lower(gw_ctx ctx, double* M, int L, int N);
 gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L,
                           const double* d_x, const double* d_w, int n_i,

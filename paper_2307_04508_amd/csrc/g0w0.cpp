@@ -81,6 +81,7 @@ extern "C" gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* P,
   double* U = static_cast<double*>(gw::ws_get(ctx, WS_G_U, (size_t)A * A * sizeof(double)));
   if (!K || !U) return GW_ENOMEM;
   int N = 0;
+  int64_t ldN = 0;   // NAF-space rows padded to whole 128-column tiles
   void* Rt_ov = nullptr;
   void* Rt_qp = nullptr;
   st = gw_naf_compress(ctx, prec, A, (int64_t)o * o, R_oo, (int64_t)o * v, R_ov, K, 0, 1,
@@ -88,12 +89,14 @@ extern "C" gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* P,
   if (st == GW_OK && N < 1)
     st = gw::fail(ctx, GW_EINVAL, "gw_g0w0: no auxiliary function above eps_naf");
   if (st == GW_OK) {
-    Rt_ov = gw::ws_get(ctx, WS_G_RT_OV, (size_t)o * v * N * esz);
-    Rt_qp = gw::ws_get(ctx, WS_G_RT_QP, (size_t)P->n_qp * Mo * N * esz);
+    ldN = ((int64_t)N + 127) / 128 * 128;
+    Rt_ov = gw::ws_get(ctx, WS_G_RT_OV, (size_t)o * v * ldN * esz);
+    Rt_qp = gw::ws_get(ctx, WS_G_RT_QP, (size_t)P->n_qp * Mo * ldN * esz);
     if (!Rt_ov || !Rt_qp) st = GW_ENOMEM;
   }
-  if (st == GW_OK) st = gw_naf_apply(ctx, prec, A, N, U, (int64_t)o * v, R_ov, Rt_ov);
-  if (st == GW_OK) st = gw_naf_apply(ctx, prec, A, N, U, (int64_t)P->n_qp * Mo, R_qp, Rt_qp);
+  if (st == GW_OK) st = gw_naf_apply(ctx, prec, A, N, U, (int64_t)o * v, R_ov, Rt_ov, ldN);
+  if (st == GW_OK)
+    st = gw_naf_apply(ctx, prec, A, N, U, (int64_t)P->n_qp * Mo, R_qp, Rt_qp, ldN);
   if (st != GW_OK) {
     lt_job.wait();
     return st;
@@ -107,7 +110,7 @@ extern "C" gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* P,
   double* Mm = static_cast<double*>(gw::ws_get(ctx, WS_G_M, (size_t)P->n_lt * N * N * sizeof(double)));
   if (!Mm) return GW_ENOMEM;
   GW_TRY(gw_polarizability_lt(ctx, prec, N, P->n_lt, xl.data(), wl.data(), o, v, eps + P->n_fc,
-                              eps + P->n_occ, Rt_ov, 0, 1, Mm));
+                              eps + P->n_occ, Rt_ov, ldN, 0, 1, Mm));
   ev.rec(2, ctx->stream);
 
   // a5-a8 in frequency batches
@@ -122,7 +125,8 @@ extern "C" gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* P,
     ev.rec(3, ctx->stream);
     GW_TRY(gw_screen(ctx, prec, N, P->n_lt, xl.data(), Mm, nb, om.data() + j0, What));
     ev.rec(4, ctx->stream);
-    GW_TRY(gw_sigma_diag(ctx, prec, N, P->n_qp, Mo, eps + P->n_fc, eF, Rt_qp, nb, om.data() + j0,
+    GW_TRY(gw_sigma_diag(ctx, prec, N, P->n_qp, Mo, eps + P->n_fc, eF, Rt_qp, ldN, nb,
+                         om.data() + j0,
                          wom.data() + j0, What, P->n_pade, omp.data(), j0 > 0, sig, nullptr));
     ev.rec(5, ctx->stream);
     if (stats) {

@@ -43,10 +43,11 @@ __global__ void reorder_kernel(const double* __restrict__ V, int n, double* __re
 struct GemmArgs {
   const void* A;      // [rows][K]
   const double* B;    // [ncols][K] FP64
-  void* C;            // [rows][ncols]
+  void* C;            // [rows][ldc]; columns ncols .. ldc-1 are zeroed
   int64_t rows;
   int K;
   int ncols;
+  int64_t ldc;
   int row_tiles, col_tiles;
 };
 
@@ -124,7 +125,8 @@ __global__ __launch_bounds__(NT, 1) void nt_gemm_f32_kernel(GemmArgs g) {
       for (int r = 0; r < 16; ++r) {
         const int64_t row = row0 + wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int col = col0 + wx * 64 + j * 32 + (lane & 31);
-        if (row < g.rows && col < g.ncols) C[row * g.ncols + col] = (float)acc64[i][j][r];
+        if (row < g.rows && col < g.ldc)
+          C[row * g.ldc + col] = col < g.ncols ? (float)acc64[i][j][r] : 0.f;
       }
 }
 
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(NT, 1) void nt_gemm_f64_kernel(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int64_t row = row0 + wy * 64 + i * 16 + (lane >> 4) + 4 * r;
         const int col = col0 + wx * 64 + j * 16 + (lane & 15);
-        if (row < g.rows && col < g.ncols) C[row * g.ncols + col] = acc[i][j][r];
+        if (row < g.rows && col < g.ldc) C[row * g.ldc + col] = col < g.ncols ? acc[i][j][r] : 0.0;
       }
 }
 
@@ -217,10 +219,11 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
   // FP32- and BF16x3-path tensors are stored in FP32: FP32 MFMA metric.
   const gw_precision mp = prec == GW_FP64 ? GW_FP64 : GW_FP32;
   if (n_oo_rows > 0)
-    GW_TRY(gw::syrk_launch(ctx, mp, R_oo, n_oo_rows, n_aux, n_aux, 1, nullptr, 2.0, K, accumulate));
+    GW_TRY(gw::syrk_launch(ctx, mp, R_oo, n_oo_rows, n_aux, n_aux, 1, nullptr, 2.0, K, accumulate,
+                           "naf_syrk"));
   if (n_ov_rows > 0)
     GW_TRY(gw::syrk_launch(ctx, mp, R_ov, n_ov_rows, n_aux, n_aux, 1, nullptr, 4.0, K,
-                           accumulate || n_oo_rows > 0));
+                           accumulate || n_oo_rows > 0, "naf_syrk"));
   if (n_oo_rows == 0 && n_ov_rows == 0 && !accumulate)
     GW_HIP(ctx, hipMemsetAsync(K, 0, (size_t)n_aux * n_aux * sizeof(double), ctx->stream));
   if (!finalize) return GW_OK;
@@ -269,7 +272,7 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
 
 extern "C" gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int n_naf,
                                   const double* U, int64_t n_rows, const void* R_in,
-                                  void* R_out) {
+                                  void* R_out, int64_t ld_out) {
   if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_naf_apply: ctx is NULL");
   gw::clear_error(ctx);
   GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
@@ -277,10 +280,12 @@ extern "C" gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int 
   GW_REQUIRE(ctx, n_aux >= 1 && n_naf >= 1 && n_naf <= n_aux && n_rows >= 0,
              "gw_naf_apply: bad sizes (n_aux=%d n_naf=%d)", n_aux, n_naf);
   GW_REQUIRE(ctx, U && (n_rows == 0 || (R_in && R_out)), "gw_naf_apply: NULL argument");
+  if (ld_out == 0) ld_out = n_naf;
+  GW_REQUIRE(ctx, ld_out >= n_naf, "gw_naf_apply: ld_out < n_naf");
   if (n_rows == 0) return GW_OK;
   GW_HIP(ctx, hipSetDevice(ctx->device));
-  const int rt = (int)((n_rows + BM - 1) / BM), ct = (n_naf + BM - 1) / BM;
-  GemmArgs g{R_in, U, R_out, n_rows, n_aux, n_naf, rt, ct};
+  const int rt = (int)((n_rows + BM - 1) / BM), ct = (int)((ld_out + BM - 1) / BM);
+  GemmArgs g{R_in, U, R_out, n_rows, n_aux, n_naf, ld_out, rt, ct};
   const int64_t grid = (int64_t)rt * ct;
   const int pi = gw::prof_begin(ctx);
   if (prec == GW_FP64)

@@ -25,10 +25,11 @@ inline int grid_for(int64_t n, int block) {
 }
 
 struct BwbArgs {
-  const void* R;      // [rows][N]
+  const void* R;      // [rows][ldr]
   const void* W;      // [F][N][N]
   int64_t rows;
   int N;
+  int64_t ldr;
   int F;
   int row_tiles;
   int col_tiles;
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a) {
       const int k = k0 + (tid & 7) * 4;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (row < a.rows) {
-        const int64_t off = row * a.N + k;
+        const int64_t off = row * a.ldr + k;
         const float* p = R + off;
         if (k + 3 < a.N && (off & 3) == 0) v = *reinterpret_cast<const float4*>(p);
         else {
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a) {
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
           const int col = col0 + wx * 64 + jj * 32 + (lane & 31);
-          if (col < a.N) s += (double)acc[i][jj][r] * (double)R[row * a.N + col];
+          if (col < a.N) s += (double)acc[i][jj][r] * (double)R[row * a.ldr + col];
         }
       }
 #pragma unroll
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a) {
       const int k = k0 + (tid & 7) * 2;
       double2 v = make_double2(0.0, 0.0);
       if (row < a.rows) {
-        const int64_t off = row * a.N + k;
+        const int64_t off = row * a.ldr + k;
         const double* p = R + off;
         if (k + 1 < a.N && (off & 1) == 0) v = *reinterpret_cast<const double2*>(p);
         else {
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a) {
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int col = col0 + wx * 64 + jj * 16 + (lane & 15);
-          if (col < a.N) s += acc[i][jj][r] * R[row * a.N + col];
+          if (col < a.N) s += acc[i][jj][r] * R[row * a.ldr + col];
         }
       }
 #pragma unroll
@@ -340,7 +341,8 @@ __global__ __launch_bounds__(256) void sigma_quad_kernel(
 
 extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
                                    int n_mo, const double* eps_mo, double eps_F,
-                                   const void* R_qp, int n_w, const double* omega,
+                                   const void* R_qp, int64_t ld_R, int n_w,
+                                   const double* omega,
                                    const double* w_omega, const void* W_hat, int n_pade,
                                    const double* omega_pade, int accumulate,
                                    double* sigma_iw, double* W_nm) {
@@ -354,6 +356,8 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
              "gw_sigma_diag: bad sizes");
   GW_REQUIRE(ctx, eps_mo && R_qp && omega && w_omega && W_hat && omega_pade && sigma_iw,
              "gw_sigma_diag: NULL argument");
+  if (ld_R == 0) ld_R = n_naf;
+  GW_REQUIRE(ctx, ld_R >= n_naf, "gw_sigma_diag: ld_R < n_naf");
   GW_HIP(ctx, hipSetDevice(ctx->device));
   const int N = n_naf, F = n_w;
   const int64_t rows = (int64_t)n_qp * n_mo;
@@ -369,7 +373,7 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
       gw::ws_get(ctx, WS_SIGMA_PART, (size_t)F * n_part * rows * sizeof(double)));
   double* W = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_W, (size_t)F * rows * sizeof(double)));
   if (!part || !W) return GW_ENOMEM;
-  BwbArgs a{R_qp, W_hat, rows, N, F, row_tiles, col_tiles, part};
+  BwbArgs a{R_qp, W_hat, rows, N, ld_R, F, row_tiles, col_tiles, part};
   const int64_t grid = (int64_t)F * row_tiles * col_tiles;
   const int pi = gw::prof_begin(ctx);
   if (prec == GW_FP64)

@@ -47,9 +47,17 @@ __device__ __forceinline__ void tile_coords(int t, int& ti, int& tj) {
 }
 
 // ------------------------------------------------------------------ FP32 MFMA
-constexpr int BK32 = 16;
+// 8 waves (4 x 2), each owning a 32 x 64 slice of the 128 x 128 tile, so the
+// FP32 accumulators (32 AGPRs) and their FP64 running sums (64 VGPRs) leave
+// room for two waves per SIMD.  FAST: rows 16-byte aligned and the row
+// stride covers every tile column, so tile loads need no column guards (the
+// columns past N only feed outputs that are discarded); rows past the end are
+// clamped and zeroed with a select, keeping the loads branch-free.
+constexpr int NT32 = 512;
+constexpr int BK32 = 32;
 
-__global__ __launch_bounds__(NT, 1) void syrk_f32_kernel(SyrkArgs a) {
+template <bool FAST, bool SCALED>
+__global__ __launch_bounds__(NT32, 2) void syrk_f32_kernel(SyrkArgs a) {
   __shared__ float As[2][BK32][BM];
   __shared__ float Bs[2][BK32][BM];
 
@@ -64,61 +72,68 @@ __global__ __launch_bounds__(NT, 1) void syrk_f32_kernel(SyrkArgs a) {
   const int64_t r1 = min(r0 + a.rows_per_split, a.k_rows);
 
   const float* X = static_cast<const float*>(a.X);
-  const float* scale = a.scale ? static_cast<const float*>(a.scale) + (int64_t)m * a.k_rows : nullptr;
+  const float* scale = SCALED ? static_cast<const float*>(a.scale) + (int64_t)m * a.k_rows : nullptr;
   const float csc = (float)a.cscale;
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wy = wave >> 1, wx = wave & 1;
-  const int lrow = tid >> 5, lcol = (tid & 31) * 4;   // loader: rows lrow, lrow+8
+  const int wy = wave >> 1, wx = wave & 1;            // rows wy*32, cols wx*64
+  const int lrow = tid >> 5, lcol = (tid & 31) * 4;   // loader rows lrow, lrow + 16
 
-  f32x16 acc[2][2];
-  double acc64[2][2][16];
+  f32x16 acc[2];
+  double acc64[2][16];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) { acc[i][j][r] = 0.f; acc64[i][j][r] = 0.0; }
-    }
+    for (int r = 0; r < 16; ++r) { acc[j][r] = 0.f; acc64[j][r] = 0.0; }
 
+  // Tile loads only issue the global reads; the scale and the row mask are
+  // applied when the registers are written to LDS after the MFMA block, so
+  // the reads stay in flight behind the block.
   float4 ra[2], rb[2];
+  float rs[2], rm[2];
   auto gload = [&](int64_t kb) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int64_t r = kb + lrow + 8 * h;
-      float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
-      if (r < r1) {
-        const float sc = scale ? scale[r] : csc;
-        const int64_t rb = r * a.ld;
-        const float* row = X + rb;
-        const int pa = p0 + lcol, pb = q0 + lcol;
-        if (pa + 3 < a.N && ((rb + pa) & 3) == 0) {
-          va = *reinterpret_cast<const float4*>(row + pa);
-        } else {
+      const int64_t r = kb + lrow + 16 * h;
+      if (FAST) {
+        const bool ok = r < r1;
+        const int64_t rr = ok ? r : r1 - 1;
+        if (SCALED) rs[h] = scale[rr]; else rs[h] = csc;
+        rm[h] = ok ? 1.f : 0.f;
+        const float* row = X + rr * a.ld;
+        ra[h] = *reinterpret_cast<const float4*>(row + p0 + lcol);
+        rb[h] = *reinterpret_cast<const float4*>(row + q0 + lcol);
+      } else {
+        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+        rs[h] = 0.f;
+        rm[h] = 0.f;
+        if (r < r1) {
+          if (SCALED) rs[h] = scale[r]; else rs[h] = csc;
+          rm[h] = 1.f;
+          const float* row = X + r * a.ld;
+          const int pa = p0 + lcol, pb = q0 + lcol;
           if (pa + 0 < a.N) va.x = row[pa + 0];
           if (pa + 1 < a.N) va.y = row[pa + 1];
           if (pa + 2 < a.N) va.z = row[pa + 2];
           if (pa + 3 < a.N) va.w = row[pa + 3];
-        }
-        if (pb + 3 < a.N && ((rb + pb) & 3) == 0) {
-          vb = *reinterpret_cast<const float4*>(row + pb);
-        } else {
           if (pb + 0 < a.N) vb.x = row[pb + 0];
           if (pb + 1 < a.N) vb.y = row[pb + 1];
           if (pb + 2 < a.N) vb.z = row[pb + 2];
           if (pb + 3 < a.N) vb.w = row[pb + 3];
         }
-        va.x *= sc; va.y *= sc; va.z *= sc; va.w *= sc;
+        ra[h] = va;
+        rb[h] = vb;
       }
-      ra[h] = va;
-      rb[h] = vb;
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      *reinterpret_cast<float4*>(&As[buf][lrow + 8 * h][lcol]) = ra[h];
-      *reinterpret_cast<float4*>(&Bs[buf][lrow + 8 * h][lcol]) = rb[h];
+      const float sa = rs[h] * rm[h], sb = rm[h];
+      *reinterpret_cast<float4*>(&As[buf][lrow + 16 * h][lcol]) =
+          make_float4(ra[h].x * sa, ra[h].y * sa, ra[h].z * sa, ra[h].w * sa);
+      *reinterpret_cast<float4*>(&Bs[buf][lrow + 16 * h][lcol]) =
+          make_float4(rb[h].x * sb, rb[h].y * sb, rb[h].z * sb, rb[h].w * sb);
     }
   };
 
@@ -129,47 +144,52 @@ __global__ __launch_bounds__(NT, 1) void syrk_f32_kernel(SyrkArgs a) {
     sstore(0);
   }
   __syncthreads();
+  const int arow = wy * 32 + (lane & 31);
+  const int bcol = wx * 64 + (lane & 31);
+  const int ksub = lane >> 5;
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
     if (it + 1 < nk) gload(r0 + (int64_t)(it + 1) * BK32);
+    float a_c = As[cur][ksub][arow];
+    float b0_c = Bs[cur][ksub][bcol];
+    float b1_c = Bs[cur][ksub][bcol + 32];
 #pragma unroll
     for (int kk = 0; kk < BK32 / 2; ++kk) {
-      const int kr = kk * 2 + (lane >> 5);
-      const float a0 = As[cur][kr][wy * 64 + (lane & 31)];
-      const float a1 = As[cur][kr][wy * 64 + 32 + (lane & 31)];
-      const float b0 = Bs[cur][kr][wx * 64 + (lane & 31)];
-      const float b1 = Bs[cur][kr][wx * 64 + 32 + (lane & 31)];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      float a_n = 0.f, b0_n = 0.f, b1_n = 0.f;
+      if (kk + 1 < BK32 / 2) {
+        const int kr = 2 * (kk + 1) + ksub;
+        a_n = As[cur][kr][arow];
+        b0_n = Bs[cur][kr][bcol];
+        b1_n = Bs[cur][kr][bcol + 32];
+      }
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_c, b0_c, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_c, b1_c, acc[1], 0, 0, 0);
+      a_c = a_n;
+      b0_c = b0_n;
+      b1_c = b1_n;
     }
     if (it + 1 < nk) sstore(cur ^ 1);
     if ((it + 1) % FLUSH_STAGES == 0 || it + 1 == nk) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            acc64[i][j][r] += (double)acc[i][j][r];
-            acc[i][j][r] = 0.f;
-          }
+        for (int r = 0; r < 16; ++r) {
+          acc64[j][r] += (double)acc[j][r];
+          acc[j][r] = 0.f;
+        }
     }
     __syncthreads();
   }
 
   double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = wx * 64 + j * 32 + (lane & 31);
-        out[row * BM + col] = acc64[i][j][r];
-      }
+    for (int r = 0; r < 16; ++r) {
+      const int row = wy * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int col = wx * 64 + j * 32 + (lane & 31);
+      out[row * BM + col] = acc64[j][r];
+    }
 }
 
 // ------------------------------------------------------------------ FP64 MFMA
@@ -370,7 +390,7 @@ static int choose_splits(int64_t k_rows, int64_t units) {
 
 gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_rows,
                       int N, int64_t ld, int L, const void* scale, double cscale,
-                      double* out, int accumulate) {
+                      double* out, int accumulate, const char* prof_name) {
   if (prec == GW_BF16X3) return fail(ctx, GW_EUNSUPPORTED, "BF16x3 SYRK not available");
   const int T = (N + BM - 1) / BM;
   const int n_tiles = T * (T + 1) / 2;
@@ -384,14 +404,19 @@ gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_ro
   SyrkArgs a{X, k_rows, N, ld, L, scale, cscale, T, n_tiles, S, rps, part};
   const int64_t grid = (int64_t)S * L * n_tiles;
   const int pi = prof_begin(ctx);
-  if (prec == GW_FP64)
+  if (prec == GW_FP64) {
     hipLaunchKernelGGL(syrk_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
-  else
-    hipLaunchKernelGGL(syrk_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
+  } else {
+    const bool fast = (ld % 4 == 0) && ld >= (int64_t)T * BM &&
+                      (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    auto kern = fast ? (scale ? syrk_f32_kernel<true, true> : syrk_f32_kernel<true, false>)
+                     : (scale ? syrk_f32_kernel<false, true> : syrk_f32_kernel<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT32), 0, ctx->stream, a);
+  }
   // algorithmic work: L lower-triangle products of 2 k flops each; X read
   // once, the triangle written once
   const double esz = prec == GW_FP64 ? 8.0 : 4.0;
-  prof_end(ctx, pi, prec == GW_FP64 ? "syrk_f64" : "syrk_f32",
+  prof_end(ctx, pi, prof_name,
            (double)L * N * (N + 1.0) * (double)k_rows,
            (double)k_rows * N * esz + (double)L * N * (N + 1.0) / 2.0 * 8.0);
   GW_TRY(launch_check(ctx, "syrk kernel"));
@@ -414,8 +439,8 @@ extern "C" gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_n
                                           int n_lt, const double* x_lt,
                                           const double* w_lt, int n_i, int n_virt,
                                           const double* eps_i, const double* eps_a,
-                                          const void* R_chunk, int accumulate,
-                                          int finalize, double* M) {
+                                          const void* R_chunk, int64_t ld_R,
+                                          int accumulate, int finalize, double* M) {
   if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_polarizability_lt: ctx is NULL");
   gw::clear_error(ctx);
   GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
@@ -427,6 +452,8 @@ extern "C" gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_n
              n_naf, n_lt, n_i, n_virt);
   GW_REQUIRE(ctx, x_lt && w_lt && M && eps_a && (n_i == 0 || (eps_i && R_chunk)),
              "gw_polarizability_lt: NULL argument");
+  if (ld_R == 0) ld_R = n_naf;
+  GW_REQUIRE(ctx, ld_R >= n_naf, "gw_polarizability_lt: ld_R < n_naf");
   GW_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t k = (int64_t)n_i * n_virt;
   const double* dx = gw::stage_t(ctx, x_lt, n_lt);
@@ -441,7 +468,8 @@ extern "C" gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_n
     if (!scale) return GW_ENOMEM;
     GW_TRY(gw::lt_scale_launch(ctx, prec, n_lt, dx, dw, n_i, n_virt, dei, dea, scale));
   }
-  GW_TRY(gw::syrk_launch(ctx, prec, R_chunk, k, n_naf, n_naf, n_lt, scale, 1.0, M, accumulate));
+  GW_TRY(gw::syrk_launch(ctx, prec, R_chunk, k, n_naf, ld_R, n_lt, scale, 1.0, M, accumulate,
+                         prec == GW_FP64 ? "chi_syrk_f64" : "chi_syrk_f32"));
   if (finalize) GW_TRY(gw::mirror_lower(ctx, M, n_lt, n_naf));
   return GW_OK;
 }

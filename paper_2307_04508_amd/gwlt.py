@@ -61,12 +61,12 @@ _sig = {
     "gw_minimax_inverse": [c_int, c_dbl, P_DBL, P_DBL, P_DBL, P_DBL, P_DBL],
     "gw_naf_compress": [c_vp, c_int, c_int, c_i64, c_vp, c_i64, c_vp, c_vp, c_int, c_int,
                         c_dbl, c_int, P_INT, c_vp, P_DBL],
-    "gw_naf_apply": [c_vp, c_int, c_int, c_int, c_vp, c_i64, c_vp, c_vp],
+    "gw_naf_apply": [c_vp, c_int, c_int, c_int, c_vp, c_i64, c_vp, c_vp, c_i64],
     "gw_polarizability_lt": [c_vp, c_int, c_int, c_int, P_DBL, P_DBL, c_int, c_int, P_DBL,
-                             P_DBL, c_vp, c_int, c_int, c_vp],
+                             P_DBL, c_vp, c_i64, c_int, c_int, c_vp],
     "gw_screen": [c_vp, c_int, c_int, c_int, P_DBL, c_vp, c_int, P_DBL, c_vp],
-    "gw_sigma_diag": [c_vp, c_int, c_int, c_int, c_int, P_DBL, c_dbl, c_vp, c_int, P_DBL,
-                      P_DBL, c_vp, c_int, P_DBL, c_int, c_vp, c_vp],
+    "gw_sigma_diag": [c_vp, c_int, c_int, c_int, c_int, P_DBL, c_dbl, c_vp, c_i64, c_int,
+                      P_DBL, P_DBL, c_vp, c_int, P_DBL, c_int, c_vp, c_vp],
     "gw_qp_solve": [c_vp, c_int, P_DBL, P_DBL, c_dbl, c_int, P_DBL, c_vp, c_dbl, c_dbl, c_int,
                     P_DBL, P_DBL, P_INT],
     "gw_g0w0": [c_vp, c_int, ctypes.POINTER(GwParams), P_DBL, P_INT, P_DBL, c_vp, c_vp, c_vp,
@@ -111,11 +111,19 @@ def _ip(a):
     return a.ctypes.data_as(P_INT) if a is not None else None
 
 
-def _dev(t):
-    """Device pointer of a torch tensor (or None)."""
+def _ld(t, n_cols):
+    """Row stride (elements) of a device tensor viewed as rows of n_cols."""
+    if t is None or t.dim() < 2:
+        return 0
+    return int(t.stride(-2)) if t.stride(-1) == 1 else n_cols
+
+
+def _dev(t, strided=False):
+    """Device pointer of a torch tensor (or None).  Strided tensors (padded
+    rows) are accepted where the C call takes a row stride."""
     if t is None:
         return None
-    if not t.is_cuda or not t.is_contiguous():
+    if not t.is_cuda or (not strided and not t.is_contiguous()):
         raise ValueError("device arguments must be contiguous GPU tensors")
     return ctypes.c_void_p(t.data_ptr())
 
@@ -212,8 +220,9 @@ def gw_naf_compress(ctx, prec, n_aux, R_oo, R_ov, K, accumulate, finalize, eps_n
 
 def gw_naf_apply(ctx, prec, n_aux, n_naf, U, R_in, R_out):
     n_rows = R_in.numel() // n_aux
+    ld = R_out.shape[-1] if R_out.dim() >= 2 else n_naf
     _check(_lib.gw_naf_apply(ctx.handle, _prec(prec), n_aux, n_naf, _dev(U), n_rows,
-                             _dev(R_in), _dev(R_out)), ctx)
+                             _dev(R_in), _dev(R_out), ld), ctx)
 
 
 def gw_polarizability_lt(ctx, prec, n_naf, x_lt, w_lt, n_i, n_virt, eps_i, eps_a, R_chunk,
@@ -221,8 +230,9 @@ def gw_polarizability_lt(ctx, prec, n_naf, x_lt, w_lt, n_i, n_virt, eps_i, eps_a
     x, w = _host(x_lt), _host(w_lt)
     ei, ea = _host(eps_i), _host(eps_a)
     _check(_lib.gw_polarizability_lt(ctx.handle, _prec(prec), n_naf, len(x), _dp(x), _dp(w),
-                                     n_i, n_virt, _dp(ei), _dp(ea), _dev(R_chunk),
-                                     int(accumulate), int(finalize), _dev(M)), ctx)
+                                     n_i, n_virt, _dp(ei), _dp(ea), _dev(R_chunk, True),
+                                     _ld(R_chunk, n_naf), int(accumulate), int(finalize),
+                                     _dev(M)), ctx)
 
 
 def gw_screen(ctx, prec, n_naf, x_lt, M, omega, W_hat):
@@ -235,8 +245,9 @@ def gw_sigma_diag(ctx, prec, n_naf, n_qp, n_mo, eps_mo, eps_F, R_qp, omega, w_om
                   omega_pade, accumulate, sigma_iw, W_nm=None):
     e, om, wt, op = _host(eps_mo), _host(omega), _host(w_omega), _host(omega_pade)
     _check(_lib.gw_sigma_diag(ctx.handle, _prec(prec), n_naf, n_qp, n_mo, _dp(e), float(eps_F),
-                              _dev(R_qp), len(om), _dp(om), _dp(wt), _dev(W_hat), len(op),
-                              _dp(op), int(accumulate), _dev(sigma_iw), _dev(W_nm)), ctx)
+                              _dev(R_qp, True), _ld(R_qp, n_naf), len(om), _dp(om), _dp(wt),
+                              _dev(W_hat), len(op), _dp(op), int(accumulate), _dev(sigma_iw),
+                              _dev(W_nm)), ctx)
 
 
 def gw_qp_solve(ctx, eps_n, static_n, eps_F, omega_pade, sigma_iw, eta, tol=1e-6,

@@ -81,6 +81,28 @@ def test_polarizability_lt_matches_oracle(gw, ctx, prec, tol, shape):
         assert rel_fro(Mh[m], ref[m]) < tol, (m, rel_fro(Mh[m], ref[m]))
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("fp64", 1e-12)])
+@pytest.mark.parametrize("shape", [(13, 389, 300, 384), (3, 7, 129, 256), (5, 50, 256, 256)])
+def test_polarizability_padded_rows(gw, ctx, prec, tol, shape):
+    """Rows padded to whole 128-column tiles take the unguarded load path;
+    the pad holds garbage that must not reach the result."""
+    o, v, N, ld = shape
+    _say(f"polarizability padded {prec} o={o} v={v} N={N} ld={ld}")
+    eps_i, eps_a, R, x, w = _lt_case(13, o, v, N, 3)
+    d = (eps_a[None, :] - eps_i[:, None]).ravel()
+    ref = rpa.m_lt(R, d, x, w)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Rp = torch.full((o * v, ld), 1e30, dtype=dt, device="cuda")
+    Rp[:, :N] = dev(R, prec)
+    M = torch.zeros((3, N, N), dtype=torch.float64, device="cuda")
+    gw.gw_polarizability_lt(ctx, prec, N, x, w, o, v, eps_i, eps_a, Rp[:, :N], 0, 1, M)
+    gw.gw_sync(ctx)
+    Mh = M.cpu().numpy()
+    assert np.all(np.isfinite(Mh))
+    for m in range(3):
+        assert rel_fro(Mh[m], ref[m]) < tol
+
+
 def test_polarizability_chunks_accumulate(gw, ctx):
     o, v, N = 10, 211, 140
     eps_i, eps_a, R, x, w = _lt_case(5, o, v, N, 3)
@@ -179,6 +201,23 @@ def test_sigma_diag_matches_oracle(gw, ctx, tiny_problem, tiny_sos, prec, tol):
     assert np.max(np.abs(S - S_ref)) < tol * np.max(np.abs(S_ref)) * 10
 
 
+def test_sigma_diag_padded_rows(gw, ctx, tiny_problem, tiny_sos):
+    p, r = tiny_problem, tiny_sos
+    c = p.cfg
+    What = rpa.screen(r.Pi)
+    eps_m = p.eps[c.n_fc:]
+    Q, Mo, N = r.Rt_qp.shape
+    W_ref = rpa.w_diag(r.Rt_qp, What)
+    Rp = torch.full((Q, Mo, 256), 1e30, dtype=torch.float32, device="cuda")
+    Rp[..., :N] = dev(r.Rt_qp, "fp32")
+    sig = torch.zeros((Q, len(r.omega_pade), 2), dtype=torch.float64, device="cuda")
+    Wnm = torch.zeros((len(r.omega), Q, Mo), dtype=torch.float64, device="cuda")
+    gw.gw_sigma_diag(ctx, "fp32", N, Q, Mo, eps_m, r.eps_f, Rp[..., :N], r.omega, r.w_omega,
+                     dev(What, "fp32"), r.omega_pade, 0, sig, Wnm)
+    gw.gw_sync(ctx)
+    assert rel_fro(Wnm.cpu().numpy(), W_ref) < 2e-6
+
+
 def test_sigma_diag_frequency_batches_accumulate(gw, ctx, tiny_problem, tiny_sos):
     p, r = tiny_problem, tiny_sos
     c = p.cfg
@@ -258,7 +297,7 @@ def test_naf_matches_oracle(gw, ctx, tiny_problem, prec):
     Kl = np.tril(K.cpu().numpy())
     Kg = Kl + np.tril(Kl, -1).T
     dK = np.linalg.norm(Kg - K_ref)
-    assert dK < (1e-13 if prec == "fp64" else 1e-7) * np.linalg.norm(K_ref)
+    assert dK < (1e-13 if prec == "fp64" else 1e-6) * np.linalg.norm(K_ref)
     K.zero_()
     n, ev = gw.gw_naf_compress(ctx, prec, A, dev(p.R_oo, prec), dev(p.R_ov, prec), K, 0, 1,
                                eps_cut, 0, U)
@@ -279,6 +318,13 @@ def test_naf_matches_oracle(gw, ctx, tiny_problem, prec):
     Ro = Rout.double().cpu().numpy()
     G, G_ref = Ro @ Ro.T, (R_ov @ U_ref) @ (R_ov @ U_ref).T
     assert rel_fro(G, G_ref) < (1e-10 if prec == "fp64" else 1e-4)
+    # padded output rows: the pad columns are zeroed
+    ldo = 128 * ((n + 127) // 128)
+    Rpad = torch.full((p.R_ov.shape[0], ldo), 7.0, dtype=Rout.dtype, device="cuda")
+    gw.gw_naf_apply(ctx, prec, A, n, U, dev(p.R_ov, prec), Rpad)
+    gw.gw_sync(ctx)
+    assert torch.all(Rpad[:, n:] == 0)
+    assert torch.equal(Rpad[:, :n], Rout)
     # max_keep cap
     K.zero_()
     n2, _ = gw.gw_naf_compress(ctx, prec, A, dev(p.R_oo, prec), dev(p.R_ov, prec), K, 0, 1,
