@@ -75,7 +75,7 @@ def test_argument_errors_are_status_codes():
     with pytest.raises(gwlt.GwError):
         gwlt.gw_prepare(3, 3, 5, np.zeros(8), 0.0)        # n_fc == n_occ
     lib = gwlt._lib
-    assert lib.gw_polarizability_lt(None, 0, 1, 1, None, None, 0, 1, None, None, None, 0, 0,
+    assert lib.gw_polarizability_lt(None, 0, 1, 1, None, None, 0, 1, None, None, None, 0, 0, 0,
                                     None) == gwlt.GW_EINVAL
     assert lib.gw_screen(None, 0, 1, 1, None, None, 1, None, None) == gwlt.GW_EINVAL
     assert lib.gw_sync(None) == gwlt.GW_EINVAL
