@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="steps of the FP64 path timed for comparison (0 = skip)")
+    ap.add_argument("--bf16x3-steps", type=int, default=3,
+                    help="steps of the BF16x3 path timed for comparison (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -147,6 +149,29 @@ def main():
                     "traffic": None, "avg_ms": round(chi["avg_ms"], 4),
                     "flops_per_launch": chi["flops_per_launch"]}
 
+    bf16 = None
+    if args.bf16x3_steps > 0 and args.prec == "fp32":
+        step("bf16x3", R)
+        gw.gw_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.bf16x3_steps):
+            Eb, _, Sb, _, _ = step("bf16x3", R)
+        torch.cuda.synchronize()
+        wb = (time.perf_counter() - t0) / args.bf16x3_steps
+        chib = kernel_rate(gw, ctx, "chi_syrk_bf16x3")
+        bwbb = kernel_rate(gw, ctx, "bwb_bf16x3")
+        gw.gw_profile_enable(ctx, False)
+        bf16 = {"wall_s": wb, "qp_diff_vs_fp32_meV": float(np.max(np.abs(Eb - E)) * HARTREE_MEV),
+                "status": Sb.tolist()}
+        for key, kr in (("chi", chib), ("sigma_contraction", bwbb)):
+            if kr:
+                bf16[key] = {"avg_ms": round(kr["avg_ms"], 4),
+                             "tflops_algorithmic": round(kr["tflops"], 3),
+                             "frac_of_bf16_peak_executed": round(3 * kr["tflops"] / 2500.0, 4),
+                             "frac_of_fp32_peak": round(kr["tflops"] / 157.3, 4)}
+        log(f"bf16x3 path: {wb * 1e3:.1f} ms/step")
+
     fp64 = None
     if args.fp64_steps > 0 and args.prec != "fp64":
         del R
@@ -204,6 +229,7 @@ def main():
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
         "lt_err_norm": st.lt_err_norm,
         "fp64": fp64,
+        "bf16x3": bf16,
         "qp_err": qp_err,
         "cpu_baseline": cpu,
     }

@@ -277,6 +277,144 @@ __global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ BF16x3
+// Same contraction as hi*hi + hi*lo + lo*hi BF16 MFMA products
+// (v_mfma_f32_32x32x16_bf16), FP32 accumulation.  W^_j is symmetric, so the
+// B operand W^[p][q] is read as row q of W^ (contiguous along p = k) and
+// both tiles stage into k-contiguous LDS rows without a transpose; the split
+// into hi/lo happens in the LDS store.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int BKB = 32;
+constexpr int LDB = BKB + 8;
+
+__device__ __forceinline__ void split4(const float4 v, bf16x4& hi, bf16x4& lo) {
+  const float x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+__device__ __forceinline__ float4 load4_guarded(const float* base, int64_t off, int k, int n) {
+  const float* p = base + off;
+  if (k + 3 < n && (off & 3) == 0) return *reinterpret_cast<const float4*>(p);
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (k + 0 < n) v.x = p[0];
+  if (k + 1 < n) v.y = p[1];
+  if (k + 2 < n) v.z = p[2];
+  if (k + 3 < n) v.w = p[3];
+  return v;
+}
+
+__global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a) {
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][LDB];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][LDB];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BM][LDB];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BM][LDB];
+  int j, ct, rt;
+  decode(a, j, ct, rt);
+  const float* R = static_cast<const float*>(a.R);
+  const float* W = static_cast<const float*>(a.W) + (int64_t)j * a.N * a.N;
+  const int64_t row0 = (int64_t)rt * BM;
+  const int col0 = ct * BM;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][jj][r] = 0.f;
+
+  // loader: rows (tid >> 3) + 32 h, k offset (tid & 7) * 4, for both tiles
+  float4 ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int lr = (tid >> 3) + 32 * h;
+      const int k = k0 + (tid & 7) * 4;
+      const int64_t row = row0 + lr;
+      ra[h] = row < a.rows ? load4_guarded(R, row * a.ldr + k, k, a.N)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int q = col0 + lr;
+      rb[h] = q < a.N ? load4_guarded(W, (int64_t)q * a.N + k, k, a.N)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int lr = (tid >> 3) + 32 * h, kk = (tid & 7) * 4;
+      bf16x4 hi, lo;
+      split4(ra[h], hi, lo);
+      *reinterpret_cast<bf16x4*>(&Ah[buf][lr][kk]) = hi;
+      *reinterpret_cast<bf16x4*>(&Al[buf][lr][kk]) = lo;
+      split4(rb[h], hi, lo);
+      *reinterpret_cast<bf16x4*>(&Bh[buf][lr][kk]) = hi;
+      *reinterpret_cast<bf16x4*>(&Bl[buf][lr][kk]) = lo;
+    }
+  };
+
+  const int nk = (a.N + BKB - 1) / BKB;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int kl = 8 * (lane >> 5);
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload((it + 1) * BKB);
+#pragma unroll
+    for (int ks = 0; ks < BKB; ks += 16) {
+      bf16x8 ahf[2], alf[2], bhf[2], blf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int pr = wy * 64 + i * 32 + (lane & 31);
+        const int qc = wx * 64 + i * 32 + (lane & 31);
+        ahf[i] = *reinterpret_cast<const bf16x8*>(&Ah[cur][pr][ks + kl]);
+        alf[i] = *reinterpret_cast<const bf16x8*>(&Al[cur][pr][ks + kl]);
+        bhf[i] = *reinterpret_cast<const bf16x8*>(&Bh[cur][qc][ks + kl]);
+        blf[i] = *reinterpret_cast<const bf16x8*>(&Bl[cur][qc][ks + kl]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahf[i], bhf[jj], acc[i][jj], 0, 0, 0);
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahf[i], blf[jj], acc[i][jj], 0, 0, 0);
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alf[i], bhf[jj], acc[i][jj], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  double* part = a.part + ((int64_t)j * 2 * a.col_tiles + 2 * ct + wx) * a.rows;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int lrow = wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int64_t row = row0 + lrow;
+      double sum = 0.0;
+      if (row < a.rows) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int col = col0 + wx * 64 + jj * 32 + (lane & 31);
+          if (col < a.N) sum += (double)acc[i][jj][r] * (double)R[row * a.ldr + col];
+        }
+      }
+#pragma unroll
+      for (int off = 16; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+      if ((lane & 31) == 0 && row < a.rows) part[row] = sum;
+    }
+  }
+}
+
 // W[j][row] = sum over column partials (fixed order); optional user copy.
 __global__ void w_reduce_kernel(const double* __restrict__ part, int n_part, int64_t rows,
                                 int F, double* __restrict__ W, double* __restrict__ W_user) {
@@ -350,8 +488,6 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
   gw::clear_error(ctx);
   GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
              "gw_sigma_diag: unknown precision %d", (int)prec);
-  if (prec == GW_BF16X3)
-    return gw::fail(ctx, GW_EUNSUPPORTED, "gw_sigma_diag: BF16x3 not available");
   GW_REQUIRE(ctx, n_naf >= 1 && n_qp >= 1 && n_mo >= 1 && n_w >= 1 && n_pade >= 1,
              "gw_sigma_diag: bad sizes");
   GW_REQUIRE(ctx, eps_mo && R_qp && omega && w_omega && W_hat && omega_pade && sigma_iw,
@@ -378,11 +514,13 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
   const int pi = gw::prof_begin(ctx);
   if (prec == GW_FP64)
     hipLaunchKernelGGL(bwb_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
+  else if (prec == GW_BF16X3)
+    hipLaunchKernelGGL(bwb_bf16x3_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
   else
     hipLaunchKernelGGL(bwb_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
   {
     const double esz = prec == GW_FP64 ? 8.0 : 4.0;
-    gw::prof_end(ctx, pi, prec == GW_FP64 ? "bwb_f64" : "bwb_f32",
+    gw::prof_end(ctx, pi, prec == GW_FP64 ? "bwb_f64" : (prec == GW_BF16X3 ? "bwb_bf16x3" : "bwb_f32"),
                  2.0 * F * (double)rows * N * (double)N,
                  (double)rows * N * esz + (double)F * N * (double)N * esz);
   }

@@ -192,6 +192,169 @@ __global__ __launch_bounds__(NT32, 2) void syrk_f32_kernel(SyrkArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ BF16x3
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each product is formed
+// as hi*hi + hi*lo + lo*hi on v_mfma_f32_32x32x16_bf16 (the lo*lo term,
+// ~2^-16 relative, is dropped).  The split happens in the LDS store; the LDS
+// tiles are k-contiguous ([column][row of X]) so each MFMA operand (8
+// consecutive k for one column) is one 16-byte read.  4 waves, 64 x 64 each;
+// FP32 accumulation over the split-K slice, FP64 across slices.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int NTB = 256;
+constexpr int BKB = 32;
+constexpr int LDB = BKB + 8;        // padded k stride (bf16) of an LDS row
+
+__device__ __forceinline__ void split4(const float4 v, float s, bf16x4& hi, bf16x4& lo) {
+  const float x[4] = {v.x * s, v.y * s, v.z * s, v.w * s};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+template <bool FAST, bool SCALED>
+__global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a) {
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][LDB];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][LDB];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BM][LDB];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BM][LDB];
+
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int m = (int)(lid % a.L);
+  const int t = (int)((lid / a.L) % a.n_tiles);
+  const int s = (int)(lid / ((int64_t)a.L * a.n_tiles));
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int p0 = ti * BM, q0 = tj * BM;
+  const int64_t r0 = (int64_t)s * a.rows_per_split;
+  const int64_t r1 = min(r0 + a.rows_per_split, a.k_rows);
+
+  const float* X = static_cast<const float*>(a.X);
+  const float* scale = SCALED ? static_cast<const float*>(a.scale) + (int64_t)m * a.k_rows : nullptr;
+  const float csc = (float)a.cscale;
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+  // loader: 4 consecutive rows (krow..krow+3) x 4 consecutive columns (lcol)
+  const int lcol = (tid & 31) * 4, krow = (tid >> 5) * 4;
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  float4 ra[4], rb[4];
+  float rs[4];
+  auto gload = [&](int64_t kb) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int64_t r = kb + krow + h;
+      if (FAST) {
+        const bool ok = r < r1;
+        const int64_t rr = ok ? r : r1 - 1;
+        const float sc = SCALED ? scale[rr] : csc;
+        rs[h] = ok ? sc : 0.f;
+        const float* row = X + rr * a.ld;
+        ra[h] = *reinterpret_cast<const float4*>(row + p0 + lcol);
+        rb[h] = *reinterpret_cast<const float4*>(row + q0 + lcol);
+        if (!ok) rb[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+        rs[h] = 0.f;
+        if (r < r1) {
+          rs[h] = SCALED ? scale[r] : csc;
+          const float* row = X + r * a.ld;
+          const int pa = p0 + lcol, pb = q0 + lcol;
+          if (pa + 0 < a.N) va.x = row[pa + 0];
+          if (pa + 1 < a.N) va.y = row[pa + 1];
+          if (pa + 2 < a.N) va.z = row[pa + 2];
+          if (pa + 3 < a.N) va.w = row[pa + 3];
+          if (pb + 0 < a.N) vb.x = row[pb + 0];
+          if (pb + 1 < a.N) vb.y = row[pb + 1];
+          if (pb + 2 < a.N) vb.z = row[pb + 2];
+          if (pb + 3 < a.N) vb.w = row[pb + 3];
+        }
+        ra[h] = va;
+        rb[h] = vb;
+      }
+    }
+  };
+  // registers hold 4 rows x 4 columns; LDS wants, per column, 4 consecutive rows
+  auto sstore = [&](int buf) {
+    bf16x4 ah[4], al[4], bh[4], bl[4];   // [row h] -> 4 columns
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      split4(ra[h], rs[h], ah[h], al[h]);
+      split4(rb[h], 1.f, bh[h], bl[h]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      bf16x4 v;
+      v = bf16x4{ah[0][c], ah[1][c], ah[2][c], ah[3][c]};
+      *reinterpret_cast<bf16x4*>(&Ah[buf][lcol + c][krow]) = v;
+      v = bf16x4{al[0][c], al[1][c], al[2][c], al[3][c]};
+      *reinterpret_cast<bf16x4*>(&Al[buf][lcol + c][krow]) = v;
+      v = bf16x4{bh[0][c], bh[1][c], bh[2][c], bh[3][c]};
+      *reinterpret_cast<bf16x4*>(&Bh[buf][lcol + c][krow]) = v;
+      v = bf16x4{bl[0][c], bl[1][c], bl[2][c], bl[3][c]};
+      *reinterpret_cast<bf16x4*>(&Bl[buf][lcol + c][krow]) = v;
+    }
+  };
+
+  const int nk = (int)((r1 - r0 + BKB - 1) / BKB);
+  if (nk > 0) {
+    gload(r0);
+    sstore(0);
+  }
+  __syncthreads();
+  const int kl = 8 * (lane >> 5);
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload(r0 + (int64_t)(it + 1) * BKB);
+#pragma unroll
+    for (int ks = 0; ks < BKB; ks += 16) {
+      bf16x8 ahf[2], alf[2], bhf[2], blf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int pr = wy * 64 + i * 32 + (lane & 31);
+        const int qc = wx * 64 + i * 32 + (lane & 31);
+        ahf[i] = *reinterpret_cast<const bf16x8*>(&Ah[cur][pr][ks + kl]);
+        alf[i] = *reinterpret_cast<const bf16x8*>(&Al[cur][pr][ks + kl]);
+        bhf[i] = *reinterpret_cast<const bf16x8*>(&Bh[cur][qc][ks + kl]);
+        blf[i] = *reinterpret_cast<const bf16x8*>(&Bl[cur][qc][ks + kl]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahf[i], bhf[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahf[i], blf[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alf[i], bhf[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = wx * 64 + j * 32 + (lane & 31);
+        out[row * BM + col] = (double)acc[i][j][r];
+      }
+}
+
 // ------------------------------------------------------------------ FP64 MFMA
 constexpr int BK64 = 16;
 
@@ -391,11 +554,10 @@ static int choose_splits(int64_t k_rows, int64_t units) {
 gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_rows,
                       int N, int64_t ld, int L, const void* scale, double cscale,
                       double* out, int accumulate, const char* prof_name) {
-  if (prec == GW_BF16X3) return fail(ctx, GW_EUNSUPPORTED, "BF16x3 SYRK not available");
   const int T = (N + BM - 1) / BM;
   const int n_tiles = T * (T + 1) / 2;
   const int S = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
-  const int64_t align = prec == GW_FP64 ? BK64 : FLUSH_ROWS;
+  const int64_t align = prec == GW_FP64 ? BK64 : (prec == GW_BF16X3 ? BKB : FLUSH_ROWS);
   int64_t rps = (k_rows + S - 1) / S;
   rps = (rps + align - 1) / align * align;
   const size_t part_bytes = (size_t)S * L * n_tiles * BM * BM * sizeof(double);
@@ -404,11 +566,15 @@ gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_ro
   SyrkArgs a{X, k_rows, N, ld, L, scale, cscale, T, n_tiles, S, rps, part};
   const int64_t grid = (int64_t)S * L * n_tiles;
   const int pi = prof_begin(ctx);
+  const bool fast = prec != GW_FP64 && (ld % 4 == 0) && ld >= (int64_t)T * BM &&
+                    (reinterpret_cast<uintptr_t>(X) % 16 == 0);
   if (prec == GW_FP64) {
     hipLaunchKernelGGL(syrk_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
+  } else if (prec == GW_BF16X3) {
+    auto kern = fast ? (scale ? syrk_bf16x3_kernel<true, true> : syrk_bf16x3_kernel<true, false>)
+                     : (scale ? syrk_bf16x3_kernel<false, true> : syrk_bf16x3_kernel<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NTB), 0, ctx->stream, a);
   } else {
-    const bool fast = (ld % 4 == 0) && ld >= (int64_t)T * BM &&
-                      (reinterpret_cast<uintptr_t>(X) % 16 == 0);
     auto kern = fast ? (scale ? syrk_f32_kernel<true, true> : syrk_f32_kernel<true, false>)
                      : (scale ? syrk_f32_kernel<false, true> : syrk_f32_kernel<false, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT32), 0, ctx->stream, a);
@@ -445,8 +611,7 @@ extern "C" gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_n
   gw::clear_error(ctx);
   GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
              "gw_polarizability_lt: unknown precision %d", (int)prec);
-  if (prec == GW_BF16X3)
-    return gw::fail(ctx, GW_EUNSUPPORTED, "gw_polarizability_lt: BF16x3 not available");
+
   GW_REQUIRE(ctx, n_naf >= 1 && n_lt >= 1 && n_lt <= 32 && n_i >= 0 && n_virt >= 1,
              "gw_polarizability_lt: bad sizes (n_naf=%d n_lt=%d n_i=%d n_virt=%d)",
              n_naf, n_lt, n_i, n_virt);
@@ -469,7 +634,8 @@ extern "C" gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_n
     GW_TRY(gw::lt_scale_launch(ctx, prec, n_lt, dx, dw, n_i, n_virt, dei, dea, scale));
   }
   GW_TRY(gw::syrk_launch(ctx, prec, R_chunk, k, n_naf, ld_R, n_lt, scale, 1.0, M, accumulate,
-                         prec == GW_FP64 ? "chi_syrk_f64" : "chi_syrk_f32"));
+                         prec == GW_FP64 ? "chi_syrk_f64"
+                                         : (prec == GW_BF16X3 ? "chi_syrk_bf16x3" : "chi_syrk_f32")));
   if (finalize) GW_TRY(gw::mirror_lower(ctx, M, n_lt, n_naf));
   return GW_OK;
 }
