@@ -4,8 +4,11 @@
 // The contraction is a GEMM Y = R_qp W^_j (rows: the Q*M pairs (n, m);
 // columns: the auxiliary index) whose epilogue takes the row-wise dot
 // product of each output tile with the matching columns of R_qp, so Y never
-// reaches memory.  Each 64-column slice of a tile writes one FP64 partial
-// per row; a second kernel sums the partials in a fixed order.
+// reaches memory.  Because W^_j is symmetric, a column block J only needs
+// the rows P >= J of W^ (off-diagonal blocks counted twice), which halves
+// the work: rows * N (N + 1) flops per frequency.  Each 64-column slice of a
+// tile writes one FP64 partial per row; a second kernel sums the partials
+// in a fixed order.
 //
 //  FP32:   v_mfma_f32_32x32x2f32, operands FP32, tile 128 x 128 x 32.
 //  FP64:   v_mfma_f64_16x16x4f64, operands FP64, tile 128 x 128 x 16.
@@ -117,13 +120,19 @@ __global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a) {
     }
   };
 
-  const int nk = (a.N + BK32 - 1) / BK32;
-  gload(0);
+  // W^ is symmetric: only rows P >= col0 of W^ are needed.  The diagonal
+  // block (P in this tile's columns) counts once, every block below it twice
+  // (it stands for its mirror image too): the accumulator is halved after the
+  // diagonal block and doubled at the end (exact scalings).
+  const int kstart = col0;
+  const int nk = (a.N - kstart + BK32 - 1) / BK32;
+  constexpr int DIAG_STAGES = BM / BK32;
+  gload(kstart);
   sstore(0);
   __syncthreads();
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
-    if (it + 1 < nk) gload((it + 1) * BK32);
+    if (it + 1 < nk) gload(kstart + (it + 1) * BK32);
 #pragma unroll
     for (int kk = 0; kk < BK32 / 2; ++kk) {
       const int kr = kk * 2 + (lane >> 5);
@@ -136,8 +145,20 @@ __global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a) {
       acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if (it + 1 == DIAG_STAGES && nk > DIAG_STAGES) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 0.5f;
+    }
     if (it + 1 < nk) sstore(cur ^ 1);
     __syncthreads();
+  }
+  if (nk > DIAG_STAGES) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 2.0f;
   }
 
   // epilogue: per-row dot product with R[row][col] over this wave's 64 columns
@@ -229,13 +250,16 @@ __global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a) {
     }
   };
 
-  const int nk = (a.N + BK64 - 1) / BK64;
-  gload(0);
+  // symmetric W^: rows P >= col0 only (see the FP32 kernel)
+  const int kstart = col0;
+  const int nk = (a.N - kstart + BK64 - 1) / BK64;
+  constexpr int DIAG_STAGES = BM / BK64;
+  gload(kstart);
   sstore(0);
   __syncthreads();
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
-    if (it + 1 < nk) gload((it + 1) * BK64);
+    if (it + 1 < nk) gload(kstart + (it + 1) * BK64);
 #pragma unroll
     for (int kk = 0; kk < BK64 / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
@@ -251,8 +275,20 @@ __global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a) {
         for (int jj = 0; jj < 4; ++jj)
           acc[i][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[jj], acc[i][jj], 0, 0, 0);
     }
+    if (it + 1 == DIAG_STAGES && nk > DIAG_STAGES) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[i][jj] *= 0.5;
+    }
     if (it + 1 < nk) sstore(cur ^ 1);
     __syncthreads();
+  }
+  if (nk > DIAG_STAGES) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) acc[i][jj] *= 2.0;
   }
 
   double* part = a.part + ((int64_t)j * 2 * a.col_tiles + 2 * ct + wx) * a.rows;
@@ -360,14 +396,17 @@ __global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a) {
     }
   };
 
-  const int nk = (a.N + BKB - 1) / BKB;
-  gload(0);
+  // symmetric W^: rows P >= col0 only (see the FP32 kernel)
+  const int kstart = col0;
+  const int nk = (a.N - kstart + BKB - 1) / BKB;
+  constexpr int DIAG_STAGES = BM / BKB;
+  gload(kstart);
   sstore(0);
   __syncthreads();
   const int kl = 8 * (lane >> 5);
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
-    if (it + 1 < nk) gload((it + 1) * BKB);
+    if (it + 1 < nk) gload(kstart + (it + 1) * BKB);
 #pragma unroll
     for (int ks = 0; ks < BKB; ks += 16) {
       bf16x8 ahf[2], alf[2], bhf[2], blf[2];
@@ -389,8 +428,20 @@ __global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a) {
           acc[i][jj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alf[i], bhf[jj], acc[i][jj], 0, 0, 0);
         }
     }
+    if (it + 1 == DIAG_STAGES && nk > DIAG_STAGES) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 0.5f;
+    }
     if (it + 1 < nk) sstore(cur ^ 1);
     __syncthreads();
+  }
+  if (nk > DIAG_STAGES) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 2.0f;
   }
 
   double* part = a.part + ((int64_t)j * 2 * a.col_tiles + 2 * ct + wx) * a.rows;
@@ -520,8 +571,9 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
     hipLaunchKernelGGL(bwb_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
   {
     const double esz = prec == GW_FP64 ? 8.0 : 4.0;
+    // algorithmic work of the symmetric form: rows * N (N + 1) per frequency
     gw::prof_end(ctx, pi, prec == GW_FP64 ? "bwb_f64" : (prec == GW_BF16X3 ? "bwb_bf16x3" : "bwb_f32"),
-                 2.0 * F * (double)rows * N * (double)N,
+                 (double)F * (double)rows * N * (N + 1.0),
                  (double)rows * N * esz + (double)F * N * (double)N * esz);
   }
   GW_TRY(gw::launch_check(ctx, "bwb kernel"));

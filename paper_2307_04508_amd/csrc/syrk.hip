@@ -49,10 +49,11 @@ __device__ __forceinline__ void tile_coords(int t, int& ti, int& tj) {
 // ------------------------------------------------------------------ FP32 MFMA
 // 8 waves (4 x 2), each owning a 32 x 64 slice of the 128 x 128 tile, so the
 // FP32 accumulators (32 AGPRs) and their FP64 running sums (64 VGPRs) leave
-// room for two waves per SIMD.  FAST: rows 16-byte aligned and the row
-// stride covers every tile column, so tile loads need no column guards (the
-// columns past N only feed outputs that are discarded); rows past the end are
-// clamped and zeroed with a select, keeping the loads branch-free.
+// room for two waves per SIMD.  FAST: rows 16-byte aligned (row stride a
+// multiple of 4).  Tile loads then need no column guards: a float4 start
+// past the row end is clamped back inside the row, and lanes past column N
+// only feed outputs that are discarded.  Rows past the end are clamped and
+// zeroed with a select, keeping the loads branch-free.
 constexpr int NT32 = 512;
 constexpr int BK32 = 32;
 
@@ -101,8 +102,8 @@ __global__ __launch_bounds__(NT32, 2) void syrk_f32_kernel(SyrkArgs a) {
         if (SCALED) rs[h] = scale[rr]; else rs[h] = csc;
         rm[h] = ok ? 1.f : 0.f;
         const float* row = X + rr * a.ld;
-        ra[h] = *reinterpret_cast<const float4*>(row + p0 + lcol);
-        rb[h] = *reinterpret_cast<const float4*>(row + q0 + lcol);
+        ra[h] = *reinterpret_cast<const float4*>(row + min(p0 + lcol, (int)a.ld - 4));
+        rb[h] = *reinterpret_cast<const float4*>(row + min(q0 + lcol, (int)a.ld - 4));
       } else {
         float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
         rs[h] = 0.f;
@@ -261,8 +262,8 @@ __global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a) {
         const float sc = SCALED ? scale[rr] : csc;
         rs[h] = ok ? sc : 0.f;
         const float* row = X + rr * a.ld;
-        ra[h] = *reinterpret_cast<const float4*>(row + p0 + lcol);
-        rb[h] = *reinterpret_cast<const float4*>(row + q0 + lcol);
+        ra[h] = *reinterpret_cast<const float4*>(row + min(p0 + lcol, (int)a.ld - 4));
+        rb[h] = *reinterpret_cast<const float4*>(row + min(q0 + lcol, (int)a.ld - 4));
         if (!ok) rb[h] = make_float4(0.f, 0.f, 0.f, 0.f);
       } else {
         float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
@@ -566,7 +567,7 @@ gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_ro
   SyrkArgs a{X, k_rows, N, ld, L, scale, cscale, T, n_tiles, S, rps, part};
   const int64_t grid = (int64_t)S * L * n_tiles;
   const int pi = prof_begin(ctx);
-  const bool fast = prec != GW_FP64 && (ld % 4 == 0) && ld >= (int64_t)T * BM &&
+  const bool fast = prec != GW_FP64 && (ld % 4 == 0) && ld >= 4 &&
                     (reinterpret_cast<uintptr_t>(X) % 16 == 0);
   if (prec == GW_FP64) {
     hipLaunchKernelGGL(syrk_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);

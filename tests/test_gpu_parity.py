@@ -201,6 +201,27 @@ def test_sigma_diag_matches_oracle(gw, ctx, tiny_problem, tiny_sos, prec, tol):
     assert np.max(np.abs(S - S_ref)) < tol * np.max(np.abs(S_ref)) * 10
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("N", [333, 128, 257])
+def test_sigma_diag_random_ragged(gw, ctx, prec, tol, N):
+    """Random rows and a random symmetric negative-definite W^ whose size
+    leaves ragged column blocks; W_nm against the direct quadratic form."""
+    rng = np.random.default_rng(N)
+    Q, Mo, F = 3, 70, 2
+    R = rng.standard_normal((Q, Mo, N)) / np.sqrt(N)
+    X = rng.standard_normal((F, N, N)) / np.sqrt(N)
+    What = -np.einsum("fij,fkj->fik", X, X) / 4.0
+    W_ref = rpa.w_diag(R, What)
+    om = np.array([0.1, 1.0])
+    sig = torch.zeros((Q, 4, 2), dtype=torch.float64, device="cuda")
+    Wnm = torch.zeros((F, Q, Mo), dtype=torch.float64, device="cuda")
+    gw.gw_sigma_diag(ctx, prec, N, Q, Mo, np.linspace(-1, 1, Mo), 0.05, dev(R, prec), om,
+                     np.array([0.5, 0.5]), dev(What, prec), np.array([0.1, 0.2, 0.3, 0.4]), 0,
+                     sig, Wnm)
+    gw.gw_sync(ctx)
+    assert rel_fro(Wnm.cpu().numpy(), W_ref) < tol
+
+
 def test_sigma_diag_padded_rows(gw, ctx, tiny_problem, tiny_sos):
     p, r = tiny_problem, tiny_sos
     c = p.cfg
