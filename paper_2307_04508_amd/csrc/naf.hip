@@ -53,11 +53,17 @@ struct GemmArgs {
 
 constexpr int BK = 32;
 constexpr int LDK = BK + 1;
+constexpr int NT8 = 512;
 
-// C[r][c] = sum_k A[r][k] B[c][k] on FP32 MFMA, FP64 flush every 256 k.
-__global__ __launch_bounds__(NT, 1) void nt_gemm_f32_kernel(GemmArgs g) {
-  __shared__ float As[BM][LDK];
-  __shared__ float Bs[BM][LDK];
+// C[r][c] = sum_k A[r][k] B[c][k] on FP32 MFMA (32x32x2), FP64 running sums
+// every 256 k.  8 waves of 32 x 64 per 128 x 128 tile; double-buffered LDS
+// tiles stored k-contiguous ([row][k], padded), filled from registers loaded
+// one stage ahead and consumed only at the LDS store, so the global reads
+// stay in flight behind the MFMA block.  Rows past the end and k past K load
+// as zeros (k is the contraction index, so the tail must be exact zeros).
+__global__ __launch_bounds__(NT8, 2) void nt_gemm_f32_kernel(GemmArgs g) {
+  __shared__ float As[2][BM][LDK];
+  __shared__ float Bs[2][BM][LDK];
   const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
   const int ct = (int)(lid % g.col_tiles);
   const int rt = (int)(lid / g.col_tiles);
@@ -65,69 +71,114 @@ __global__ __launch_bounds__(NT, 1) void nt_gemm_f32_kernel(GemmArgs g) {
   const int col0 = ct * BM;
   const float* A = static_cast<const float*>(g.A);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wy = wave >> 1, wx = wave & 1;
-  f32x16 acc[2][2];
-  double acc64[2][2][16];
+  const int wy = wave >> 1, wx = wave & 1;            // rows wy*32, cols wx*64
+  f32x16 acc[2];
+  double acc64[2][16];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int r = 0; r < 16; ++r) { acc[j][r] = 0.f; acc64[j][r] = 0.0; }
+
+  // A loader: rows (tid >> 3) + 64 h, k offset (tid & 7) * 4 (float4)
+  // B loader: rows (tid >> 4) + 32 h, k offset (tid & 15) * 2 (double2)
+  const bool vecA = (g.K % 4 == 0), vecB = (g.K % 2 == 0);
+  float4 ra[2];
+  double2 rb[4];
+  auto gload = [&](int k0) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) { acc[i][j][r] = 0.f; acc64[i][j][r] = 0.0; }
-  const int nk = (g.K + BK - 1) / BK;
-  for (int it = 0; it < nk; ++it) {
-    const int k0 = it * BK;
-    // 128 rows x 32 k per operand; thread: rows (tid >> 3) + 32 h, k (tid & 7) * 4
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r = row0 + (tid >> 3) + 64 * h;
+      const int k = k0 + (tid & 7) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r < g.rows) {
+        const float* p = A + r * g.K;
+        if (vecA && k + 3 < g.K) {
+          v = *reinterpret_cast<const float4*>(p + k);
+        } else {
+          if (k + 0 < g.K) v.x = p[k + 0];
+          if (k + 1 < g.K) v.y = p[k + 1];
+          if (k + 2 < g.K) v.z = p[k + 2];
+          if (k + 3 < g.K) v.w = p[k + 3];
+        }
+      }
+      ra[h] = v;
+    }
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-      const int r = (tid >> 3) + 32 * h, k = k0 + (tid & 7) * 4;
-      const int64_t ar = row0 + r;
-      const int bc = col0 + r;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        As[r][(tid & 7) * 4 + e] = (ar < g.rows && k + e < g.K) ? A[ar * g.K + k + e] : 0.f;
-        Bs[r][(tid & 7) * 4 + e] =
-            (bc < g.ncols && k + e < g.K) ? (float)g.B[(int64_t)bc * g.K + k + e] : 0.f;
+      const int c = col0 + (tid >> 4) + 32 * h;
+      const int k = k0 + (tid & 15) * 2;
+      double2 v = make_double2(0.0, 0.0);
+      if (c < g.ncols) {
+        const double* p = g.B + (int64_t)c * g.K;
+        if (vecB && k + 1 < g.K) {
+          v = *reinterpret_cast<const double2*>(p + k);
+        } else {
+          if (k + 0 < g.K) v.x = p[k + 0];
+          if (k + 1 < g.K) v.y = p[k + 1];
+        }
       }
+      rb[h] = v;
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = (tid >> 3) + 64 * h, k = (tid & 7) * 4;
+      As[buf][r][k + 0] = ra[h].x;
+      As[buf][r][k + 1] = ra[h].y;
+      As[buf][r][k + 2] = ra[h].z;
+      As[buf][r][k + 3] = ra[h].w;
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int c = (tid >> 4) + 32 * h, k = (tid & 15) * 2;
+      Bs[buf][c][k + 0] = (float)rb[h].x;
+      Bs[buf][c][k + 1] = (float)rb[h].y;
+    }
+  };
+
+  const int nk = (g.K + BK - 1) / BK;
+  constexpr int FLUSH_STAGES = 256 / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int arow = wy * 32 + (lane & 31);
+  const int bcol = wx * 64 + (lane & 31);
+  const int ksub = lane >> 5;
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload((it + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 2; ++kk) {
-      const int kr = kk * 2 + (lane >> 5);
-      const float a0 = As[wy * 64 + (lane & 31)][kr];
-      const float a1 = As[wy * 64 + 32 + (lane & 31)][kr];
-      const float b0 = Bs[wx * 64 + (lane & 31)][kr];
-      const float b1 = Bs[wx * 64 + 32 + (lane & 31)][kr];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      const int kr = 2 * kk + ksub;
+      const float a0 = As[cur][arow][kr];
+      const float b0 = Bs[cur][bcol][kr];
+      const float b1 = Bs[cur][bcol + 32][kr];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[1], 0, 0, 0);
     }
-    if ((it + 1) % 8 == 0 || it + 1 == nk) {
+    if (it + 1 < nk) sstore(cur ^ 1);
+    if ((it + 1) % FLUSH_STAGES == 0 || it + 1 == nk) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            acc64[i][j][r] += (double)acc[i][j][r];
-            acc[i][j][r] = 0.f;
-          }
+        for (int r = 0; r < 16; ++r) {
+          acc64[j][r] += (double)acc[j][r];
+          acc[j][r] = 0.f;
+        }
     }
     __syncthreads();
   }
   float* C = static_cast<float*>(g.C);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t row = row0 + wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = col0 + wx * 64 + j * 32 + (lane & 31);
-        if (row < g.rows && col < g.ldc)
-          C[row * g.ldc + col] = col < g.ncols ? (float)acc64[i][j][r] : 0.f;
-      }
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = row0 + wy * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int col = col0 + wx * 64 + j * 32 + (lane & 31);
+      if (row < g.rows && col < g.ldc)
+        C[row * g.ldc + col] = col < g.ncols ? (float)acc64[j][r] : 0.f;
+    }
 }
 
 constexpr int BK64 = 16;
@@ -291,7 +342,7 @@ extern "C" gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int 
   if (prec == GW_FP64)
     hipLaunchKernelGGL(nt_gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, g);
   else
-    hipLaunchKernelGGL(nt_gemm_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, g);
+    hipLaunchKernelGGL(nt_gemm_f32_kernel, dim3((unsigned)grid), dim3(NT8), 0, ctx->stream, g);
   gw::prof_end(ctx, pi, prec == GW_FP64 ? "naf_gemm_f64" : "naf_gemm_f32",
                2.0 * (double)n_rows * n_aux * (double)n_naf, 0.0);
   return gw::launch_check(ctx, "naf transform");

@@ -70,55 +70,76 @@ __global__ void gather_panel_kernel(const double* __restrict__ A, int N, int F, 
   }
 }
 
-// One workgroup per frequency: sweep the bw x bw pivot block in LDS; store
-// D^-1 (zero-padded to 64 x 64).
-__global__ __launch_bounds__(256) void pivot_kernel(const double* __restrict__ C, int N,
-                                                    int kb, int bw,
-                                                    double* __restrict__ Dinv,
-                                                    int* __restrict__ flags, int j_offset) {
-  __shared__ double D[B][B + 1];
-  __shared__ double colk[B], rowk[B];
-  __shared__ int bad;
+// One workgroup per frequency sweeps the 64 x 64 pivot block, stored in
+// registers: thread (tr, tc) owns rows 4 tr .. 4 tr + 3 and columns
+// 4 tc .. 4 tc + 3.  Each step the owners of pivot column k and row k publish
+// them through double-buffered LDS (one barrier per step).  A partial block
+// (bw < 64) is padded with the identity, which the sweep leaves as -1 and
+// does not couple to the valid part.  Stores D^-1 (zero-padded).
+constexpr int PIV_THREADS = 256;
+__global__ __launch_bounds__(PIV_THREADS) void pivot_kernel(const double* __restrict__ C, int N,
+                                                            int kb, int bw,
+                                                            double* __restrict__ Dinv,
+                                                            int* __restrict__ flags, int j_offset) {
+  __shared__ double colb[2][B], rowb[2][B];
   const int j = blockIdx.x;
   const double* Cj = C + (int64_t)j * N * B;
-  for (int i = threadIdx.x; i < B * B; i += blockDim.x) {
-    const int r = i / B, c = i % B;
-    D[r][c] = (r < bw && c < bw) ? Cj[(int64_t)(kb + r) * B + c] : 0.0;
-  }
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int k = 0; k < bw; ++k) {
-    const double piv = D[k][k];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      if (threadIdx.x == 0) bad = 1;
-      break;     // uniform: every thread reads the same pivot
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  double d[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gr = 4 * tr + r, gc = 4 * tc + c;
+      d[r][c] = (gr < bw && gc < bw) ? Cj[(int64_t)(kb + gr) * B + gc] : (gr == gc ? 1.0 : 0.0);
     }
-    if (threadIdx.x < bw) {
-      colk[threadIdx.x] = D[threadIdx.x][k];
-      rowk[threadIdx.x] = D[k][threadIdx.x];
+  bool bad = false;
+  for (int k4 = 0; k4 < B / 4; ++k4) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * k4 + kk, buf = k & 1;
+      if (tc == k4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) colb[buf][4 * tr + r] = d[r][kk];
+      }
+      if (tr == k4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rowb[buf][4 * tc + c] = d[kk][c];
+      }
+      __syncthreads();
+      const double piv = colb[buf][k];
+      bad = bad || !(piv > 0.0) || !isfinite(piv);
+      const double inv = 1.0 / piv;
+      double cr[4], rc[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        cr[e] = colb[buf][4 * tr + e];
+        rc[e] = rowb[buf][4 * tc + e];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int gr = 4 * tr + r, gc = 4 * tc + c;
+          double v;
+          if (gr == k && gc == k) v = -inv;
+          else if (gr == k) v = rc[c] * inv;
+          else if (gc == k) v = cr[r] * inv;
+          else v = d[r][c] - cr[r] * rc[c] * inv;
+          d[r][c] = v;
+        }
     }
-    __syncthreads();
-    const double inv = 1.0 / piv;
-    for (int i = threadIdx.x; i < bw * bw; i += blockDim.x) {
-      const int r = i / bw, c = i % bw;
-      double v;
-      if (r == k && c == k) v = -inv;
-      else if (r == k) v = rowk[c] * inv;
-      else if (c == k) v = colk[r] * inv;
-      else v = D[r][c] - colk[r] * rowk[c] * inv;
-      D[r][c] = v;
-    }
-    __syncthreads();
   }
-  __syncthreads();
-  if (bad) {
-    if (threadIdx.x == 0) atomicCAS(flags, 0, j_offset + j + 1);
-  }
+  // every thread sees the same pivots, so `bad` is uniform
+  if (bad && threadIdx.x == 0) atomicCAS(flags, 0, j_offset + j + 1);
   double* out = Dinv + (int64_t)j * B * B;
-  for (int i = threadIdx.x; i < B * B; i += blockDim.x) {
-    const int r = i / B, c = i % B;
-    out[i] = (r < bw && c < bw && !bad) ? -D[r][c] : 0.0;   // D holds -D^-1
-  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gr = 4 * tr + r, gc = 4 * tc + c;
+      out[gr * B + gc] = (gr < bw && gc < bw && !bad) ? -d[r][c] : 0.0;   // d holds -D^-1
+    }
 }
 
 // P[j][r][c] = sum_c' C[j][r][c'] Dinv[j][c'][c] for every row r.
@@ -163,7 +184,23 @@ __global__ __launch_bounds__(256) void update_kernel(double* __restrict__ A,
   if (I == kt || J == kt) return;
   const double* Pj = P + (int64_t)j * N * B;
   const double* Cj = C + (int64_t)j * N * B;
+  double* Aj = A + (int64_t)j * N * N;
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+  // Read this thread's part of the A tile first: its latency overlaps the
+  // panel loads and the MFMA block.
+  double av[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = I * B + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int col = J * B + wx * 32 + b * 16 + (lane & 15);
+        av[a][b][r] = (row < N && col < N) ? Aj[(int64_t)row * N + col] : 0.0;
+      }
   for (int i = tid; i < B * B / 2; i += 256) {
     const int r = i / (B / 2), c2 = (i % (B / 2)) * 2;
     const int gr = I * B + r, gc = J * B + r;
@@ -174,8 +211,6 @@ __global__ __launch_bounds__(256) void update_kernel(double* __restrict__ A,
     *reinterpret_cast<double2*>(&Cs[r][c2]) = cv;
   }
   __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wy = wave >> 1, wx = wave & 1;
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -196,7 +231,6 @@ __global__ __launch_bounds__(256) void update_kernel(double* __restrict__ A,
       for (int b = 0; b < 2; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
   }
-  double* Aj = A + (int64_t)j * N * N;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -205,7 +239,7 @@ __global__ __launch_bounds__(256) void update_kernel(double* __restrict__ A,
       for (int r = 0; r < 4; ++r) {
         const int row = I * B + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
         const int col = J * B + wx * 32 + b * 16 + (lane & 15);
-        if (row < N && col < N) Aj[(int64_t)row * N + col] -= acc[a][b][r];
+        if (row < N && col < N) Aj[(int64_t)row * N + col] = av[a][b][r] - acc[a][b][r];
       }
 }
 
@@ -294,8 +328,8 @@ extern "C" gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_l
     const int kb = kt * B, bw = std::min(B, N - kb);
     hipLaunchKernelGGL(gather_panel_kernel, dim3(grid_for((int64_t)F * N * B, 256)), dim3(256),
                        0, ctx->stream, A, N, F, kb, bw, C);
-    hipLaunchKernelGGL(pivot_kernel, dim3(F), dim3(256), 0, ctx->stream, C, N, kb, bw, Dinv,
-                       ctx->d_flags, 0);
+    hipLaunchKernelGGL(pivot_kernel, dim3(F), dim3(PIV_THREADS), 0, ctx->stream, C, N, kb, bw,
+                       Dinv, ctx->d_flags, 0);
     hipLaunchKernelGGL(panel_kernel, dim3(std::min(1024, (N + 3) / 4), F), dim3(256), 0,
                        ctx->stream, C, Dinv, N, P);
     if (T > 1)
