@@ -1,0 +1,249 @@
+"""GPU parity at the large shape (n_occ 300 with 80 frozen, v = 2200,
+n_aux = 7000 -> about 3500 NAFs, 12 Laplace points, 80 frequencies, 20 QP
+states), generated on the device by the generator's torch twin.
+
+The full FP64 oracle is too slow here, so each step is checked on outputs
+the oracle computes one by one (a block of sampled columns of M^m, sampled
+metric entries, sampled W_nm, whole screened matrices at a few
+frequencies), by properties that hold at any size (eigenpair residuals and
+orthonormality of the kept NAFs), and the QP energies transitively: the FP32
+and BF16x3 paths against the FP64 path at this size, the FP64 path being
+checked against the oracle at the smaller sizes.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import HARTREE_MEV
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from oracle import grids, naf, rpa  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_04508_amd import gwlt
+    return gwlt
+
+
+@pytest.fixture(scope="module")
+def ctx(gw):
+    c = gw.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def large():
+    from gwsynth import get_config
+    from gwsynth.device import make_problem_device
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _say("generating the large problem on the device (FP64)")
+    p = make_problem_device(get_config("large"), device="cuda", dtype=torch.float64)
+    torch.cuda.synchronize()
+    return p
+
+
+def _f32(t):
+    return t.to(torch.float32).contiguous()
+
+
+def _cols(t, cols):
+    """Host FP64 copy of the selected columns of a [rows][A] device tensor."""
+    idx = torch.as_tensor(cols, device=t.device)
+    return t.index_select(1, idx).double().cpu().numpy()
+
+
+def _sample_cols(N, n, seed):
+    rng = np.random.default_rng(seed)
+    s = set(rng.choice(N, size=n - 4, replace=False).tolist()) | {0, 127, 128, N - 1}
+    return np.array(sorted(s))
+
+
+def test_g0w0_large_precisions(gw, ctx, large):
+    p = large
+    c = p.cfg
+    params = gw.params_for(c)
+    out = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        if prec == "fp64":
+            R = (p.R_oo, p.R_ov, p.R_qp)
+        else:
+            R = tuple(_f32(t) for t in (p.R_oo, p.R_ov, p.R_qp))
+        _say(f"g0w0 large {prec}")
+        E, Z, S, sig, st = gw.gw_g0w0(ctx, prec, params, p.eps, p.qp, None, *R)
+        _say(f"  N_NAF={st.n_naf} total {st.t_total_ms:.0f} ms (NAF {st.t_naf_ms:.0f}, "
+             f"chi {st.t_chi_ms:.0f}, screen {st.t_screen_ms:.0f}, "
+             f"sigma {st.t_sigma_ms:.0f}), status {S}")
+        assert np.all(S == 0)
+        assert 3000 <= st.n_naf <= 4000
+        out[prec] = (E, sig, st.n_naf)
+        del R
+        torch.cuda.empty_cache()
+    E64, S64, n64 = out["fp64"]
+    assert np.all(np.isfinite(E64))
+    # QP energies move from the KS values by a physical amount (< 2 eV)
+    assert np.all(np.abs(E64 - p.eps[p.qp]) * HARTREE_MEV < 2000.0)
+    for prec in ("fp32", "bf16x3"):
+        E, sig, n = out[prec]
+        assert n == n64
+        d = np.abs(E - E64) * HARTREE_MEV
+        _say(f"  {prec} vs fp64: max QP difference {d.max():.2e} meV")
+        assert np.all(d < 1.0)
+        stol = 1e-4 if prec == "fp32" else 1e-3
+        assert np.max(np.abs(sig - S64)) < stol * np.max(np.abs(S64))
+
+
+def test_naf_metric_large_sampled(gw, ctx, large):
+    """Sampled entries of K against the oracle metric on the same columns,
+    and eigenpair residuals of the kept NAFs."""
+    p = large
+    c = p.cfg
+    A = c.n_aux
+    K = torch.zeros((A, A), dtype=torch.float64, device="cuda")
+    U = torch.zeros((A, A), dtype=torch.float64, device="cuda")
+    _say("naf metric large fp64")
+    gw.gw_naf_compress(ctx, "fp64", A, p.R_oo, p.R_ov, K, 0, 0, 0.0, 0, None)
+    gw.gw_sync(ctx)
+    Kl = torch.tril(K)
+    Kf = Kl + torch.tril(Kl, -1).T            # the lower triangle is the computed part
+    del Kl
+    cols = _sample_cols(A, 40, 7)
+    oo = p.R_oo.reshape(-1, A)
+    ref = naf.naf_metric(_cols(oo, cols), _cols(p.R_ov, cols))
+    idx = torch.as_tensor(cols, device="cuda")
+    got = Kf.index_select(0, idx).index_select(1, idx).cpu().numpy()
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    _say("naf compress large fp64")
+    K.zero_()
+    n, ev = gw.gw_naf_compress(ctx, "fp64", A, p.R_oo, p.R_ov, K, 0, 1, c.eps_naf,
+                               c.max_keep, U)
+    gw.gw_sync(ctx)
+    # descending eigenvalues, count above the threshold
+    assert np.all(np.diff(ev) <= 0)
+    assert n == int(np.count_nonzero(ev > c.eps_naf))
+    # residuals and orthonormality of sampled kept eigenvectors (row q of U
+    # is the eigenvector of the q-th largest eigenvalue)
+    Uk = U[:n].T
+    pick = _sample_cols(n, 24, 8)
+    V = Uk.index_select(1, torch.as_tensor(pick, device="cuda"))
+    lam = torch.as_tensor(ev[pick], device="cuda")
+    res = torch.linalg.norm(Kf @ V - V * lam[None, :], dim=0)
+    assert float(res.max()) < 1e-10 * float(abs(ev[0]))
+    G = Uk.T @ Uk
+    assert float((G - torch.eye(n, dtype=G.dtype, device="cuda")).abs().max()) < 1e-10
+
+
+def test_polarizability_large_sampled(gw, ctx, large):
+    """M^m at the large shape (k = 484000 rows, N = 3500 of the 7000 columns
+    with row stride 7000): a sampled block of columns in FP64 against the
+    oracle; the whole of FP32 and BF16x3 against FP64."""
+    p = large
+    c = p.cfg
+    o, v, N, L = c.n_act_occ, c.n_virt, 3500, c.n_lt
+    eps_i = p.eps[c.n_fc:c.n_occ]
+    eps_a = p.eps[c.n_occ:]
+    lo, hi = grids.lt_bounds(p.eps, c.n_fc, c.n_occ, grids.modified_gauss_legendre(c.n_freq)[0][0])
+    x, w, _ = grids.lt_grid(L, lo, hi)
+    Rv = p.R_ov[:, :N]
+    Ms = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        R = Rv if prec == "fp64" else _f32(p.R_ov)[:, :N]
+        M = torch.empty((L, N, N), dtype=torch.float64, device="cuda")
+        _say(f"polarizability large {prec}")
+        gw.gw_polarizability_lt(ctx, prec, N, x, w, o, v, eps_i, eps_a, R, 0, 1, M)
+        gw.gw_sync(ctx)
+        Ms[prec] = M
+        del R
+    cols = _sample_cols(N, 48, 9)
+    d = (eps_a[None, :] - eps_i[:, None]).ravel()
+    ref = rpa.m_lt(_cols(p.R_ov, cols), d, x, w)
+    idx = torch.as_tensor(cols, device="cuda")
+    got = Ms["fp64"].index_select(1, idx).index_select(2, idx).cpu().numpy()
+    for m in range(L):
+        e = np.linalg.norm(got[m] - ref[m]) / np.linalg.norm(ref[m])
+        assert e < 1e-12, (m, e)
+    for prec, tol in (("fp32", 1e-6), ("bf16x3", 1e-4)):
+        for m in range(L):
+            e = float(torch.linalg.norm(Ms[prec][m] - Ms["fp64"][m]) /
+                      torch.linalg.norm(Ms["fp64"][m]))
+            assert e < tol, (prec, m, e)
+        _say(f"  {prec}: chi relative Frobenius error vs fp64 <= {tol:g}")
+
+
+def test_screen_large_against_oracle(gw, ctx, large):
+    """gw_screen at N = 3500 and 80 frequencies; whole matrices at three
+    frequencies against the oracle's dense inverse."""
+    c = large.cfg
+    N, L, F = 3500, c.n_lt, c.n_freq
+    g = torch.Generator(device="cuda").manual_seed(31)
+    B = torch.randn((N, N), generator=g, dtype=torch.float64, device="cuda") / np.sqrt(N)
+    base = B @ B.T
+    x = np.geomspace(0.02, 40.0, L)
+    M = torch.stack([base * (0.3 * np.exp(-0.2 * m)) for m in range(L)]).contiguous()
+    om, _ = grids.modified_gauss_legendre(F)
+    Mh = M.cpu().numpy()
+    for prec, tol in (("fp64", 1e-11), ("fp32", 2e-7)):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        W = torch.empty((F, N, N), dtype=dt, device="cuda")
+        _say(f"screen large {prec}")
+        gw.gw_screen(ctx, prec, N, x, M, om, W)
+        gw.gw_sync(ctx)
+        for j in (0, F // 4, F // 2):
+            ref = rpa.screen(rpa.pi_lt(Mh, x, om[j:j + 1]))[0]
+            e = np.linalg.norm(W[j].double().cpu().numpy() - ref) / np.linalg.norm(ref)
+            assert e < tol, (prec, j, e)
+        # at the top frequency every exp(-w^2 x_m) underflows: Pi = 0, W^ = 0
+        ref = rpa.screen(rpa.pi_lt(Mh, x, om[F - 1:]))[0]
+        assert np.max(np.abs(ref)) == 0.0
+        assert float(W[F - 1].abs().max()) == 0.0
+        del W
+        torch.cuda.empty_cache()
+
+
+def test_sigma_large_sampled(gw, ctx, large):
+    """W_nm of gw_sigma_diag at the large shape (20 QP states x 2420
+    orbitals, N = 3500 with row stride 7000, 80 frequencies) on sampled
+    orbitals at three frequencies against the oracle."""
+    p = large
+    c = p.cfg
+    N, F, Q, Mo = 3500, c.n_freq, c.n_qp, c.n_act
+    g = torch.Generator(device="cuda").manual_seed(37)
+    W = torch.empty((F, N, N), dtype=torch.float64, device="cuda")
+    for j in range(F):
+        B = torch.randn((N, N), generator=g, dtype=torch.float64, device="cuda") / N
+        W[j] = (B + B.T) * (1.0 / (1.0 + j))
+    om, wom = grids.modified_gauss_legendre(F)
+    omp, _ = grids.modified_gauss_legendre(c.n_pade)
+    eps_m = p.eps[c.n_fc:]
+    eps_f = 0.5 * (p.eps[c.n_occ - 1] + p.eps[c.n_occ])
+    rows = _sample_cols(Mo, 32, 11)
+    for prec, tol in (("fp64", 1e-11), ("fp32", 2e-6), ("bf16x3", 1e-4)):
+        R = p.R_qp[..., :N] if prec == "fp64" else _f32(p.R_qp)[..., :N]
+        Wd = W if prec == "fp64" else W.to(torch.float32)
+        sig = torch.zeros((Q, c.n_pade, 2), dtype=torch.float64, device="cuda")
+        Wnm = torch.empty((F, Q, Mo), dtype=torch.float64, device="cuda")
+        _say(f"sigma large {prec}")
+        gw.gw_sigma_diag(ctx, prec, N, Q, Mo, eps_m, eps_f, R, om, wom, Wd, omp, 0, sig, Wnm)
+        gw.gw_sync(ctx)
+        Rh = p.R_qp[:, torch.as_tensor(rows, device="cuda"), :N].cpu().numpy()
+        for j in (0, F // 2, F - 1):
+            Wj = Wd[j].double().cpu().numpy()
+            ref = rpa.w_diag(Rh, Wj[None])[0]          # [Q][rows]
+            got = Wnm[j][:, torch.as_tensor(rows, device="cuda")].cpu().numpy()
+            e = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+            assert e < tol, (prec, j, e)
+        assert torch.all(torch.isfinite(sig))
+        del R, Wd
+        torch.cuda.empty_cache()
