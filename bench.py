@@ -47,6 +47,27 @@ def kernel_rate(gw, ctx, name):
             "gbs": nbytes / n / avg_s / 1e9}
 
 
+def source_hash(path):
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the stored PMC passes (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy), or None if none were taken for this
+    kernel and workload or the kernel's source changed since."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(f"{kernel}@{workload}")
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or source_hash(src) != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(prob, n_freq_sample=2):
     """Oracle (FP64 NumPy) on a bounded sample: the NAF stage once and the
     per-frequency work (sum-over-states Pi, dense inverse, W_nm) for
@@ -79,6 +100,147 @@ def cpu_baseline(prob, n_freq_sample=2):
             "measured_s": t_naf + t_freq}
 
 
+def run_streamed(args, cfg, gw, torch):
+    """The paper-scale workload, whose raw tensors do not fit in HBM: the
+    occupied-occupied and occupied-virtual rows are generated on the device
+    in occupied-index chunks and streamed through the chunked calls twice
+    (metric accumulation, then NAF transform and Laplace polarizability
+    accumulation), with the requested precisions in lockstep on each chunk
+    (the BF16x3 path shares the FP32 path's NAF basis, as in gw_g0w0).
+    Screening and self-energy run in frequency batches.  Stage times are
+    device-synchronised host times; generation is timed apart and excluded."""
+    from gwsynth.device import make_problem_device
+    precs = args.precs.split(",")
+    c = cfg
+    o, v, A, Q, Mo, L, F, Pd = (c.n_act_occ, c.n_virt, c.n_aux, c.n_qp, c.n_act, c.n_lt,
+                                c.n_freq, c.n_pade)
+    f64 = torch.float64
+    t0 = time.perf_counter()
+    p = make_problem_device(cfg, "cuda", f64, with_ov=False, with_oo=False, haar_on_device=True)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    log(f"{cfg.name}: energies, U and QP rows generated in {gen_s:.1f} s")
+    ctx = gw.Context(0)
+    chunk = args.chunk_i or max(1, int(args.chunk_gb * 1e9 // ((v + o) * A * 8)))
+    mprec = {q: ("fp64" if q == "fp64" else "fp32") for q in precs}
+    metric_precs = sorted(set(mprec.values()))
+    times = {q: {} for q in set(precs) | set(metric_precs)}
+
+    def timed(q, stage, fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        times[q][stage] = times[q].get(stage, 0.0) + time.perf_counter() - t
+        return r
+
+    def gen(fn):
+        nonlocal gen_s
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        gen_s += time.perf_counter() - t
+        return r
+
+    K = {m: torch.zeros((A, A), dtype=f64, device="cuda") for m in metric_precs}
+    U = {m: torch.zeros((A, A), dtype=f64, device="cuda") for m in metric_precs}
+    for i0 in range(0, o, chunk):
+        i1 = min(o, i0 + chunk)
+        oo = gen(lambda: p.oo_chunk(i0, i1, f64))
+        ov = gen(lambda: p.ov_chunk(i0, i1, f64))
+        for m in metric_precs:
+            a, b = (oo, ov) if m == "fp64" else (gen(lambda: oo.float()), gen(lambda: ov.float()))
+            timed(m, "naf_metric", lambda: gw.gw_naf_compress(ctx, m, A, a, b, K[m], i0 > 0, 0,
+                                                              0.0, 0, None))
+            del a, b
+        del oo, ov
+        log(f"metric pass: occupied {i1}/{o}")
+    n_naf = {}
+    for m in metric_precs:
+        n_naf[m], _ = timed(m, "naf_eig", lambda: gw.gw_naf_compress(
+            ctx, m, A, None, None, K[m], 1, 1, c.eps_naf, c.max_keep, U[m]))
+        log(f"{m} NAF: {n_naf[m]} of {A} kept")
+    del K
+    om, wom = gw.gw_freq_grid_mgl(F, c.x0)
+    omp, _ = gw.gw_freq_grid_mgl(Pd, c.x0)
+    eF, ymin, ymax = gw.gw_prepare(c.n_occ, c.n_fc, c.n_virt, p.eps, om[0])
+    x, w, lt_err = gw.gw_lt_grid_minimax(L, ymin, ymax)
+    eps_i, eps_a, eps_m = p.eps[c.n_fc:c.n_occ], p.eps[c.n_occ:], p.eps[c.n_fc:]
+    ld = {m: (n_naf[m] + 127) // 128 * 128 for m in metric_precs}
+    M = {q: torch.zeros((L, n_naf[mprec[q]], n_naf[mprec[q]]), dtype=f64, device="cuda")
+         for q in precs}
+    for i0 in range(0, o, chunk):
+        i1 = min(o, i0 + chunk)
+        ov = gen(lambda: p.ov_chunk(i0, i1, f64))
+        for m in metric_precs:
+            Rin = ov if m == "fp64" else gen(lambda: ov.float())
+            Rt = torch.empty((Rin.shape[0], ld[m]), dtype=Rin.dtype, device="cuda")
+            timed(m, "naf_transform", lambda: gw.gw_naf_apply(ctx, m, A, n_naf[m], U[m], Rin, Rt))
+            del Rin
+            for q in precs:
+                if mprec[q] != m:
+                    continue
+                N = n_naf[m]
+                timed(q, "chi", lambda: gw.gw_polarizability_lt(
+                    ctx, q, N, x, w, i1 - i0, v, eps_i[i0:i1], eps_a, Rt[:, :N], i0 > 0,
+                    i1 == o, M[q]))
+            del Rt
+        del ov
+        log(f"polarizability pass: occupied {i1}/{o}")
+    out = {}
+    for q in precs:
+        m = mprec[q]
+        N = n_naf[m]
+        Rqp = p.R_qp if m == "fp64" else p.R_qp.float()
+        Rt_qp = torch.empty((Q, Mo, ld[m]), dtype=Rqp.dtype, device="cuda")
+        timed(q, "naf_transform", lambda: gw.gw_naf_apply(ctx, m, A, N, U[m], Rqp, Rt_qp))
+        del Rqp
+        esz = 8 if q == "fp64" else 4
+        fb = max(1, min(F, int(args.screen_gb * 1e9 // (N * N * (esz + (0 if q == "fp64" else 8))))))
+        sig = torch.zeros((Q, Pd, 2), dtype=f64, device="cuda")
+        for j0 in range(0, F, fb):
+            j1 = min(F, j0 + fb)
+            W = torch.empty((j1 - j0, N, N), dtype=f64 if q == "fp64" else torch.float32,
+                            device="cuda")
+            timed(q, "screen", lambda: gw.gw_screen(ctx, q, N, x, M[q], om[j0:j1], W))
+            timed(q, "sigma", lambda: gw.gw_sigma_diag(ctx, q, N, Q, Mo, eps_m, eF,
+                                                       Rt_qp[..., :N], om[j0:j1], wom[j0:j1], W,
+                                                       omp, j0 > 0, sig))
+            del W
+        E, Z, S = timed(q, "qp", lambda: gw.gw_qp_solve(ctx, p.eps[p.qp], None, eF, omp, sig,
+                                                         c.eta, 1e-6, 100))
+        out[q] = (E, S)
+        del Rt_qp
+        torch.cuda.empty_cache()
+        log(f"{q}: QP done, status {S.tolist()}")
+    # totals per precision: the BF16x3 path's NAF is the FP32 path's
+    res = {}
+    for q in precs:
+        st = dict(times[q])
+        for k, val in times[mprec[q]].items():
+            if k.startswith("naf_") and q != mprec[q]:
+                st[k] = val
+        res[q] = {"stage_s": {k: round(val, 3) for k, val in st.items()},
+                  "total_s": round(sum(st.values()), 3), "n_naf": n_naf[mprec[q]],
+                  "status": out[q][1].tolist()}
+    ref = "fp64" if "fp64" in precs else None
+    for q in precs:
+        if ref and q != ref:
+            res[q]["qp_diff_vs_fp64_meV"] = float(np.max(np.abs(out[q][0] - out[ref][0])) *
+                                                  HARTREE_MEV)
+            if M[q].shape == M[ref].shape:
+                res[q]["chi_rel_fro_vs_fp64"] = max(
+                    float(torch.linalg.norm(M[q][m] - M[ref][m]) / torch.linalg.norm(M[ref][m]))
+                    for m in range(L))
+    line = {"workload": f"{cfg.name}: n_occ={c.n_occ} (n_fc={c.n_fc}), n_virt={v}, "
+                        f"n_aux={A}, L={L}, F={F}, Pd={Pd}, Q={Q}, streamed in chunks of "
+                        f"{chunk} occupied orbitals",
+            "generation_s": round(gen_s, 1), "lt_err_norm": lt_err, "paths": res,
+            "eps_qp": {q: out[q][0].tolist() for q in precs}}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +253,15 @@ def main():
     ap.add_argument("--bf16x3-steps", type=int, default=3,
                     help="steps of the BF16x3 path timed for comparison (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--streamed", action="store_true",
+                    help="stream the raw tensors in occupied chunks (the paper-scale workload; "
+                         "prints its own JSON line)")
+    ap.add_argument("--precs", default="fp64,fp32,bf16x3")
+    ap.add_argument("--chunk-i", type=int, default=0)
+    ap.add_argument("--chunk-gb", type=float, default=12.0)
+    ap.add_argument("--screen-gb", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -103,6 +274,9 @@ def main():
     from paper_2307_04508_amd import gwlt as gw
 
     cfg = get_config(args.config)
+    if args.streamed:
+        run_streamed(args, cfg, gw, torch)
+        return
     t0 = time.perf_counter()
     prob = make_problem(cfg, dtype=np.float32)
     log(f"generated {cfg.name} inputs in {time.perf_counter() - t0:.1f} s")
@@ -146,8 +320,10 @@ def main():
     if chi:
         roofline = {"kernel": kname, "bound": "mfma", "achieved": round(chi["tflops"], 3),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(chi["tflops"] / peak, 4),
-                    "traffic": None, "avg_ms": round(chi["avg_ms"], 4),
-                    "flops_per_launch": chi["flops_per_launch"]}
+                    "traffic": measured_traffic(kname, cfg.name),
+                    "avg_ms": round(chi["avg_ms"], 4),
+                    "flops_per_launch": chi["flops_per_launch"],
+                    "algorithmic_bytes_per_launch": chi["bytes_per_launch"]}
 
     bf16 = None
     if args.bf16x3_steps > 0 and args.prec == "fp32":
@@ -187,6 +363,16 @@ def main():
                 "qp_diff_vs_fp32_meV": float(np.max(np.abs(E64 - E)) * HARTREE_MEV)}
         del R64
         log(f"fp64 path: {fp64['wall_s'] * 1e3:.1f} ms/step")
+
+    if args.copy_calibration:
+        # one elementwise kernel reading 1 GiB and writing 1 GiB
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB write elementwise kernel done")
+        del src, dst
 
     qp_err = None
     gpath = os.path.join(ROOT, "tests", "golden", f"{cfg.name}_oracle.json")

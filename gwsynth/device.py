@@ -19,7 +19,10 @@ import dataclasses
 import numpy as np
 
 from .configs import Config
-from .problem import _GOLDEN, _MIX1, _MIX2, _RowSource, _energies, _pair_index, _seed_key
+import math
+
+from .problem import (_GOLDEN, _MIX1, _MIX2, _RowSource, _energies, _pair_index, _seed_key,
+                      decay_length)
 
 
 def _signed(c: int) -> int:
@@ -48,17 +51,39 @@ def splitmix64_uniform_torch(key: int, counters):
 class DeviceRowSource:
     """Rows B[pair, :] generated on ``device`` (torch)."""
 
-    def __init__(self, cfg: Config, rng: np.random.Generator, device):
+    def __init__(self, cfg: Config, rng: np.random.Generator, device,
+                 haar_on_device: bool = False):
+        """``haar_on_device``: draw the same Gaussian matrix on the host but
+        take its QR on the device (for n_aux in the tens of thousands); U
+        then differs from the host generator's by rounding only."""
         import torch
         if cfg.exact_orthonormal:
             raise ValueError("the exactly orthonormal (tiny) recipe is host-only")
-        host = _RowSource(cfg, rng)           # consumes the same draws as the host path
+        self.device = torch.device(device)
+        if haar_on_device:
+            A = cfg.n_aux
+            z = torch.as_tensor(rng.standard_normal((A, A)), device=self.device)
+            q, r = torch.linalg.qr(z)
+            del z
+            U = q * torch.sign(torch.diagonal(r))[None, :]
+            del q, r
+            self.UT = U.T.contiguous()
+            del U
+            host = _RowSource.__new__(_RowSource)
+            host.cfg = cfg
+            host.n_tot = cfg.n_occ + cfg.n_virt
+            n_all = host.n_tot * (host.n_tot + 1) / 2.0
+            host.c = 1.0
+            tau = decay_length(cfg)
+            s = np.exp(-np.arange(A) / tau)
+            host.colscale = (host.c / math.sqrt(n_all)) * s * math.sqrt(3.0)
+        else:
+            host = _RowSource(cfg, rng)       # consumes the same draws as the host path
+            self.UT = torch.as_tensor(host.U.T.copy(), device=self.device)
         self.cfg = cfg
         self.n_tot = host.n_tot
         self.key = _seed_key(cfg.seed)
         self.c = host.c
-        self.device = torch.device(device)
-        self.UT = torch.as_tensor(host.U.T.copy(), device=self.device)
         self.colscale = torch.as_tensor(host.colscale, device=self.device)
         self.j = torch.arange(cfg.n_aux, dtype=torch.int64, device=self.device)
 
@@ -95,6 +120,18 @@ class DeviceProblem:
     c_scale: float
     src: DeviceRowSource
 
+    def oo_chunk(self, i0: int, i1: int, dtype, out=None):
+        """Rows (i, j) of the occupied-occupied block for active occupied i in
+        [i0, i1) and every active occupied j, as a [(i1-i0)*o][A] tensor."""
+        import torch
+        c = self.cfg
+        occ = np.arange(c.n_fc, c.n_occ)
+        vi, vj = np.meshgrid(occ[i0:i1], occ, indexing="ij")
+        idx = _pair_index(vi.ravel(), vj.ravel(), self.src.n_tot)
+        if out is None:
+            out = torch.empty((idx.size, c.n_aux), dtype=dtype, device=self.src.device)
+        return self.src.rows_from_index(idx, out)
+
     def ov_chunk(self, i0: int, i1: int, dtype, out=None):
         """Rows i*v + a of the occupied-virtual block for active occupied
         i in [i0, i1), as a [(i1-i0)*v][A] tensor (or into ``out``)."""
@@ -110,15 +147,17 @@ class DeviceProblem:
 
 
 def make_problem_device(cfg: Config, device="cuda", dtype=None, with_ov: bool = True,
-                        block: int = 4096) -> DeviceProblem:
+                        block: int = 4096, with_oo: bool = True,
+                        haar_on_device: bool = False) -> DeviceProblem:
     """The problem of ``make_problem(cfg)`` with its tensors generated on
-    ``device`` (default dtype float64).  ``with_ov=False`` leaves the
-    occupied-virtual block to be streamed with ``DeviceProblem.ov_chunk``."""
+    ``device`` (default dtype float64).  ``with_ov=False`` / ``with_oo=False``
+    leave the occupied-virtual / occupied-occupied blocks to be streamed with
+    ``DeviceProblem.ov_chunk`` / ``oo_chunk``."""
     import torch
     dtype = torch.float64 if dtype is None else dtype
     rng = np.random.default_rng(cfg.seed)
     eps = _energies(cfg, rng)
-    src = DeviceRowSource(cfg, rng, device)
+    src = DeviceRowSource(cfg, rng, device, haar_on_device)
     nf, no, nv = cfg.n_fc, cfg.n_occ, cfg.n_virt
     o, M, A = cfg.n_act_occ, cfg.n_act, cfg.n_aux
     act = np.arange(nf, no + nv)
@@ -129,8 +168,10 @@ def make_problem_device(cfg: Config, device="cuda", dtype=None, with_ov: bool = 
                          np.arange(lumo, lumo + cfg.n_qp_virt)])
     if qp.min() < nf or qp.max() >= no + nv:
         raise ValueError("QP states must be active orbitals")
-    pi, pj = np.meshgrid(occ, occ, indexing="ij")
-    R_oo = src.rows(pi.ravel(), pj.ravel(), dtype, block).reshape(o, o, A)
+    R_oo = None
+    if with_oo:
+        pi, pj = np.meshgrid(occ, occ, indexing="ij")
+        R_oo = src.rows(pi.ravel(), pj.ravel(), dtype, block).reshape(o, o, A)
     R_ov = None
     if with_ov:
         vi, va = np.meshgrid(occ, virt, indexing="ij")

@@ -275,6 +275,150 @@ gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* params,
                   double* eps_qp, double* z_factor, int* status,
                   double* sigma_iw, gw_stats* stats);
 
+/* ------------------------------------------------------ graph capture */
+
+/* Capture the device work of the following calls on ctx into a HIP graph
+ * and replay it.  Between gw_graph_begin and gw_graph_end the calls are
+ * recorded, not run: ctx enqueues on a private capturing stream, and the
+ * host arrays the calls receive are copied into a device arena owned by the
+ * graph, so every replay sees the values given at capture.  Capturable:
+ * gw_naf_compress without finalize, gw_naf_apply, gw_polarizability_lt,
+ * gw_screen, gw_sigma_diag and their batched twins.  Calls that return host
+ * results or synchronise (finalize, gw_qp_solve, gw_g0w0, gw_sync,
+ * gw_profile_*, gw_set_stream) fail with GW_EUNSUPPORTED while capturing,
+ * as does any call that would have to grow the context's workspace: run
+ * the sequence once eagerly first.  While a graph lives, calls that would
+ * grow the workspace fail (the graph holds its buffers' addresses).
+ * gw_graph_launch enqueues a replay on ctx's stream; device arrays named at
+ * capture are read and written again in place.  gw_graph_destroy waits for
+ * ctx's stream, then releases the graph and its arena. */
+typedef struct gw_graph_s* gw_graph;
+gw_status gw_graph_begin(gw_ctx ctx);
+gw_status gw_graph_end(gw_ctx ctx, gw_graph* out);
+gw_status gw_graph_launch(gw_ctx ctx, gw_graph graph);
+gw_status gw_graph_destroy(gw_graph graph);
+
+/* ---------------------------------------- batched twins (many molecules) */
+
+/* The batched calls run the same computation as their single-molecule
+ * twins for n_jobs independent problems of uneven size in one launch per
+ * kernel: every work unit (tile, frequency, QP state) of every job goes
+ * into one grid, longest units first.  Arguments per job mean what they
+ * mean in the single call. */
+
+/* Eq. 10 for each job (see gw_polarizability_lt); all jobs share n_lt. */
+typedef struct {
+  int n_naf, n_i, n_virt;
+  const double* x_lt;       /* host [n_lt] */
+  const double* w_lt;       /* host [n_lt] */
+  const double* eps_i;      /* host [n_i] */
+  const double* eps_a;      /* host [n_virt] */
+  const void* R_chunk;      /* device [n_i * n_virt][ld_R] */
+  int64_t ld_R;             /* 0 = n_naf */
+  double* M;                /* device [n_lt][n_naf][n_naf] FP64 */
+} gw_chi_job;
+gw_status gw_polarizability_lt_batched(gw_ctx ctx, gw_precision prec, int n_lt,
+                                       int n_jobs, const gw_chi_job* jobs,
+                                       int accumulate, int finalize);
+
+/* Eqs. 2 and 10 for each job (see gw_screen); all jobs share n_lt.
+ * A non-positive pivot is reported as GW_ENOTSPD by the next synchronising
+ * call, naming the job and frequency. */
+typedef struct {
+  int n_naf;
+  const double* x_lt;       /* host [n_lt] */
+  const double* M;          /* device [n_lt][n_naf][n_naf] FP64 */
+  int n_w;
+  const double* omega;      /* host [n_w] */
+  void* W_hat;              /* device [n_w][n_naf][n_naf] */
+} gw_screen_job;
+gw_status gw_screen_batched(gw_ctx ctx, gw_precision prec, int n_lt, int n_jobs,
+                            const gw_screen_job* jobs);
+
+/* Eqs. 2 and 7 for each job (see gw_sigma_diag). */
+typedef struct {
+  int n_naf, n_qp, n_mo;
+  const double* eps_mo;     /* host [n_mo] */
+  double eps_F;
+  const void* R_qp;         /* device [n_qp][n_mo][ld_R] */
+  int64_t ld_R;             /* 0 = n_naf */
+  int n_w;
+  const double* omega;      /* host [n_w] */
+  const double* w_omega;    /* host [n_w] */
+  const void* W_hat;        /* device [n_w][n_naf][n_naf] */
+  int n_pade;
+  const double* omega_pade; /* host [n_pade] */
+  double* sigma_iw;         /* device [n_qp][n_pade] complex */
+  double* W_nm;             /* device [n_w][n_qp][n_mo] FP64 or NULL */
+} gw_sigma_job;
+gw_status gw_sigma_diag_batched(gw_ctx ctx, gw_precision prec, int n_jobs,
+                                const gw_sigma_job* jobs, int accumulate);
+
+/* Pade + QP fixed point for each job (see gw_qp_solve); one launch for all
+ * states of all jobs.  Synchronises. */
+typedef struct {
+  int n_qp;
+  const double* eps_n;      /* host [n_qp] */
+  const double* static_n;   /* host [n_qp] or NULL */
+  double eps_F;
+  int n_pade;
+  const double* omega_pade; /* host [n_pade] */
+  const double* sigma_iw;   /* device [n_qp][n_pade] complex */
+  double* eps_qp;           /* host [n_qp] */
+  double* z_factor;         /* host [n_qp] or NULL */
+  int* status;              /* host [n_qp] */
+} gw_qp_job;
+gw_status gw_qp_solve_batched(gw_ctx ctx, int n_jobs, const gw_qp_job* jobs,
+                              double eta, double tol, int max_iter);
+
+/* One molecule of gw_g0w0_batched: its sizes, NAF rule, energies, raw
+ * tensors (as for gw_g0w0) and host outputs. */
+typedef struct {
+  int n_occ, n_fc, n_virt, n_aux, n_qp;
+  double eps_naf;
+  int max_keep;
+  const double* eps;        /* host [n_occ + n_virt] */
+  const int* qp;            /* host [n_qp] absolute indices of active orbitals */
+  const double* static_n;   /* host [n_qp] or NULL */
+  const void* R_oo;         /* device [o][o][n_aux] */
+  const void* R_ov;         /* device [o * n_virt][n_aux] */
+  const void* R_qp;         /* device [n_qp][o + n_virt][n_aux] */
+  double* eps_qp;           /* host [n_qp] */
+  double* z_factor;         /* host [n_qp] or NULL */
+  int* status;              /* host [n_qp] */
+  double* sigma_iw;         /* host [n_qp][n_pade] complex or NULL */
+  int n_naf;                /* out: kept natural auxiliary functions */
+} gw_mol;
+
+/* Grid sizes and QP settings shared by all molecules of a batch. */
+typedef struct {
+  int n_lt, n_freq, n_pade;
+  double x0, eta, tol;
+  int max_iter;
+} gw_batch_params;
+
+#define GW_BATCH_GRAPH 1    /* replay the post-NAF work as one HIP graph */
+
+typedef struct {
+  double t_naf_ms;          /* NAF of all molecules (eager)               */
+  double t_rest_ms;         /* polarizability .. QP of all molecules      */
+  double t_total_ms;
+  int graph_replayed;       /* 1 if the post-NAF work ran as a cached graph */
+} gw_batch_stats;
+
+/* G0W0 for n_mol molecules of uneven size (a1-a9 for each).  The NAF stage
+ * runs eagerly: both metric SYRKs of all molecules in two launches, the
+ * eigendecompositions as batched FP64 solves over groups of similar size
+ * (each metric padded with a decoupled -1 diagonal block, which the exact
+ * block structure keeps out of the kept eigenvectors), the transforms per
+ * molecule.  Each molecule gets its own Laplace grid.  The rest (Laplace
+ * polarizability, screening, self-energy, QP) runs as batched launches; with
+ * GW_BATCH_GRAPH in flags those launches are captured once into a HIP graph
+ * after an eager run and replayed by later calls whose sizes, NAF counts and
+ * device inputs are unchanged.  Synchronises. */
+gw_status gw_g0w0_batched(gw_ctx ctx, gw_precision prec, const gw_batch_params* params,
+                          int n_mol, gw_mol* mols, int flags, gw_batch_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,10 +32,21 @@ enum WsSlot {
   WS_G_M,           // whole-step driver: Laplace matrices M^m
   WS_G_WHAT,        // whole-step driver: screened interaction
   WS_G_SIGMA,       // whole-step driver: Sigma(i w) on the Pade nodes
+  WS_B_RT_OV,       // batched driver: NAF-transformed ov tensors
+  WS_B_RT_QP,       // batched driver: NAF-transformed QP rows
+  WS_B_K,           // batched driver: padded NAF metrics
+  WS_B_U,           // batched driver: NAF bases
+  WS_B_M,           // batched driver: Laplace matrices
+  WS_B_WHAT,        // batched driver: screened interactions
+  WS_B_SIGMA,       // batched driver: Sigma(i w) and QP outputs
+  WS_B_EIG,         // batched driver: eigenvalues, off-diagonals, info
   WS_COUNT
 };
 
 constexpr size_t kStageBytes = size_t(4) << 20;   // staging ring size
+constexpr size_t kArenaBytes = size_t(32) << 20;  // per-graph copy of staged arrays
+
+struct BatchGraph;
 
 // One bracketed launch recorded while kernel timing is enabled.
 struct ProfEvent {
@@ -64,6 +75,23 @@ struct gw_ctx_s {
   bool prof = false;
   std::vector<ProfEvent> prof_pending;
   std::map<std::string, ProfStat> prof_stats;
+  // graph capture (gw_graph_begin / gw_graph_end): while capturing, host
+  // arrays are staged into a per-graph device arena instead of the ring, so
+  // replays read what the captured calls were given
+  bool capturing = false;
+  hipStream_t user_stream = nullptr;     // restored when the capture ends
+  hipStream_t capture_stream = nullptr;  // private, created lazily
+  unsigned char* arena_dev = nullptr;
+  std::vector<unsigned char> arena_host;
+  int live_graphs = 0;                   // caller-held graphs (workspace pinned)
+  BatchGraph* batch_graph = nullptr;     // gw_g0w0_batched's cached graph
+};
+
+// A captured, instantiated graph and the arena its kernels read.
+struct gw_graph_s {
+  gw_ctx ctx = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* arena = nullptr;
 };
 
 namespace gw {
@@ -79,6 +107,11 @@ template <typename T>
 inline const T* stage_t(gw_ctx ctx, const T* host, size_t n) {
   return static_cast<const T*>(stage(ctx, host, n * sizeof(T)));
 }
+// Begin / end a capture on the context (used by the public graph calls and
+// the batched driver).  end_capture instantiates the graph into *out.
+gw_status begin_capture(gw_ctx ctx);
+gw_status end_capture(gw_ctx ctx, gw_graph_s* out);
+void drop_batch_graph(gw_ctx ctx);
 // Read and clear the deferred device error flags (synchronises).
 gw_status check_flags(gw_ctx ctx);
 gw_status launch_check(gw_ctx ctx, const char* what);
@@ -98,6 +131,66 @@ gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X,
                       const void* scale, double cscale, double* out,
                       int accumulate, const char* prof_name);
 gw_status mirror_lower(gw_ctx ctx, double* M, int L, int N);
+
+// Batched forms: one launch over the work of several problems.
+struct SyrkJob {
+  const void* X;        // [k_rows][ld]
+  int64_t k_rows;
+  int N;
+  int64_t ld;
+  int L;
+  const void* scale;    // [L][k_rows] or nullptr
+  double cscale;
+  double* out;          // [L][N][N] FP64, lower triangle
+  int accumulate;
+};
+struct ScaleJob {
+  int L;
+  const double* x;      // device [L]
+  const double* w;      // device [L]
+  int n_i, n_virt;
+  const double* eps_i;  // device [n_i]
+  const double* eps_a;  // device [n_virt]
+  void* out;            // device [L][n_i * n_virt]
+};
+struct MirrorJob {
+  double* M;
+  int L, N;
+};
+gw_status syrk_batched_launch(gw_ctx ctx, gw_precision prec, const std::vector<SyrkJob>& jobs,
+                              const char* prof_name);
+gw_status lt_scale_batched(gw_ctx ctx, gw_precision prec, const std::vector<ScaleJob>& jobs);
+gw_status mirror_lower_batched(gw_ctx ctx, const std::vector<MirrorJob>& jobs);
+// Pade + QP for several jobs (device arrays), outputs [3 * state] on the device.
+struct QpJob {
+  int n_qp, n_pade;
+  const double* omega_pade;
+  const double* sigma_iw;
+  const double* eps_n;
+  const double* static_n;
+  double eps_F;
+};
+gw_status qp_batched_launch(gw_ctx ctx, const std::vector<QpJob>& jobs, double eta, double tol,
+                            int max_iter, double* out);
+// Batched NAF pieces (naf.hip).
+struct NafEigJob {
+  const double* K;      // device [A][A] metric, lower triangle
+  int A;
+  double* U;            // device [A][A]: eigenvectors as rows, descending
+  double* eig;          // host [A]: eigenvalues, descending
+};
+gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs);
+struct NafGemmJob {
+  const void* A;        // [rows][K]
+  const double* U;      // [>= ncols][K]
+  void* C;              // [rows][ldc]
+  int64_t rows;
+  int K, ncols;
+  int64_t ldc;
+};
+gw_status naf_gemm_batched(gw_ctx ctx, gw_precision prec, const std::vector<NafGemmJob>& jobs);
+// Zero n doubles with a kernel (capturable, unlike hipMemsetAsync).
+gw_status fill_zero(gw_ctx ctx, double* p, int64_t n);
 gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L,
                           const double* d_x, const double* d_w, int n_i,
                           int n_virt, const double* d_eps_i,
@@ -135,3 +228,91 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
   const int64_t g8 = G >> 3, rem = G & 7;
   return x * g8 + (x < rem ? x : rem) + slot;
 }
+
+// Batched launches put the work units of several problems in one grid:
+// problem d owns the logical units [off[d], off[d+1]) and its arguments are
+// descs[d].  Workgroups map to units in chunks of `chunk` consecutive units
+// per XCD, the chunks dealt round-robin over the 8 XCDs, so every XCD gets a
+// share of every problem while units that share data stay on one XCD.  The
+// grid is padded to a multiple of 8 * chunk; surplus workgroups exit.
+struct Batch {
+  const void* descs;      // device array of per-problem argument structs
+  const int64_t* off;     // device [n + 1] unit offsets
+  int n;
+  int chunk;
+  int64_t units;          // off[n]
+};
+
+__device__ __forceinline__ int64_t xcd_chunk_remap(int64_t b, int chunk) {
+  const int64_t x = b & 7, s = b >> 3;
+  return ((s / chunk) * 8 + x) * chunk + s % chunk;
+}
+
+__device__ __forceinline__ int find_problem(const int64_t* __restrict__ off, int n, int64_t u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= u) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The logical unit of this workgroup and its problem's arguments: a single
+// problem (bt.descs == nullptr) uses a0 and the XCD remap of the whole grid.
+template <typename Args>
+__device__ __forceinline__ bool unit_of(const Args& a0, const Batch& bt, Args& a, int64_t& lid) {
+  if (!bt.descs) {
+    a = a0;
+    lid = xcd_remap(blockIdx.x, gridDim.x);
+    return true;
+  }
+  const int64_t u = xcd_chunk_remap(blockIdx.x, bt.chunk);
+  if (u >= bt.units) return false;
+  const int d = find_problem(bt.off, bt.n, u);
+  a = static_cast<const Args*>(bt.descs)[d];
+  lid = u - bt.off[d];
+  return true;
+}
+
+// Same for element-wise kernels: a batched problem owns whole blocks of
+// kBatchElems elements, one 256-thread workgroup each (4 elements per
+// thread, strided by 256); returns the first element index of the block.
+constexpr int kBatchElems = 1024;
+template <typename Args>
+__device__ __forceinline__ bool block_of(const Batch& bt, Args& a, int64_t& first) {
+  const int64_t u = blockIdx.x;
+  if (u >= bt.units) return false;
+  const int d = find_problem(bt.off, bt.n, u);
+  a = static_cast<const Args*>(bt.descs)[d];
+  first = (u - bt.off[d]) * kBatchElems;
+  return true;
+}
+
+// ---------------------------------------------------------- batched launches
+namespace gw {
+
+// Stage a descriptor table and its unit offsets; returns the Batch.
+template <typename Args>
+inline gw_status stage_batch(gw_ctx ctx, const std::vector<Args>& d,
+                             const std::vector<int64_t>& off, int chunk, Batch& bt) {
+  const Args* dd = static_cast<const Args*>(stage(ctx, d.data(), d.size() * sizeof(Args)));
+  const int64_t* doff = static_cast<const int64_t*>(stage(ctx, off.data(), off.size() * sizeof(int64_t)));
+  if (!dd || !doff) return GW_EINVAL;
+  bt = Batch{dd, doff, (int)d.size(), chunk, off.back()};
+  return GW_OK;
+}
+
+template <typename Args>
+inline gw_status elementwise_batched(gw_ctx ctx, const std::vector<Args>& d,
+                                     const std::vector<int64_t>& n_elems, void (*kern)(Batch),
+                                     const char* what) {
+  std::vector<int64_t> off(1, 0);
+  for (int64_t n : n_elems) off.push_back(off.back() + (n + kBatchElems - 1) / kBatchElems);
+  if (off.back() == 0) return GW_OK;
+  Batch bt;
+  GW_TRY(stage_batch(ctx, d, off, 1, bt));
+  hipLaunchKernelGGL(kern, dim3((unsigned)off.back()), dim3(256), 0, ctx->stream, bt);
+  return launch_check(ctx, what);
+}
+
+}  // namespace gw

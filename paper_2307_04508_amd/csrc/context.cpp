@@ -34,6 +34,18 @@ gw_status launch_check(gw_ctx ctx, const char* what) {
 void* ws_get(gw_ctx ctx, WsSlot slot, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (ctx->ws_bytes[slot] >= bytes) return ctx->ws[slot];
+  if (ctx->capturing) {
+    fail(ctx, GW_EUNSUPPORTED,
+         "workspace would grow during graph capture; run the calls once eagerly "
+         "(or gw_reserve) before capturing them");
+    return nullptr;
+  }
+  if (ctx->live_graphs > 0) {
+    fail(ctx, GW_EUNSUPPORTED,
+         "workspace would grow while a captured graph references it; destroy the graph first");
+    return nullptr;
+  }
+  drop_batch_graph(ctx);   // the cached batched graph references the old buffers
   if (ctx->ws[slot]) {
     if (hipStreamSynchronize(ctx->stream) != hipSuccess ||
         hipFree(ctx->ws[slot]) != hipSuccess) {
@@ -59,6 +71,16 @@ void* ws_get(gw_ctx ctx, WsSlot slot, size_t bytes) {
 
 const void* stage(gw_ctx ctx, const void* host, size_t bytes) {
   size_t need = (bytes + 255) & ~size_t(255);
+  if (ctx->capturing) {
+    const size_t off = ctx->arena_host.size();
+    if (off + need > kArenaBytes) {
+      fail(ctx, GW_ENOMEM, "graph capture arena exhausted (%zu bytes)", kArenaBytes);
+      return nullptr;
+    }
+    ctx->arena_host.resize(off + need);
+    std::memcpy(ctx->arena_host.data() + off, host, bytes);
+    return ctx->arena_dev + off;
+  }
   if (need > kStageBytes) {
     fail(ctx, GW_EINVAL, "host array of %zu bytes exceeds the staging ring", bytes);
     return nullptr;
@@ -96,7 +118,7 @@ gw_status check_flags(gw_ctx ctx) {
 }
 
 int prof_begin(gw_ctx ctx) {
-  if (!ctx->prof) return -1;
+  if (!ctx->prof || ctx->capturing) return -1;
   ProfEvent e;
   if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return -1;
   hipEventRecord(e.a, ctx->stream);
@@ -129,12 +151,108 @@ static void prof_resolve(gw_ctx ctx) {
   ctx->prof_pending.clear();
 }
 
+gw_status begin_capture(gw_ctx ctx) {
+  if (ctx->capturing) return fail(ctx, GW_EINVAL, "a graph capture is already in progress");
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (!ctx->capture_stream)
+    GW_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+  void* arena = nullptr;
+  if (hipMalloc(&arena, kArenaBytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, GW_ENOMEM, "graph arena allocation failed");
+  }
+  ctx->arena_dev = static_cast<unsigned char*>(arena);
+  ctx->arena_host.clear();
+  ctx->user_stream = ctx->stream;
+  ctx->stream = ctx->capture_stream;
+  if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    ctx->stream = ctx->user_stream;
+    hipFree(arena);
+    ctx->arena_dev = nullptr;
+    return fail(ctx, GW_EDEVICE, "hipStreamBeginCapture failed");
+  }
+  ctx->capturing = true;
+  return GW_OK;
+}
+
+gw_status end_capture(gw_ctx ctx, gw_graph_s* out) {
+  if (!ctx->capturing) return fail(ctx, GW_EINVAL, "no graph capture in progress");
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  ctx->stream = ctx->user_stream;
+  ctx->capturing = false;
+  hipGraphExec_t exec = nullptr;
+  hipError_t ei = hipErrorUnknown;
+  if (e == hipSuccess && graph) {
+    ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+  }
+  hipError_t ec = hipSuccess;
+  if (ei == hipSuccess && !ctx->arena_host.empty())
+    ec = hipMemcpy(ctx->arena_dev, ctx->arena_host.data(), ctx->arena_host.size(),
+                   hipMemcpyHostToDevice);
+  if (e != hipSuccess || ei != hipSuccess || ec != hipSuccess) {
+    if (exec) hipGraphExecDestroy(exec);
+    hipFree(ctx->arena_dev);
+    ctx->arena_dev = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, GW_EDEVICE, "graph capture failed (%s)",
+                hipGetErrorString(e != hipSuccess ? e : (ei != hipSuccess ? ei : ec)));
+  }
+  out->ctx = ctx;
+  out->exec = exec;
+  out->arena = ctx->arena_dev;
+  ctx->arena_dev = nullptr;
+  ctx->arena_host.clear();
+  return GW_OK;
+}
+
 }  // namespace gw
 
 extern "C" {
 
+gw_status gw_graph_begin(gw_ctx ctx) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_graph_begin: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  return gw::begin_capture(ctx);
+}
+
+gw_status gw_graph_end(gw_ctx ctx, gw_graph* out) {
+  if (!ctx || !out) return gw::fail(ctx, GW_EINVAL, "gw_graph_end: NULL argument");
+  *out = nullptr;
+  gw_graph_s g;
+  GW_TRY(gw::end_capture(ctx, &g));
+  *out = new gw_graph_s(g);
+  ctx->live_graphs += 1;
+  return GW_OK;
+}
+
+gw_status gw_graph_launch(gw_ctx ctx, gw_graph g) {
+  if (!ctx || !g || g->ctx != ctx)
+    return gw::fail(ctx, GW_EINVAL, "gw_graph_launch: bad graph or context");
+  if (ctx->capturing) return gw::fail(ctx, GW_EUNSUPPORTED, "gw_graph_launch inside a capture");
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  GW_HIP(ctx, hipGraphLaunch(g->exec, ctx->stream));
+  return GW_OK;
+}
+
+gw_status gw_graph_destroy(gw_graph g) {
+  if (!g) return GW_OK;
+  gw_ctx ctx = g->ctx;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->arena) hipFree(g->arena);
+  ctx->live_graphs -= 1;
+  delete g;
+  return GW_OK;
+}
+
+
 gw_status gw_profile_enable(gw_ctx ctx, int enable) {
   if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_profile_enable: ctx is NULL");
+  if (ctx->capturing) return gw::fail(ctx, GW_EUNSUPPORTED, "gw_profile_enable inside a graph capture");
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
   gw::prof_resolve(ctx);
   ctx->prof_stats.clear();
@@ -145,6 +263,7 @@ gw_status gw_profile_enable(gw_ctx ctx, int enable) {
 gw_status gw_profile_get(gw_ctx ctx, const char* kernel, double* total_ms, int64_t* launches,
                          double* flops, double* bytes) {
   if (!ctx || !kernel) return gw::fail(ctx, GW_EINVAL, "gw_profile_get: NULL argument");
+  if (ctx->capturing) return gw::fail(ctx, GW_EUNSUPPORTED, "gw_profile_get inside a graph capture");
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
   gw::prof_resolve(ctx);
   auto it = ctx->prof_stats.find(kernel);
@@ -185,6 +304,8 @@ gw_status gw_destroy(gw_ctx ctx) {
   if (!ctx) return GW_OK;
   hipSetDevice(ctx->device);
   if (ctx->stream) hipStreamSynchronize(ctx->stream); else hipDeviceSynchronize();
+  gw::drop_batch_graph(ctx);
+  if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
   for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) hipFree(ctx->ws[i]);
   if (ctx->d_flags) hipFree(ctx->d_flags);
@@ -200,6 +321,7 @@ gw_status gw_destroy(gw_ctx ctx) {
 
 gw_status gw_set_stream(gw_ctx ctx, void* hip_stream) {
   if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_set_stream: ctx is NULL");
+  if (ctx->capturing) return gw::fail(ctx, GW_EUNSUPPORTED, "gw_set_stream inside a graph capture");
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   return GW_OK;
@@ -207,6 +329,7 @@ gw_status gw_set_stream(gw_ctx ctx, void* hip_stream) {
 
 gw_status gw_sync(gw_ctx ctx) {
   if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_sync: ctx is NULL");
+  if (ctx->capturing) return gw::fail(ctx, GW_EUNSUPPORTED, "gw_sync inside a graph capture");
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return gw::check_flags(ctx);
 }

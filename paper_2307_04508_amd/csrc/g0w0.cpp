@@ -43,6 +43,8 @@ extern "C" gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* P,
                              double* sigma_iw, gw_stats* stats) {
   if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_g0w0: ctx is NULL");
   gw::clear_error(ctx);
+  if (ctx->capturing)
+    return gw::fail(ctx, GW_EUNSUPPORTED, "gw_g0w0 synchronises and cannot be captured");
   GW_REQUIRE(ctx, P && eps && qp && R_oo && R_ov && R_qp && eps_qp && status,
              "gw_g0w0: NULL argument");
   const int o = P->n_occ - P->n_fc, v = P->n_virt, Mo = o + v, A = P->n_aux;

@@ -31,6 +31,50 @@ inline int grid_for(int64_t n, int block) {
 // U[p][:] = eigenvector of the p-th largest eigenvalue.  syevd leaves the
 // eigenvectors in the rows of V (column-major output of a symmetric input)
 // in ascending order.
+// Batched NAF: metric K (lower triangle, [A][A]) copied into a padded
+// [Ap][Ap] matrix with a decoupled -1 diagonal block; after the solve the
+// eigenvectors of the A largest eigenvalues are taken back, descending, as
+// rows of U [A][A] (their padded components are exact zeros: the block
+// structure is preserved exactly by the reduction to tridiagonal form).
+struct PadArgs {
+  const double* K;      // [A][A] lower triangle
+  int A, Ap;
+  double* Kp;           // [Ap][Ap] (column-major = row-major, symmetric)
+  const double* V;      // [Ap][Ap] eigenvectors as rows (column-major solve output)
+  double* U;            // [A][A]
+};
+
+__device__ __forceinline__ void pad_elem(const PadArgs& a, int64_t idx) {
+  if (idx >= (int64_t)a.Ap * a.Ap) return;
+  const int p = (int)(idx / a.Ap), q = (int)(idx % a.Ap);
+  double v;
+  if (p < a.A && q < a.A)
+    v = p >= q ? a.K[(int64_t)p * a.A + q] : a.K[(int64_t)q * a.A + p];
+  else
+    v = p == q ? -1.0 : 0.0;
+  a.Kp[idx] = v;
+}
+
+__global__ void pad_batched_kernel(Batch bt) {
+  PadArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) pad_elem(a, first + e + threadIdx.x);
+}
+
+__device__ __forceinline__ void unpad_elem(const PadArgs& a, int64_t idx) {
+  if (idx >= (int64_t)a.A * a.A) return;
+  const int p = (int)(idx / a.A), c = (int)(idx % a.A);
+  a.U[idx] = a.V[(int64_t)(a.Ap - 1 - p) * a.Ap + c];
+}
+
+__global__ void unpad_batched_kernel(Batch bt) {
+  PadArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) unpad_elem(a, first + e + threadIdx.x);
+}
+
 __global__ void reorder_kernel(const double* __restrict__ V, int n, double* __restrict__ U) {
   const int64_t total = (int64_t)n * n;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -61,10 +105,12 @@ constexpr int NT8 = 512;
 // one stage ahead and consumed only at the LDS store, so the global reads
 // stay in flight behind the MFMA block.  Rows past the end and k past K load
 // as zeros (k is the contraction index, so the tail must be exact zeros).
-__global__ __launch_bounds__(NT8, 2) void nt_gemm_f32_kernel(GemmArgs g) {
+__global__ __launch_bounds__(NT8, 2) void nt_gemm_f32_kernel(GemmArgs g0, Batch bt) {
   __shared__ float As[2][BM][LDK];
   __shared__ float Bs[2][BM][LDK];
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  GemmArgs g;
+  int64_t lid;
+  if (!unit_of(g0, bt, g, lid)) return;
   const int ct = (int)(lid % g.col_tiles);
   const int rt = (int)(lid / g.col_tiles);
   const int64_t row0 = (int64_t)rt * BM;
@@ -184,10 +230,12 @@ __global__ __launch_bounds__(NT8, 2) void nt_gemm_f32_kernel(GemmArgs g) {
 constexpr int BK64 = 16;
 constexpr int LDK64 = BK64 + 2;
 
-__global__ __launch_bounds__(NT, 1) void nt_gemm_f64_kernel(GemmArgs g) {
+__global__ __launch_bounds__(NT, 1) void nt_gemm_f64_kernel(GemmArgs g0, Batch bt) {
   __shared__ double As[BM][LDK64];
   __shared__ double Bs[BM][LDK64];
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  GemmArgs g;
+  int64_t lid;
+  if (!unit_of(g0, bt, g, lid)) return;
   const int ct = (int)(lid % g.col_tiles);
   const int rt = (int)(lid / g.col_tiles);
   const int64_t row0 = (int64_t)rt * BM;
@@ -266,6 +314,9 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
   GW_REQUIRE(ctx, K && (n_oo_rows == 0 || R_oo) && (n_ov_rows == 0 || R_ov),
              "gw_naf_compress: NULL argument");
   GW_REQUIRE(ctx, !finalize || (n_naf && U), "gw_naf_compress: finalize needs n_naf and U");
+  if (finalize && ctx->capturing)
+    return gw::fail(ctx, GW_EUNSUPPORTED,
+                    "gw_naf_compress: the eigensolver synchronises and cannot be captured");
   GW_HIP(ctx, hipSetDevice(ctx->device));
   // FP32- and BF16x3-path tensors are stored in FP32: FP32 MFMA metric.
   const gw_precision mp = prec == GW_FP64 ? GW_FP64 : GW_FP32;
@@ -276,7 +327,7 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
     GW_TRY(gw::syrk_launch(ctx, mp, R_ov, n_ov_rows, n_aux, n_aux, 1, nullptr, 4.0, K,
                            accumulate || n_oo_rows > 0, "naf_syrk"));
   if (n_oo_rows == 0 && n_ov_rows == 0 && !accumulate)
-    GW_HIP(ctx, hipMemsetAsync(K, 0, (size_t)n_aux * n_aux * sizeof(double), ctx->stream));
+    GW_TRY(gw::fill_zero(ctx, K, (int64_t)n_aux * n_aux));
   if (!finalize) return GW_OK;
 
   GW_TRY(gw::mirror_lower(ctx, K, 1, n_aux));
@@ -340,10 +391,149 @@ extern "C" gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int 
   const int64_t grid = (int64_t)rt * ct;
   const int pi = gw::prof_begin(ctx);
   if (prec == GW_FP64)
-    hipLaunchKernelGGL(nt_gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, g);
+    hipLaunchKernelGGL(nt_gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, g,
+                       Batch{});
   else
-    hipLaunchKernelGGL(nt_gemm_f32_kernel, dim3((unsigned)grid), dim3(NT8), 0, ctx->stream, g);
+    hipLaunchKernelGGL(nt_gemm_f32_kernel, dim3((unsigned)grid), dim3(NT8), 0, ctx->stream, g,
+                       Batch{});
   gw::prof_end(ctx, pi, prec == GW_FP64 ? "naf_gemm_f64" : "naf_gemm_f32",
                2.0 * (double)n_rows * n_aux * (double)n_naf, 0.0);
   return gw::launch_check(ctx, "naf transform");
 }
+
+namespace gw {
+
+rocblas_handle naf_rocblas(gw_ctx ctx) {
+  if (!ctx->rocblas) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+    ctx->rocblas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(ctx->rocblas);
+  rocblas_set_stream(h, ctx->stream);
+  return h;
+}
+
+// Eigendecompositions of several metrics: jobs grouped into buckets of
+// similar size, each bucket one strided-batched FP64 divide-and-conquer
+// solve over padded copies.  K[d] (lower triangle) is read; U[d] receives
+// the eigenvectors as rows, descending; eig[d] (host, descending) the
+// eigenvalues.  Synchronises.
+gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs) {
+  const int n = (int)jobs.size();
+  if (n == 0) return GW_OK;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return jobs[x].A > jobs[y].A; });
+  // greedy buckets, largest first: add a job while the padded cubic cost of
+  // the bucket stays within 25% of its unpadded cost
+  struct Bucket { int Ap; std::vector<int> ids; };
+  std::vector<Bucket> buckets;
+  for (int id : order) {
+    const double a3 = std::pow((double)jobs[id].A, 3);
+    if (!buckets.empty()) {
+      Bucket& b = buckets.back();
+      double cost = 0;
+      for (int j : b.ids) cost += std::pow((double)jobs[j].A, 3);
+      cost += a3;
+      if ((double)(b.ids.size() + 1) * std::pow((double)b.Ap, 3) <= 1.25 * cost) {
+        b.ids.push_back(id);
+        continue;
+      }
+    }
+    buckets.push_back(Bucket{jobs[id].A, {id}});
+  }
+  size_t kp_tot = 0, ev_tot = 0;
+  for (const Bucket& b : buckets) {
+    kp_tot += b.ids.size() * (size_t)b.Ap * b.Ap;
+    ev_tot += b.ids.size() * (size_t)b.Ap;
+  }
+  double* Kp = static_cast<double*>(ws_get(ctx, WS_B_K, kp_tot * sizeof(double)));
+  double* ev = static_cast<double*>(
+      ws_get(ctx, WS_B_EIG, (2 * ev_tot + (size_t)n + 8) * sizeof(double)));
+  if (!Kp || !ev) return GW_ENOMEM;
+  double* E = ev + ev_tot;
+  rocblas_int* info = reinterpret_cast<rocblas_int*>(ev + 2 * ev_tot);
+  rocblas_handle h = naf_rocblas(ctx);
+  if (!h) return fail(ctx, GW_EDEVICE, "rocblas_create_handle failed");
+  std::vector<PadArgs> pads(n);
+  std::vector<int64_t> pad_n(n), un_n(n);
+  std::vector<size_t> ev_off(n);
+  size_t ko = 0, eo = 0, io = 0;
+  std::vector<std::pair<size_t, size_t>> bucket_at;   // (Kp offset, ev offset)
+  for (const Bucket& b : buckets) {
+    bucket_at.push_back({ko, eo});
+    for (int id : b.ids) {
+      pads[id] = PadArgs{jobs[id].K, jobs[id].A, b.Ap, Kp + ko, Kp + ko, jobs[id].U};
+      pad_n[id] = (int64_t)b.Ap * b.Ap;
+      un_n[id] = (int64_t)jobs[id].A * jobs[id].A;
+      ev_off[id] = eo;
+      ko += (size_t)b.Ap * b.Ap;
+      eo += b.Ap;
+    }
+  }
+  GW_TRY(elementwise_batched(ctx, pads, pad_n, pad_batched_kernel, "pad_batched_kernel"));
+  const int pe = prof_begin(ctx);
+  for (size_t bi = 0; bi < buckets.size(); ++bi) {
+    const Bucket& b = buckets[bi];
+    const rocblas_stride sA = (rocblas_stride)b.Ap * b.Ap;
+    rocblas_status rs = rocsolver_dsyevd_strided_batched(
+        h, rocblas_evect_original, rocblas_fill_lower, b.Ap, Kp + bucket_at[bi].first, b.Ap, sA,
+        ev + bucket_at[bi].second, b.Ap, E + bucket_at[bi].second, b.Ap, info + io,
+        (rocblas_int)b.ids.size());
+    if (rs != rocblas_status_success)
+      return fail(ctx, GW_EDEVICE, "rocsolver_dsyevd_strided_batched failed (%d)", (int)rs);
+    io += b.ids.size();
+  }
+  prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
+  GW_TRY(elementwise_batched(ctx, pads, un_n, unpad_batched_kernel, "unpad_batched_kernel"));
+  std::vector<double> hev(ev_tot);
+  std::vector<rocblas_int> hinfo(n);
+  GW_HIP(ctx, hipMemcpyAsync(hev.data(), ev, ev_tot * sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  GW_HIP(ctx, hipMemcpyAsync(hinfo.data(), info, n * sizeof(rocblas_int), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < n; ++i)
+    if (hinfo[i] != 0) return fail(ctx, GW_ENOCONV, "batched eigensolver info = %d", (int)hinfo[i]);
+  for (int id = 0; id < n; ++id) {
+    const int A = jobs[id].A;
+    int Ap = 0;
+    for (const Bucket& b : buckets)
+      for (int j : b.ids)
+        if (j == id) Ap = b.Ap;
+    // ascending; the top A belong to the molecule (padding sits at -1)
+    for (int p = 0; p < A; ++p) jobs[id].eig[p] = hev[ev_off[id] + Ap - 1 - p];
+  }
+  return GW_OK;
+}
+
+gw_status naf_gemm_batched(gw_ctx ctx, gw_precision prec, const std::vector<NafGemmJob>& jobs) {
+  std::vector<GemmArgs> d;
+  std::vector<int64_t> off(1, 0);
+  double flops = 0;
+  for (const NafGemmJob& j : jobs) {
+    if (j.rows == 0) continue;
+    const int rt = (int)((j.rows + BM - 1) / BM), ct = (int)((j.ldc + BM - 1) / BM);
+    d.push_back(GemmArgs{j.A, j.U, j.C, j.rows, j.K, j.ncols, j.ldc, rt, ct});
+    off.push_back(off.back() + (int64_t)rt * ct);
+    flops += 2.0 * (double)j.rows * j.K * (double)j.ncols;
+  }
+  if (d.empty()) return GW_OK;
+  constexpr int CHUNK = 8;
+  Batch bt;
+  GW_TRY(stage_batch(ctx, d, off, CHUNK, bt));
+  const int64_t grid = (off.back() + 8 * CHUNK - 1) / (8 * CHUNK) * (8 * CHUNK);
+  const int pi = prof_begin(ctx);
+  if (prec == GW_FP64)
+    hipLaunchKernelGGL(nt_gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream,
+                       GemmArgs{}, bt);
+  else
+    hipLaunchKernelGGL(nt_gemm_f32_kernel, dim3((unsigned)grid), dim3(NT8), 0, ctx->stream,
+                       GemmArgs{}, bt);
+  prof_end(ctx, pi, prec == GW_FP64 ? "naf_gemm_f64" : "naf_gemm_f32", flops, 0.0);
+  return launch_check(ctx, "batched naf transform");
+}
+
+}  // namespace gw

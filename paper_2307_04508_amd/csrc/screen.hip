@@ -26,48 +26,95 @@ inline int grid_for(int64_t n, int block) {
 }
 
 // A_j[p][q] = delta_pq + 2 s sum_m exp(-w_j^2 x_m) M^m[p][q], lower triangle.
-__global__ void assemble_kernel(const double* __restrict__ M, int L, int N,
-                                const double* __restrict__ x, const double* __restrict__ omega,
-                                int F, double* __restrict__ A) {
-  extern __shared__ double coef[];   // [F][L]
-  for (int i = threadIdx.x; i < F * L; i += blockDim.x) {
-    const int j = i / L, m = i % L;
-    coef[i] = 4.0 * exp(-omega[j] * omega[j] * x[m]);   // 2 s, s = 2
+struct AsmArgs {
+  const double* M;      // [L][N][N]
+  int L, N;
+  const double* x;      // [L]
+  const double* omega;  // [F]
+  int F;
+  double* A;            // [F][N][N]
+};
+
+__device__ __forceinline__ void load_coef(const AsmArgs& a, double* coef) {
+  for (int i = threadIdx.x; i < a.F * a.L; i += blockDim.x) {
+    const int j = i / a.L, m = i % a.L;
+    coef[i] = 4.0 * exp(-a.omega[j] * a.omega[j] * a.x[m]);   // 2 s, s = 2
   }
   __syncthreads();
-  const int64_t NN = (int64_t)N * N;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < NN;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int p = (int)(idx / N), q = (int)(idx % N);
-    if (q > p) continue;
-    double mv[32];
-    for (int m = 0; m < L; ++m) mv[m] = M[m * NN + idx];
-    const double d = (p == q) ? 1.0 : 0.0;
-    for (int j = 0; j < F; ++j) {
-      double v = d;
-      for (int m = 0; m < L; ++m) v += coef[j * L + m] * mv[m];
-      A[j * NN + idx] = v;
-    }
+}
+
+__device__ __forceinline__ void assemble_elem(const AsmArgs& a, const double* coef, int64_t idx) {
+  const int64_t NN = (int64_t)a.N * a.N;
+  if (idx >= NN) return;
+  const int p = (int)(idx / a.N), q = (int)(idx % a.N);
+  if (q > p) return;
+  double mv[32];
+  for (int m = 0; m < a.L; ++m) mv[m] = a.M[m * NN + idx];
+  const double d = (p == q) ? 1.0 : 0.0;
+  for (int j = 0; j < a.F; ++j) {
+    double v = d;
+    for (int m = 0; m < a.L; ++m) v += coef[j * a.L + m] * mv[m];
+    a.A[j * NN + idx] = v;
   }
 }
 
+__global__ void assemble_kernel(AsmArgs a) {
+  extern __shared__ double coef[];   // [F][L]
+  load_coef(a, coef);
+  const int64_t NN = (int64_t)a.N * a.N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < NN;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    assemble_elem(a, coef, idx);
+}
+
+__global__ void assemble_batched_kernel(Batch bt) {
+  extern __shared__ double coef[];
+  AsmArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  load_coef(a, coef);
+  for (int e = 0; e < kBatchElems; e += 256) assemble_elem(a, coef, first + e + threadIdx.x);
+}
+
+// Arguments of one sweep step (pivot block kt, columns kb .. kb + bw - 1)
+// for one batch of F matrices.
+struct SwArgs {
+  double* A;            // [F][N][N] lower triangle
+  double* C;            // [F][N][B] pivot column panel
+  double* P;            // [F][N][B] scaled panel
+  double* Dinv;         // [F][B][B]
+  int N, F, kb, bw, T, kt;
+  int flag_base;        // flag value offset of this batch's first matrix
+  int panel_blocks;     // batched panel kernel: workgroups per matrix
+};
+
 // C[j][r][c] = A_j(r, kb + c) read from the lower triangle; zero for c >= bw.
-__global__ void gather_panel_kernel(const double* __restrict__ A, int N, int F, int kb,
-                                    int bw, double* __restrict__ C) {
-  const int64_t NN = (int64_t)N * N;
-  const int64_t total = (int64_t)F * N * B;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(idx % B);
-    const int r = (int)((idx / B) % N);
-    const int j = (int)(idx / ((int64_t)B * N));
-    double v = 0.0;
-    if (c < bw) {
-      const int col = kb + c;
-      v = (r >= col) ? A[j * NN + (int64_t)r * N + col] : A[j * NN + (int64_t)col * N + r];
-    }
-    C[idx] = v;
+__device__ __forceinline__ void gather_elem(const SwArgs& a, int64_t idx) {
+  const int64_t NN = (int64_t)a.N * a.N;
+  if (idx >= (int64_t)a.F * a.N * B) return;
+  const int c = (int)(idx % B);
+  const int r = (int)((idx / B) % a.N);
+  const int j = (int)(idx / ((int64_t)B * a.N));
+  double v = 0.0;
+  if (c < a.bw) {
+    const int col = a.kb + c;
+    v = (r >= col) ? a.A[j * NN + (int64_t)r * a.N + col] : a.A[j * NN + (int64_t)col * a.N + r];
   }
+  a.C[idx] = v;
+}
+
+__global__ void gather_panel_kernel(SwArgs a) {
+  const int64_t total = (int64_t)a.F * a.N * B;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    gather_elem(a, idx);
+}
+
+__global__ void gather_panel_batched_kernel(Batch bt) {
+  SwArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) gather_elem(a, first + e + threadIdx.x);
 }
 
 // One workgroup per frequency sweeps the 64 x 64 pivot block, stored in
@@ -77,13 +124,10 @@ __global__ void gather_panel_kernel(const double* __restrict__ A, int N, int F, 
 // (bw < 64) is padded with the identity, which the sweep leaves as -1 and
 // does not couple to the valid part.  Stores D^-1 (zero-padded).
 constexpr int PIV_THREADS = 256;
-__global__ __launch_bounds__(PIV_THREADS) void pivot_kernel(const double* __restrict__ C, int N,
-                                                            int kb, int bw,
-                                                            double* __restrict__ Dinv,
-                                                            int* __restrict__ flags, int j_offset) {
+__device__ __forceinline__ void pivot_unit(const SwArgs& a, int j, int* __restrict__ flags) {
   __shared__ double colb[2][B], rowb[2][B];
-  const int j = blockIdx.x;
-  const double* Cj = C + (int64_t)j * N * B;
+  const int N = a.N, kb = a.kb, bw = a.bw;
+  const double* Cj = a.C + (int64_t)j * N * B;
   const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
   double d[4][4];
 #pragma unroll
@@ -131,8 +175,8 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_kernel(const double* __rest
     }
   }
   // every thread sees the same pivots, so `bad` is uniform
-  if (bad && threadIdx.x == 0) atomicCAS(flags, 0, j_offset + j + 1);
-  double* out = Dinv + (int64_t)j * B * B;
+  if (bad && threadIdx.x == 0) atomicCAS(flags, 0, a.flag_base + j + 1);
+  double* out = a.Dinv + (int64_t)j * B * B;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -142,39 +186,63 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_kernel(const double* __rest
     }
 }
 
-// P[j][r][c] = sum_c' C[j][r][c'] Dinv[j][c'][c] for every row r.
-__global__ __launch_bounds__(256) void panel_kernel(const double* __restrict__ C,
-                                                    const double* __restrict__ Dinv, int N,
-                                                    double* __restrict__ P) {
+__global__ __launch_bounds__(PIV_THREADS) void pivot_kernel(SwArgs a, int* __restrict__ flags) {
+  pivot_unit(a, blockIdx.x, flags);
+}
+
+__global__ __launch_bounds__(PIV_THREADS) void pivot_batched_kernel(Batch bt,
+                                                                    int* __restrict__ flags) {
+  const int d = find_problem(bt.off, bt.n, blockIdx.x);
+  const SwArgs a = static_cast<const SwArgs*>(bt.descs)[d];
+  pivot_unit(a, (int)(blockIdx.x - bt.off[d]), flags);
+}
+
+// P[j][r][c] = sum_c' C[j][r][c'] Dinv[j][c'][c] for every row r; this
+// workgroup takes row groups blk, blk + nblk, ... of 4 rows.
+__device__ __forceinline__ void panel_unit(const SwArgs& a, int j, int blk, int nblk) {
   __shared__ double Ds[B][B + 1];
   __shared__ double Cs[4][B];
-  const int j = blockIdx.y;
-  const double* Dj = Dinv + (int64_t)j * B * B;
+  const int N = a.N;
+  const double* Dj = a.Dinv + (int64_t)j * B * B;
   for (int i = threadIdx.x; i < B * B; i += blockDim.x) Ds[i / B][i % B] = Dj[i];
   const int rsub = threadIdx.x / B, c = threadIdx.x % B;
-  for (int r0 = blockIdx.x * 4; r0 < N; r0 += gridDim.x * 4) {
+  for (int r0 = blk * 4; r0 < N; r0 += nblk * 4) {
     __syncthreads();
     const int r = r0 + rsub;
-    Cs[rsub][c] = (r < N) ? C[((int64_t)j * N + r) * B + c] : 0.0;
+    Cs[rsub][c] = (r < N) ? a.C[((int64_t)j * N + r) * B + c] : 0.0;
     __syncthreads();
     if (r < N) {
       double v = 0.0;
 #pragma unroll 8
       for (int k = 0; k < B; ++k) v += Cs[rsub][k] * Ds[k][c];
-      P[((int64_t)j * N + r) * B + c] = v;
+      a.P[((int64_t)j * N + r) * B + c] = v;
     }
   }
 }
 
+__global__ __launch_bounds__(256) void panel_kernel(SwArgs a) {
+  panel_unit(a, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void panel_batched_kernel(Batch bt) {
+  const int d = find_problem(bt.off, bt.n, blockIdx.x);
+  const SwArgs a = static_cast<const SwArgs*>(bt.descs)[d];
+  const int u = (int)(blockIdx.x - bt.off[d]);
+  panel_unit(a, u / a.panel_blocks, u % a.panel_blocks, a.panel_blocks);
+}
+
 // A[I][J] -= P[I rows] C[J rows]^T for lower tiles I >= J, I, J != pivot tile.
-__global__ __launch_bounds__(256) void update_kernel(double* __restrict__ A,
-                                                     const double* __restrict__ P,
-                                                     const double* __restrict__ C, int N,
-                                                     int T, int kt) {
+__global__ __launch_bounds__(256) void update_kernel(SwArgs a0, Batch bt) {
   __shared__ double Ps[B][LDP];
   __shared__ double Cs[B][LDP];
+  SwArgs sa;
+  int64_t lid;
+  if (!unit_of(a0, bt, sa, lid)) return;
+  const int N = sa.N, T = sa.T, kt = sa.kt;
+  double* __restrict__ A = sa.A;
+  const double* __restrict__ P = sa.P;
+  const double* __restrict__ C = sa.C;
   const int n_tiles = T * (T + 1) / 2;
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
   const int j = (int)(lid / n_tiles);
   const int t = (int)(lid % n_tiles);
   int I = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
@@ -245,44 +313,73 @@ __global__ __launch_bounds__(256) void update_kernel(double* __restrict__ A,
 
 // Pivot row / column after the update: A(r, K) <- P[r] for r outside K,
 // A(K, K) <- -D^-1 (lower triangle storage).
-__global__ void writeback_kernel(double* __restrict__ A, const double* __restrict__ P,
-                                 const double* __restrict__ Dinv, int N, int F, int kb,
-                                 int bw) {
-  const int64_t NN = (int64_t)N * N;
-  const int64_t total = (int64_t)F * N * B;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(idx % B);
-    const int r = (int)((idx / B) % N);
-    const int j = (int)(idx / ((int64_t)B * N));
-    if (c >= bw) continue;
-    const int col = kb + c;
-    double* Aj = A + j * NN;
-    if (r >= kb && r < kb + bw) {
-      const int rr = r - kb;
-      if (rr >= c) Aj[(int64_t)r * N + col] = -Dinv[((int64_t)j * B + rr) * B + c];
-    } else {
-      const double v = P[idx];
-      if (r > col) Aj[(int64_t)r * N + col] = v;
-      else Aj[(int64_t)col * N + r] = v;
-    }
+__device__ __forceinline__ void writeback_elem(const SwArgs& a, int64_t idx) {
+  const int64_t NN = (int64_t)a.N * a.N;
+  if (idx >= (int64_t)a.F * a.N * B) return;
+  const int c = (int)(idx % B);
+  const int r = (int)((idx / B) % a.N);
+  const int j = (int)(idx / ((int64_t)B * a.N));
+  if (c >= a.bw) return;
+  const int col = a.kb + c;
+  double* Aj = a.A + j * NN;
+  if (r >= a.kb && r < a.kb + a.bw) {
+    const int rr = r - a.kb;
+    if (rr >= c) Aj[(int64_t)r * a.N + col] = -a.Dinv[((int64_t)j * B + rr) * B + c];
+  } else {
+    const double v = a.P[idx];
+    if (r > col) Aj[(int64_t)r * a.N + col] = v;
+    else Aj[(int64_t)col * a.N + r] = v;
   }
 }
 
-// W^ = -S - 1 from the swept lower triangle S = -A^-1; both triangles.
-template <typename T>
-__global__ void finish_kernel(const double* __restrict__ S, int N, int F, T* __restrict__ W) {
-  const int64_t NN = (int64_t)N * N;
-  const int64_t total = (int64_t)F * NN;
+__global__ void writeback_kernel(SwArgs a) {
+  const int64_t total = (int64_t)a.F * a.N * B;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = idx / NN, e = idx % NN;
-    const int p = (int)(e / N), q = (int)(e % N);
-    if (q > p) continue;
-    const double v = -S[j * NN + e] - (p == q ? 1.0 : 0.0);
-    W[j * NN + (int64_t)p * N + q] = (T)v;
-    W[j * NN + (int64_t)q * N + p] = (T)v;
-  }
+       idx += (int64_t)gridDim.x * blockDim.x)
+    writeback_elem(a, idx);
+}
+
+__global__ void writeback_batched_kernel(Batch bt) {
+  SwArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) writeback_elem(a, first + e + threadIdx.x);
+}
+
+// W^ = -S - 1 from the swept lower triangle S = -A^-1; both triangles.
+struct FinArgs {
+  const double* S;      // [F][N][N]
+  int N, F;
+  void* W;              // [F][N][N] FP64 or FP32
+};
+
+template <typename T>
+__device__ __forceinline__ void finish_elem(const FinArgs& a, int64_t idx) {
+  const int64_t NN = (int64_t)a.N * a.N;
+  if (idx >= (int64_t)a.F * NN) return;
+  const int64_t j = idx / NN, e = idx % NN;
+  const int p = (int)(e / a.N), q = (int)(e % a.N);
+  if (q > p) return;
+  const double v = -a.S[j * NN + e] - (p == q ? 1.0 : 0.0);
+  T* W = static_cast<T*>(a.W);
+  W[j * NN + (int64_t)p * a.N + q] = (T)v;
+  W[j * NN + (int64_t)q * a.N + p] = (T)v;
+}
+
+template <typename T>
+__global__ void finish_kernel(FinArgs a) {
+  const int64_t total = (int64_t)a.F * a.N * a.N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    finish_elem<T>(a, idx);
+}
+
+template <typename T>
+__global__ void finish_batched_kernel(Batch bt) {
+  FinArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) finish_elem<T>(a, first + e + threadIdx.x);
 }
 
 }  // namespace
@@ -320,32 +417,158 @@ extern "C" gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_l
 
   const int pi = gw::prof_begin(ctx);
   hipLaunchKernelGGL(assemble_kernel, dim3(grid_for(NN, 256)), dim3(256),
-                     (size_t)F * n_lt * sizeof(double), ctx->stream, M, n_lt, N, dx, dw, F, A);
+                     (size_t)F * n_lt * sizeof(double), ctx->stream,
+                     AsmArgs{M, n_lt, N, dx, dw, F, A});
   GW_TRY(gw::launch_check(ctx, "assemble_kernel"));
   const int T = (N + B - 1) / B;
   const int n_tiles = T * (T + 1) / 2;
   for (int kt = 0; kt < T; ++kt) {
     const int kb = kt * B, bw = std::min(B, N - kb);
+    const SwArgs sa{A, C, P, Dinv, N, F, kb, bw, T, kt, 0, 0};
     hipLaunchKernelGGL(gather_panel_kernel, dim3(grid_for((int64_t)F * N * B, 256)), dim3(256),
-                       0, ctx->stream, A, N, F, kb, bw, C);
-    hipLaunchKernelGGL(pivot_kernel, dim3(F), dim3(PIV_THREADS), 0, ctx->stream, C, N, kb, bw,
-                       Dinv, ctx->d_flags, 0);
+                       0, ctx->stream, sa);
+    hipLaunchKernelGGL(pivot_kernel, dim3(F), dim3(PIV_THREADS), 0, ctx->stream, sa,
+                       ctx->d_flags);
     hipLaunchKernelGGL(panel_kernel, dim3(std::min(1024, (N + 3) / 4), F), dim3(256), 0,
-                       ctx->stream, C, Dinv, N, P);
+                       ctx->stream, sa);
     if (T > 1)
       hipLaunchKernelGGL(update_kernel, dim3((unsigned)((int64_t)F * n_tiles)), dim3(256), 0,
-                         ctx->stream, A, P, C, N, T, kt);
+                         ctx->stream, sa, Batch{});
     hipLaunchKernelGGL(writeback_kernel, dim3(grid_for((int64_t)F * N * B, 256)), dim3(256), 0,
-                       ctx->stream, A, P, Dinv, N, F, kb, bw);
+                       ctx->stream, sa);
     GW_TRY(gw::launch_check(ctx, "screening sweep"));
   }
   gw::prof_end(ctx, pi, "screen_sweep", (double)F * N * (double)N * N,
                (double)F * N * (double)N * 8.0 * 2.0);
+  const FinArgs fa{A, N, F, W_hat};
   if (prec == GW_FP64)
     hipLaunchKernelGGL(finish_kernel<double>, dim3(grid_for(F * NN, 256)), dim3(256), 0,
-                       ctx->stream, A, N, F, static_cast<double*>(W_hat));
+                       ctx->stream, fa);
   else
     hipLaunchKernelGGL(finish_kernel<float>, dim3(grid_for(F * NN, 256)), dim3(256), 0,
-                       ctx->stream, A, N, F, static_cast<float*>(W_hat));
+                       ctx->stream, fa);
   return gw::launch_check(ctx, "finish_kernel");
+}
+
+extern "C" gw_status gw_screen_batched(gw_ctx ctx, gw_precision prec, int n_lt, int n_jobs,
+                                       const gw_screen_job* jobs) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_screen_batched: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_screen_batched: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_lt >= 1 && n_lt <= 32 && n_jobs >= 0 && (n_jobs == 0 || jobs),
+             "gw_screen_batched: bad sizes (n_lt=%d n_jobs=%d)", n_lt, n_jobs);
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_screen_job& j = jobs[d];
+    GW_REQUIRE(ctx, j.n_naf >= 1 && j.n_w >= 1 && j.n_w * n_lt <= 4096,
+               "gw_screen_batched: job %d: bad sizes (n_naf=%d n_w=%d)", d, j.n_naf, j.n_w);
+    GW_REQUIRE(ctx, j.x_lt && j.M && j.omega && j.W_hat, "gw_screen_batched: job %d: NULL argument", d);
+  }
+  if (n_jobs == 0) return GW_OK;
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+
+  // workspace: FP64 working matrices (in place for FP64), panels, pivots
+  size_t a_tot = 0, p_tot = 0, d_tot = 0;
+  for (int d = 0; d < n_jobs; ++d) {
+    const size_t N = jobs[d].n_naf, F = jobs[d].n_w;
+    if (prec != GW_FP64) a_tot += F * N * N;
+    p_tot += F * N * B;
+    d_tot += F * B * B;
+  }
+  double* Aws = nullptr;
+  if (a_tot) {
+    Aws = static_cast<double*>(gw::ws_get(ctx, WS_SCREEN_A, a_tot * sizeof(double)));
+    if (!Aws) return GW_ENOMEM;
+  }
+  double* pan = static_cast<double*>(
+      gw::ws_get(ctx, WS_SCREEN_PANEL, (2 * p_tot + d_tot) * sizeof(double)));
+  if (!pan) return GW_ENOMEM;
+
+  std::vector<AsmArgs> asm_d;
+  std::vector<FinArgs> fin_d;
+  std::vector<SwArgs> base;
+  std::vector<int64_t> n_asm, n_fin;
+  size_t ao = 0, po = 0, dof = 0;
+  int flag_base = 0, T_max = 0, smem = 0;
+  double flops = 0, bytes = 0;
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_screen_job& j = jobs[d];
+    const int N = j.n_naf, F = j.n_w;
+    const double* dx = gw::stage_t(ctx, j.x_lt, n_lt);
+    const double* dw = gw::stage_t(ctx, j.omega, F);
+    if (!dx || !dw) return GW_EINVAL;
+    double* A = prec == GW_FP64 ? static_cast<double*>(j.W_hat) : Aws + ao;
+    if (prec != GW_FP64) ao += (size_t)F * N * N;
+    SwArgs sa{A, pan + po, pan + p_tot + po, pan + 2 * p_tot + dof, N, F, 0, 0,
+              (N + B - 1) / B, 0, flag_base, std::min(1024, (N + 15) / 16)};
+    po += (size_t)F * N * B;
+    dof += (size_t)F * B * B;
+    flag_base += F;
+    T_max = std::max(T_max, sa.T);
+    smem = std::max(smem, F * n_lt);
+    base.push_back(sa);
+    asm_d.push_back(AsmArgs{j.M, n_lt, N, dx, dw, F, A});
+    n_asm.push_back((int64_t)N * N);
+    fin_d.push_back(FinArgs{A, N, F, j.W_hat});
+    n_fin.push_back((int64_t)F * N * N);
+    flops += (double)F * N * (double)N * N;
+    bytes += (double)F * N * (double)N * 8.0 * 2.0;
+  }
+
+  const int pi = gw::prof_begin(ctx);
+  {
+    std::vector<int64_t> off(1, 0);
+    for (int64_t n : n_asm) off.push_back(off.back() + (n + kBatchElems - 1) / kBatchElems);
+    Batch bt;
+    GW_TRY(gw::stage_batch(ctx, asm_d, off, 1, bt));
+    hipLaunchKernelGGL(assemble_batched_kernel, dim3((unsigned)off.back()), dim3(256),
+                       (size_t)smem * sizeof(double), ctx->stream, bt);
+    GW_TRY(gw::launch_check(ctx, "assemble_batched_kernel"));
+  }
+  for (int kt = 0; kt < T_max; ++kt) {
+    std::vector<SwArgs> st;
+    std::vector<int64_t> o_el(1, 0), o_piv(1, 0), o_pan(1, 0), o_upd(1, 0);
+    for (const SwArgs& b0 : base) {
+      if (kt >= b0.T) continue;
+      SwArgs sa = b0;
+      sa.kt = kt;
+      sa.kb = kt * B;
+      sa.bw = std::min(B, sa.N - sa.kb);
+      st.push_back(sa);
+      const int64_t el = (int64_t)sa.F * sa.N * B;
+      o_el.push_back(o_el.back() + (el + kBatchElems - 1) / kBatchElems);
+      o_piv.push_back(o_piv.back() + sa.F);
+      o_pan.push_back(o_pan.back() + (int64_t)sa.F * sa.panel_blocks);
+      o_upd.push_back(o_upd.back() + (int64_t)sa.F * sa.T * (sa.T + 1) / 2);
+    }
+    const SwArgs* dst = static_cast<const SwArgs*>(gw::stage(ctx, st.data(), st.size() * sizeof(SwArgs)));
+    const int64_t* d_el = gw::stage_t(ctx, o_el.data(), o_el.size());
+    const int64_t* d_piv = gw::stage_t(ctx, o_piv.data(), o_piv.size());
+    const int64_t* d_pan = gw::stage_t(ctx, o_pan.data(), o_pan.size());
+    const int64_t* d_upd = gw::stage_t(ctx, o_upd.data(), o_upd.size());
+    if (!dst || !d_el || !d_piv || !d_pan || !d_upd) return GW_EINVAL;
+    const int n = (int)st.size();
+    constexpr int CHUNK = 8;
+    const Batch b_el{dst, d_el, n, 1, o_el.back()};
+    const Batch b_piv{dst, d_piv, n, 1, o_piv.back()};
+    const Batch b_pan{dst, d_pan, n, 1, o_pan.back()};
+    const Batch b_upd{dst, d_upd, n, CHUNK, o_upd.back()};
+    hipLaunchKernelGGL(gather_panel_batched_kernel, dim3((unsigned)o_el.back()), dim3(256), 0,
+                       ctx->stream, b_el);
+    hipLaunchKernelGGL(pivot_batched_kernel, dim3((unsigned)o_piv.back()), dim3(PIV_THREADS), 0,
+                       ctx->stream, b_piv, ctx->d_flags);
+    hipLaunchKernelGGL(panel_batched_kernel, dim3((unsigned)o_pan.back()), dim3(256), 0,
+                       ctx->stream, b_pan);
+    const int64_t g_upd = (o_upd.back() + 8 * CHUNK - 1) / (8 * CHUNK) * (8 * CHUNK);
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)g_upd), dim3(256), 0, ctx->stream,
+                       SwArgs{}, b_upd);
+    hipLaunchKernelGGL(writeback_batched_kernel, dim3((unsigned)o_el.back()), dim3(256), 0,
+                       ctx->stream, b_el);
+    GW_TRY(gw::launch_check(ctx, "batched screening sweep"));
+  }
+  gw::prof_end(ctx, pi, "screen_sweep", flops, bytes);
+  return gw::elementwise_batched(ctx, fin_d, n_fin,
+                                 prec == GW_FP64 ? finish_batched_kernel<double>
+                                                 : finish_batched_kernel<float>,
+                                 "finish_batched_kernel");
 }

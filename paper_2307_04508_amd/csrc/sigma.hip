@@ -39,8 +39,7 @@ struct BwbArgs {
   double* part;       // [F][2 * col_tiles][rows]
 };
 
-__device__ __forceinline__ void decode(const BwbArgs& a, int& j, int& ct, int& rt) {
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void decode(const BwbArgs& a, int64_t lid, int& j, int& ct, int& rt) {
   rt = (int)(lid % a.row_tiles);
   ct = (int)((lid / a.row_tiles) % a.col_tiles);
   j = (int)(lid / ((int64_t)a.row_tiles * a.col_tiles));
@@ -50,11 +49,14 @@ __device__ __forceinline__ void decode(const BwbArgs& a, int& j, int& ct, int& r
 constexpr int BK32 = 32;
 constexpr int LDA32 = BK32 + 1;
 
-__global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a) {
+__global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a0, Batch bt) {
   __shared__ float As[2][BM][LDA32];
   __shared__ float Bs[2][BK32][BM];
   int j, ct, rt;
-  decode(a, j, ct, rt);
+  BwbArgs a;
+  int64_t lid;
+  if (!unit_of(a0, bt, a, lid)) return;
+  decode(a, lid, j, ct, rt);
   const float* R = static_cast<const float*>(a.R);
   const float* W = static_cast<const float*>(a.W) + (int64_t)j * a.N * a.N;
   const int64_t row0 = (int64_t)rt * BM;
@@ -188,11 +190,14 @@ __global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a) {
 constexpr int BK64 = 16;
 constexpr int LDA64 = BK64 + 2;
 
-__global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a) {
+__global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a0, Batch bt) {
   __shared__ double As[2][BM][LDA64];
   __shared__ double Bs[2][BK64][BM];
   int j, ct, rt;
-  decode(a, j, ct, rt);
+  BwbArgs a;
+  int64_t lid;
+  if (!unit_of(a0, bt, a, lid)) return;
+  decode(a, lid, j, ct, rt);
   const double* R = static_cast<const double*>(a.R);
   const double* W = static_cast<const double*>(a.W) + (int64_t)j * a.N * a.N;
   const int64_t row0 = (int64_t)rt * BM;
@@ -345,13 +350,16 @@ __device__ __forceinline__ float4 load4_guarded(const float* base, int64_t off, 
   return v;
 }
 
-__global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a) {
+__global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a0, Batch bt) {
   __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][LDB];
   __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][LDB];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BM][LDB];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BM][LDB];
   int j, ct, rt;
-  decode(a, j, ct, rt);
+  BwbArgs a;
+  int64_t lid;
+  if (!unit_of(a0, bt, a, lid)) return;
+  decode(a, lid, j, ct, rt);
   const float* R = static_cast<const float*>(a.R);
   const float* W = static_cast<const float*>(a.W) + (int64_t)j * a.N * a.N;
   const int64_t row0 = (int64_t)rt * BM;
@@ -467,39 +475,68 @@ __global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a) {
 }
 
 // W[j][row] = sum over column partials (fixed order); optional user copy.
-__global__ void w_reduce_kernel(const double* __restrict__ part, int n_part, int64_t rows,
-                                int F, double* __restrict__ W, double* __restrict__ W_user) {
-  const int64_t total = (int64_t)F * rows;
+struct WRedArgs {
+  const double* part;   // [F][n_part][rows]
+  int n_part;
+  int64_t rows;
+  int F;
+  double* W;            // [F][rows]
+  double* W_user;       // optional copy
+};
+
+__device__ __forceinline__ void w_reduce_elem(const WRedArgs& a, int64_t idx) {
+  if (idx >= (int64_t)a.F * a.rows) return;
+  const int64_t j = idx / a.rows, r = idx % a.rows;
+  double v = 0.0;
+  for (int p = 0; p < a.n_part; ++p) v += a.part[(j * a.n_part + p) * a.rows + r];
+  a.W[idx] = v;
+  if (a.W_user) a.W_user[idx] = v;
+}
+
+__global__ void w_reduce_kernel(WRedArgs a) {
+  const int64_t total = (int64_t)a.F * a.rows;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = idx / rows, r = idx % rows;
-    double v = 0.0;
-    for (int p = 0; p < n_part; ++p) v += part[(j * n_part + p) * rows + r];
-    W[idx] = v;
-    if (W_user) W_user[idx] = v;
-  }
+       idx += (int64_t)gridDim.x * blockDim.x)
+    w_reduce_elem(a, idx);
+}
+
+__global__ void w_reduce_batched_kernel(Batch bt) {
+  WRedArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) w_reduce_elem(a, first + e + threadIdx.x);
 }
 
 // One workgroup per (QP state q, Pade node k):
 //   Sigma = -(1/pi) sum_j w_j sum_m a / (a^2 + w_j^2) W[j][q][m],
 //   a = i wp_k + e_F - e_m.
-__global__ __launch_bounds__(256) void sigma_quad_kernel(
-    const double* __restrict__ W, int F, int Q, int M, const double* __restrict__ eps_m,
-    double eps_f, const double* __restrict__ omega, const double* __restrict__ w_omega,
-    const double* __restrict__ omega_p, int Pd, int accumulate, double* __restrict__ sigma) {
+struct QuadArgs {
+  const double* W;      // [F][Q][M]
+  int F, Q, M;
+  const double* eps_m;  // [M]
+  double eps_f;
+  const double* omega;
+  const double* w_omega;
+  const double* omega_p;
+  int Pd;
+  int accumulate;
+  double* sigma;        // [Q][Pd][2]
+};
+
+__device__ __forceinline__ void sigma_quad_unit(const QuadArgs& a, int unit) {
   __shared__ double sre[256], sim[256];
-  const int q = blockIdx.x / Pd, k = blockIdx.x % Pd;
-  const double wk = omega_p[k];
+  const int q = unit / a.Pd, k = unit % a.Pd;
+  const double wk = a.omega_p[k];
   double re = 0.0, im = 0.0;
-  for (int idx = threadIdx.x; idx < F * M; idx += blockDim.x) {
-    const int j = idx / M, m = idx % M;
-    const double ar = eps_f - eps_m[m], ai = wk;          // a = ar + i ai
-    const double wj = omega[j];
+  for (int idx = threadIdx.x; idx < a.F * a.M; idx += blockDim.x) {
+    const int j = idx / a.M, m = idx % a.M;
+    const double ar = a.eps_f - a.eps_m[m], ai = wk;      // a = ar + i ai
+    const double wj = a.omega[j];
     // a^2 + w_j^2 = (ar^2 - ai^2 + wj^2) + i (2 ar ai)
     const double dr = ar * ar - ai * ai + wj * wj, di = 2.0 * ar * ai;
     const double den = dr * dr + di * di;
     const double gr = (ar * dr + ai * di) / den, gi = (ai * dr - ar * di) / den;
-    const double f = w_omega[j] * W[((int64_t)j * Q + q) * M + m];
+    const double f = a.w_omega[j] * a.W[((int64_t)j * a.Q + q) * a.M + m];
     re += f * gr;
     im += f * gi;
   }
@@ -515,8 +552,8 @@ __global__ __launch_bounds__(256) void sigma_quad_kernel(
   }
   if (threadIdx.x == 0) {
     const double c = -1.0 / 3.14159265358979323846;
-    double* out = sigma + 2 * ((int64_t)q * Pd + k);
-    if (accumulate) {
+    double* out = a.sigma + 2 * ((int64_t)q * a.Pd + k);
+    if (a.accumulate) {
       out[0] += c * sre[0];
       out[1] += c * sim[0];
     } else {
@@ -524,6 +561,26 @@ __global__ __launch_bounds__(256) void sigma_quad_kernel(
       out[1] = c * sim[0];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void sigma_quad_kernel(QuadArgs a) {
+  sigma_quad_unit(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void sigma_quad_batched_kernel(Batch bt) {
+  const int d = find_problem(bt.off, bt.n, blockIdx.x);
+  const QuadArgs a = static_cast<const QuadArgs*>(bt.descs)[d];
+  sigma_quad_unit(a, (int)(blockIdx.x - bt.off[d]));
+}
+
+void launch_bwb(gw_ctx ctx, gw_precision prec, const BwbArgs& a, const Batch& bt,
+                int64_t grid) {
+  if (prec == GW_FP64)
+    hipLaunchKernelGGL(bwb_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a, bt);
+  else if (prec == GW_BF16X3)
+    hipLaunchKernelGGL(bwb_bf16x3_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a, bt);
+  else
+    hipLaunchKernelGGL(bwb_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a, bt);
 }
 
 }  // namespace
@@ -563,12 +620,7 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
   BwbArgs a{R_qp, W_hat, rows, N, ld_R, F, row_tiles, col_tiles, part};
   const int64_t grid = (int64_t)F * row_tiles * col_tiles;
   const int pi = gw::prof_begin(ctx);
-  if (prec == GW_FP64)
-    hipLaunchKernelGGL(bwb_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
-  else if (prec == GW_BF16X3)
-    hipLaunchKernelGGL(bwb_bf16x3_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
-  else
-    hipLaunchKernelGGL(bwb_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
+  launch_bwb(ctx, prec, a, Batch{}, grid);
   {
     const double esz = prec == GW_FP64 ? 8.0 : 4.0;
     // algorithmic work of the symmetric form: rows * N (N + 1) per frequency
@@ -578,9 +630,93 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
   }
   GW_TRY(gw::launch_check(ctx, "bwb kernel"));
   hipLaunchKernelGGL(w_reduce_kernel, dim3(grid_for((int64_t)F * rows, 256)), dim3(256), 0,
-                     ctx->stream, part, n_part, rows, F, W, W_nm);
+                     ctx->stream, WRedArgs{part, n_part, rows, F, W, W_nm});
   GW_TRY(gw::launch_check(ctx, "w_reduce_kernel"));
-  hipLaunchKernelGGL(sigma_quad_kernel, dim3(n_qp * n_pade), dim3(256), 0, ctx->stream, W, F,
-                     n_qp, n_mo, d_eps, eps_F, d_om, d_wt, d_op, n_pade, accumulate, sigma_iw);
+  hipLaunchKernelGGL(sigma_quad_kernel, dim3(n_qp * n_pade), dim3(256), 0, ctx->stream,
+                     QuadArgs{W, F, n_qp, n_mo, d_eps, eps_F, d_om, d_wt, d_op, n_pade,
+                              accumulate, sigma_iw});
   return gw::launch_check(ctx, "sigma_quad_kernel");
+}
+
+extern "C" gw_status gw_sigma_diag_batched(gw_ctx ctx, gw_precision prec, int n_jobs,
+                                           const gw_sigma_job* jobs, int accumulate) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_sigma_diag_batched: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_sigma_diag_batched: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_jobs >= 0 && (n_jobs == 0 || jobs), "gw_sigma_diag_batched: bad n_jobs");
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_sigma_job& j = jobs[d];
+    GW_REQUIRE(ctx, j.n_naf >= 1 && j.n_qp >= 1 && j.n_mo >= 1 && j.n_w >= 1 && j.n_pade >= 1,
+               "gw_sigma_diag_batched: job %d: bad sizes", d);
+    GW_REQUIRE(ctx, j.eps_mo && j.R_qp && j.omega && j.w_omega && j.W_hat && j.omega_pade &&
+                        j.sigma_iw,
+               "gw_sigma_diag_batched: job %d: NULL argument", d);
+    GW_REQUIRE(ctx, j.ld_R == 0 || j.ld_R >= j.n_naf, "gw_sigma_diag_batched: job %d: ld_R < n_naf", d);
+  }
+  if (n_jobs == 0) return GW_OK;
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  size_t part_tot = 0, w_tot = 0;
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_sigma_job& j = jobs[d];
+    const size_t rows = (size_t)j.n_qp * j.n_mo;
+    part_tot += (size_t)j.n_w * 2 * ((j.n_naf + BM - 1) / BM) * rows;
+    w_tot += (size_t)j.n_w * rows;
+  }
+  double* part = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_PART, part_tot * sizeof(double)));
+  double* W = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_W, w_tot * sizeof(double)));
+  if (!part || !W) return GW_ENOMEM;
+  std::vector<BwbArgs> bw;
+  std::vector<WRedArgs> red;
+  std::vector<QuadArgs> quad;
+  std::vector<int64_t> n_red;
+  size_t po = 0, wo = 0;
+  double flops = 0, bytes = 0;
+  const double esz = prec == GW_FP64 ? 8.0 : 4.0;
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_sigma_job& j = jobs[d];
+    const int N = j.n_naf, F = j.n_w;
+    const int64_t rows = (int64_t)j.n_qp * j.n_mo;
+    const double* d_eps = gw::stage_t(ctx, j.eps_mo, j.n_mo);
+    const double* d_om = gw::stage_t(ctx, j.omega, F);
+    const double* d_wt = gw::stage_t(ctx, j.w_omega, F);
+    const double* d_op = gw::stage_t(ctx, j.omega_pade, j.n_pade);
+    if (!d_eps || !d_om || !d_wt || !d_op) return GW_EINVAL;
+    const int row_tiles = (int)((rows + BM - 1) / BM);
+    const int col_tiles = (N + BM - 1) / BM;
+    const int n_part = 2 * col_tiles;
+    bw.push_back(BwbArgs{j.R_qp, j.W_hat, rows, N, j.ld_R ? j.ld_R : N, F, row_tiles, col_tiles,
+                         part + po});
+    red.push_back(WRedArgs{part + po, n_part, rows, F, W + wo, j.W_nm});
+    n_red.push_back((int64_t)F * rows);
+    quad.push_back(QuadArgs{W + wo, F, j.n_qp, j.n_mo, d_eps, j.eps_F, d_om, d_wt, d_op,
+                            j.n_pade, accumulate, j.sigma_iw});
+    po += (size_t)F * n_part * rows;
+    wo += (size_t)F * rows;
+    flops += (double)F * (double)rows * N * (N + 1.0);
+    bytes += (double)rows * N * esz + (double)F * N * (double)N * esz;
+  }
+  // longest work units first: rows of a unit are fixed, its length grows with N
+  std::vector<BwbArgs> order = bw;
+  std::stable_sort(order.begin(), order.end(),
+                   [](const BwbArgs& x, const BwbArgs& y) { return x.N > y.N; });
+  std::vector<int64_t> off(1, 0);
+  for (const BwbArgs& a : order) off.push_back(off.back() + (int64_t)a.F * a.row_tiles * a.col_tiles);
+  constexpr int CHUNK = 8;
+  Batch bt;
+  GW_TRY(gw::stage_batch(ctx, order, off, CHUNK, bt));
+  const int64_t grid = (off.back() + 8 * CHUNK - 1) / (8 * CHUNK) * (8 * CHUNK);
+  const int pi = gw::prof_begin(ctx);
+  launch_bwb(ctx, prec, BwbArgs{}, bt, grid);
+  gw::prof_end(ctx, pi, prec == GW_FP64 ? "bwb_f64" : (prec == GW_BF16X3 ? "bwb_bf16x3" : "bwb_f32"),
+               flops, bytes);
+  GW_TRY(gw::launch_check(ctx, "batched bwb kernel"));
+  GW_TRY(gw::elementwise_batched(ctx, red, n_red, w_reduce_batched_kernel, "w_reduce_batched"));
+  std::vector<int64_t> qoff(1, 0);
+  for (const QuadArgs& q : quad) qoff.push_back(qoff.back() + (int64_t)q.Q * q.Pd);
+  Batch bq;
+  GW_TRY(gw::stage_batch(ctx, quad, qoff, 1, bq));
+  hipLaunchKernelGGL(sigma_quad_batched_kernel, dim3((unsigned)qoff.back()), dim3(256), 0,
+                     ctx->stream, bq);
+  return gw::launch_check(ctx, "sigma_quad_batched_kernel");
 }

@@ -58,11 +58,13 @@ constexpr int NT32 = 512;
 constexpr int BK32 = 32;
 
 template <bool FAST, bool SCALED>
-__global__ __launch_bounds__(NT32, 2) void syrk_f32_kernel(SyrkArgs a) {
+__global__ __launch_bounds__(NT32, 2) void syrk_f32_kernel(SyrkArgs a0, Batch bt) {
   __shared__ float As[2][BK32][BM];
   __shared__ float Bs[2][BK32][BM];
 
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  SyrkArgs a;
+  int64_t lid;
+  if (!unit_of(a0, bt, a, lid)) return;
   const int m = (int)(lid % a.L);
   const int t = (int)((lid / a.L) % a.n_tiles);
   const int s = (int)(lid / ((int64_t)a.L * a.n_tiles));
@@ -217,13 +219,15 @@ __device__ __forceinline__ void split4(const float4 v, float s, bf16x4& hi, bf16
 }
 
 template <bool FAST, bool SCALED>
-__global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a) {
+__global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a0, Batch bt) {
   __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][LDB];
   __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][LDB];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BM][LDB];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BM][LDB];
 
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  SyrkArgs a;
+  int64_t lid;
+  if (!unit_of(a0, bt, a, lid)) return;
   const int m = (int)(lid % a.L);
   const int t = (int)((lid / a.L) % a.n_tiles);
   const int s = (int)(lid / ((int64_t)a.L * a.n_tiles));
@@ -359,11 +363,13 @@ __global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a) {
 // ------------------------------------------------------------------ FP64 MFMA
 constexpr int BK64 = 16;
 
-__global__ __launch_bounds__(NT, 1) void syrk_f64_kernel(SyrkArgs a) {
+__global__ __launch_bounds__(NT, 1) void syrk_f64_kernel(SyrkArgs a0, Batch bt) {
   __shared__ double As[2][BK64][BM];
   __shared__ double Bs[2][BK64][BM];
 
-  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  SyrkArgs a;
+  int64_t lid;
+  if (!unit_of(a0, bt, a, lid)) return;
   const int m = (int)(lid % a.L);
   const int t = (int)((lid / a.L) % a.n_tiles);
   const int s = (int)(lid / ((int64_t)a.L * a.n_tiles));
@@ -466,53 +472,107 @@ __global__ __launch_bounds__(NT, 1) void syrk_f64_kernel(SyrkArgs a) {
 }
 
 // Sum the split-K partials in a fixed order into the lower triangle of out.
-__global__ void syrk_reduce_kernel(const double* __restrict__ part, int splits,
-                                   int L, int n_tiles, int N, double* __restrict__ out,
-                                   int accumulate) {
+struct RedArgs {
+  const double* part;   // [splits][L][n_tiles][BM*BM]
+  int splits, L, n_tiles, N;
+  double* out;          // [L][N][N]
+  int accumulate;
+};
+
+__device__ __forceinline__ void reduce_elem(const RedArgs& r, int64_t idx) {
   const int64_t per_tile = BM * BM;
-  const int64_t total = (int64_t)L * n_tiles * per_tile;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int e = (int)(idx % per_tile);
-    const int t = (int)((idx / per_tile) % n_tiles);
-    const int m = (int)(idx / (per_tile * n_tiles));
-    int ti, tj;
-    tile_coords(t, ti, tj);
-    const int p = ti * BM + e / BM, q = tj * BM + e % BM;
-    if (p >= N || q >= N || q > p) continue;
-    double v = 0.0;
-    for (int s = 0; s < splits; ++s)
-      v += part[(((int64_t)s * L + m) * n_tiles + t) * per_tile + e];
-    double* dst = out + ((int64_t)m * N + p) * N + q;
-    *dst = accumulate ? *dst + v : v;
-  }
+  if (idx >= (int64_t)r.L * r.n_tiles * per_tile) return;
+  const int e = (int)(idx % per_tile);
+  const int t = (int)((idx / per_tile) % r.n_tiles);
+  const int m = (int)(idx / (per_tile * r.n_tiles));
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int p = ti * BM + e / BM, q = tj * BM + e % BM;
+  if (p >= r.N || q >= r.N || q > p) return;
+  double v = 0.0;
+  for (int s = 0; s < r.splits; ++s)
+    v += r.part[(((int64_t)s * r.L + m) * r.n_tiles + t) * per_tile + e];
+  double* dst = r.out + ((int64_t)m * r.N + p) * r.N + q;
+  *dst = r.accumulate ? *dst + v : v;
 }
 
-__global__ void mirror_kernel(double* M, int L, int N) {
-  const int64_t total = (int64_t)L * N * N;
+__global__ void syrk_reduce_kernel(RedArgs r) {
+  const int64_t total = (int64_t)r.L * r.n_tiles * BM * BM;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(idx % N);
-    const int p = (int)((idx / N) % N);
-    const int64_t m = idx / ((int64_t)N * N);
-    if (q > p) M[(m * N + p) * N + q] = M[(m * N + q) * N + p];
-  }
+       idx += (int64_t)gridDim.x * blockDim.x)
+    reduce_elem(r, idx);
+}
+
+__global__ void syrk_reduce_batched_kernel(Batch bt) {
+  RedArgs r;
+  int64_t first;
+  if (!block_of(bt, r, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) reduce_elem(r, first + e + threadIdx.x);
+}
+
+struct MirArgs {
+  double* M;
+  int L, N;
+};
+
+__device__ __forceinline__ void mirror_elem(const MirArgs& a, int64_t idx) {
+  if (idx >= (int64_t)a.L * a.N * a.N) return;
+  const int q = (int)(idx % a.N);
+  const int p = (int)((idx / a.N) % a.N);
+  const int64_t m = idx / ((int64_t)a.N * a.N);
+  if (q > p) a.M[(m * a.N + p) * a.N + q] = a.M[(m * a.N + q) * a.N + p];
+}
+
+__global__ void mirror_kernel(MirArgs a) {
+  const int64_t total = (int64_t)a.L * a.N * a.N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    mirror_elem(a, idx);
+}
+
+__global__ void mirror_batched_kernel(Batch bt) {
+  MirArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) mirror_elem(a, first + e + threadIdx.x);
+}
+
+// s_m(ia) = w_m D_ia exp(-D_ia^2 x_m) for every Laplace point and pair.
+struct ScaleArgs {
+  int L;
+  const double* x;
+  const double* w;
+  int n_i, n_virt;
+  const double* eps_i;
+  const double* eps_a;
+  void* out;            // [L][n_i * n_virt], FP64 or FP32
+};
+
+template <typename T>
+__device__ __forceinline__ void scale_elem(const ScaleArgs& s, int64_t idx) {
+  const int64_t k = (int64_t)s.n_i * s.n_virt;
+  if (idx >= k * s.L) return;
+  const int64_t r = idx % k;
+  const int m = (int)(idx / k);
+  const int i = (int)(r / s.n_virt), aa = (int)(r % s.n_virt);
+  const double d = s.eps_a[aa] - s.eps_i[i];
+  static_cast<T*>(s.out)[idx] = (T)(s.w[m] * d * exp(-d * d * s.x[m]));
 }
 
 template <typename T>
-__global__ void lt_scale_kernel(int L, const double* __restrict__ x,
-                                const double* __restrict__ w, int n_i, int n_virt,
-                                const double* __restrict__ eps_i,
-                                const double* __restrict__ eps_a, T* __restrict__ out) {
-  const int64_t k = (int64_t)n_i * n_virt;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < k * L;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = idx % k;
-    const int m = (int)(idx / k);
-    const int i = (int)(r / n_virt), aa = (int)(r % n_virt);
-    const double d = eps_a[aa] - eps_i[i];
-    out[idx] = (T)(w[m] * d * exp(-d * d * x[m]));
-  }
+__global__ void lt_scale_kernel(ScaleArgs s) {
+  const int64_t total = (int64_t)s.n_i * s.n_virt * s.L;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    scale_elem<T>(s, idx);
+}
+
+template <typename T>
+__global__ void lt_scale_batched_kernel(Batch bt) {
+  ScaleArgs s;
+  int64_t first;
+  if (!block_of(bt, s, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) scale_elem<T>(s, first + e + threadIdx.x);
 }
 
 inline int grid_for(int64_t n, int block) {
@@ -528,14 +588,13 @@ gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L, const double* d_
                           const double* d_w, int n_i, int n_virt,
                           const double* d_eps_i, const double* d_eps_a, void* scale) {
   const int64_t n = (int64_t)L * n_i * n_virt;
+  const ScaleArgs sa{L, d_x, d_w, n_i, n_virt, d_eps_i, d_eps_a, scale};
   if (prec == GW_FP64)
     hipLaunchKernelGGL(lt_scale_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0,
-                       ctx->stream, L, d_x, d_w, n_i, n_virt, d_eps_i, d_eps_a,
-                       static_cast<double*>(scale));
+                       ctx->stream, sa);
   else
     hipLaunchKernelGGL(lt_scale_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0,
-                       ctx->stream, L, d_x, d_w, n_i, n_virt, d_eps_i, d_eps_a,
-                       static_cast<float*>(scale));
+                       ctx->stream, sa);
   return launch_check(ctx, "lt_scale_kernel");
 }
 
@@ -552,13 +611,37 @@ static int choose_splits(int64_t k_rows, int64_t units) {
   return best;
 }
 
+static int64_t split_align(gw_precision prec) {
+  return prec == GW_FP64 ? BK64 : (prec == GW_BF16X3 ? BKB : FLUSH_ROWS);
+}
+
+static void launch_syrk_kernel(gw_ctx ctx, gw_precision prec, bool fast, bool scaled,
+                               const SyrkArgs& a, const Batch& bt, int64_t grid) {
+  if (prec == GW_FP64) {
+    hipLaunchKernelGGL(syrk_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a, bt);
+  } else if (prec == GW_BF16X3) {
+    auto kern = fast ? (scaled ? syrk_bf16x3_kernel<true, true> : syrk_bf16x3_kernel<true, false>)
+                     : (scaled ? syrk_bf16x3_kernel<false, true> : syrk_bf16x3_kernel<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NTB), 0, ctx->stream, a, bt);
+  } else {
+    auto kern = fast ? (scaled ? syrk_f32_kernel<true, true> : syrk_f32_kernel<true, false>)
+                     : (scaled ? syrk_f32_kernel<false, true> : syrk_f32_kernel<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT32), 0, ctx->stream, a, bt);
+  }
+}
+
+static bool fast_rows(gw_precision prec, const void* X, int64_t ld) {
+  return prec != GW_FP64 && (ld % 4 == 0) && ld >= 4 &&
+         (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+}
+
 gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_rows,
                       int N, int64_t ld, int L, const void* scale, double cscale,
                       double* out, int accumulate, const char* prof_name) {
   const int T = (N + BM - 1) / BM;
   const int n_tiles = T * (T + 1) / 2;
   const int S = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
-  const int64_t align = prec == GW_FP64 ? BK64 : (prec == GW_BF16X3 ? BKB : FLUSH_ROWS);
+  const int64_t align = split_align(prec);
   int64_t rps = (k_rows + S - 1) / S;
   rps = (rps + align - 1) / align * align;
   const size_t part_bytes = (size_t)S * L * n_tiles * BM * BM * sizeof(double);
@@ -567,19 +650,7 @@ gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_ro
   SyrkArgs a{X, k_rows, N, ld, L, scale, cscale, T, n_tiles, S, rps, part};
   const int64_t grid = (int64_t)S * L * n_tiles;
   const int pi = prof_begin(ctx);
-  const bool fast = prec != GW_FP64 && (ld % 4 == 0) && ld >= 4 &&
-                    (reinterpret_cast<uintptr_t>(X) % 16 == 0);
-  if (prec == GW_FP64) {
-    hipLaunchKernelGGL(syrk_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a);
-  } else if (prec == GW_BF16X3) {
-    auto kern = fast ? (scale ? syrk_bf16x3_kernel<true, true> : syrk_bf16x3_kernel<true, false>)
-                     : (scale ? syrk_bf16x3_kernel<false, true> : syrk_bf16x3_kernel<false, false>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NTB), 0, ctx->stream, a);
-  } else {
-    auto kern = fast ? (scale ? syrk_f32_kernel<true, true> : syrk_f32_kernel<true, false>)
-                     : (scale ? syrk_f32_kernel<false, true> : syrk_f32_kernel<false, false>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT32), 0, ctx->stream, a);
-  }
+  launch_syrk_kernel(ctx, prec, fast_rows(prec, X, ld), scale != nullptr, a, Batch{}, grid);
   // algorithmic work: L lower-triangle products of 2 k flops each; X read
   // once, the triangle written once
   const double esz = prec == GW_FP64 ? 8.0 : 4.0;
@@ -588,16 +659,114 @@ gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_ro
            (double)k_rows * N * esz + (double)L * N * (N + 1.0) / 2.0 * 8.0);
   GW_TRY(launch_check(ctx, "syrk kernel"));
   const int64_t tot = (int64_t)L * n_tiles * BM * BM;
-  hipLaunchKernelGGL(syrk_reduce_kernel, dim3(grid_for(tot, 256)), dim3(256), 0,
-                     ctx->stream, part, S, L, n_tiles, N, out, accumulate);
+  const RedArgs r{part, S, L, n_tiles, N, out, accumulate};
+  hipLaunchKernelGGL(syrk_reduce_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, ctx->stream, r);
   return launch_check(ctx, "syrk_reduce_kernel");
 }
 
 gw_status mirror_lower(gw_ctx ctx, double* M, int L, int N) {
   const int64_t tot = (int64_t)L * N * N;
   hipLaunchKernelGGL(mirror_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, ctx->stream,
-                     M, L, N);
+                     MirArgs{M, L, N});
   return launch_check(ctx, "mirror_kernel");
+}
+
+// ------------------------------------------------------------------ batched
+
+gw_status lt_scale_batched(gw_ctx ctx, gw_precision prec, const std::vector<ScaleJob>& jobs) {
+  std::vector<ScaleArgs> d;
+  std::vector<int64_t> n;
+  for (const ScaleJob& j : jobs) {
+    d.push_back(ScaleArgs{j.L, j.x, j.w, j.n_i, j.n_virt, j.eps_i, j.eps_a, j.out});
+    n.push_back((int64_t)j.L * j.n_i * j.n_virt);
+  }
+  return elementwise_batched(ctx, d, n, prec == GW_FP64 ? lt_scale_batched_kernel<double>
+                                                        : lt_scale_batched_kernel<float>,
+                             "lt_scale_batched_kernel");
+}
+
+gw_status mirror_lower_batched(gw_ctx ctx, const std::vector<MirrorJob>& jobs) {
+  std::vector<MirArgs> d;
+  std::vector<int64_t> n;
+  for (const MirrorJob& j : jobs) {
+    d.push_back(MirArgs{j.M, j.L, j.N});
+    n.push_back((int64_t)j.L * j.N * j.N);
+  }
+  return elementwise_batched(ctx, d, n, mirror_batched_kernel, "mirror_batched_kernel");
+}
+
+// All jobs' tiles in one launch.  Jobs must agree on whether they carry a
+// per-row scale.  Split-K: a job's rows are split so that no work unit is
+// much longer than twice the mean, and the descriptors are ordered by unit
+// length, longest first, so the long units start first.
+gw_status syrk_batched_launch(gw_ctx ctx, gw_precision prec, const std::vector<SyrkJob>& jobs,
+                              const char* prof_name) {
+  if (jobs.empty()) return GW_OK;
+  const bool scaled = jobs[0].scale != nullptr;
+  double w_units = 0, w_rows = 0;
+  for (const SyrkJob& j : jobs) {
+    if ((j.scale != nullptr) != scaled)
+      return fail(ctx, GW_EINVAL, "batched SYRK: jobs mix scaled and unscaled rows");
+    const int T = (j.N + BM - 1) / BM;
+    const double u = (double)j.L * T * (T + 1) / 2;
+    w_units += u;
+    w_rows += u * (double)j.k_rows;
+  }
+  const int64_t align = split_align(prec);
+  const int64_t target = std::max<int64_t>(4096, (int64_t)(2.0 * w_rows / std::max(w_units, 1.0)));
+  struct Item { SyrkArgs a; RedArgs r; int64_t units; };
+  std::vector<Item> items;
+  size_t part_total = 0;
+  bool fast = true;
+  for (const SyrkJob& j : jobs) {
+    const int T = (j.N + BM - 1) / BM;
+    const int n_tiles = T * (T + 1) / 2;
+    const int S = (int)std::min<int64_t>(16, std::max<int64_t>(1, (j.k_rows + target - 1) / target));
+    int64_t rps = (j.k_rows + S - 1) / S;
+    rps = std::max<int64_t>(align, (rps + align - 1) / align * align);
+    Item it;
+    it.a = SyrkArgs{j.X, j.k_rows, j.N, j.ld, j.L, j.scale, j.cscale, T, n_tiles, S, rps,
+                    reinterpret_cast<double*>(part_total)};
+    it.r = RedArgs{nullptr, S, j.L, n_tiles, j.N, j.out, j.accumulate};
+    it.units = (int64_t)S * j.L * n_tiles;
+    part_total += (size_t)it.units * BM * BM;
+    fast = fast && (j.k_rows == 0 || fast_rows(prec, j.X, j.ld));
+    items.push_back(it);
+  }
+  double* part = static_cast<double*>(ws_get(ctx, WS_SYRK_PART, part_total * sizeof(double)));
+  if (!part) return GW_ENOMEM;
+  for (Item& it : items) {
+    it.a.part = part + reinterpret_cast<size_t>(it.a.part);
+    it.r.part = it.a.part;
+  }
+  std::vector<SyrkArgs> order;
+  for (const Item& it : items) order.push_back(it.a);
+  std::stable_sort(order.begin(), order.end(), [](const SyrkArgs& x, const SyrkArgs& y) {
+    return x.rows_per_split > y.rows_per_split;
+  });
+  std::vector<int64_t> off(1, 0);
+  double flops = 0, bytes = 0;
+  const double esz = prec == GW_FP64 ? 8.0 : 4.0;
+  for (const SyrkArgs& a : order) {
+    off.push_back(off.back() + (int64_t)a.splits * a.L * a.n_tiles);
+    flops += (double)a.L * a.N * (a.N + 1.0) * (double)a.k_rows;
+    bytes += (double)a.k_rows * a.N * esz + (double)a.L * a.N * (a.N + 1.0) / 2.0 * 8.0;
+  }
+  constexpr int CHUNK = 8;
+  Batch bt;
+  GW_TRY(stage_batch(ctx, order, off, CHUNK, bt));
+  const int64_t grid = (off.back() + 8 * CHUNK - 1) / (8 * CHUNK) * (8 * CHUNK);
+  const int pi = prof_begin(ctx);
+  launch_syrk_kernel(ctx, prec, fast, scaled, SyrkArgs{}, bt, grid);
+  prof_end(ctx, pi, prof_name, flops, bytes);
+  GW_TRY(launch_check(ctx, "batched syrk kernel"));
+  std::vector<RedArgs> red;
+  std::vector<int64_t> n;
+  for (const Item& it : items) {
+    red.push_back(it.r);
+    n.push_back((int64_t)it.r.L * it.r.n_tiles * BM * BM);
+  }
+  return elementwise_batched(ctx, red, n, syrk_reduce_batched_kernel, "syrk_reduce_batched");
 }
 
 }  // namespace gw
@@ -638,5 +807,83 @@ extern "C" gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_n
                          prec == GW_FP64 ? "chi_syrk_f64"
                                          : (prec == GW_BF16X3 ? "chi_syrk_bf16x3" : "chi_syrk_f32")));
   if (finalize) GW_TRY(gw::mirror_lower(ctx, M, n_lt, n_naf));
+  return GW_OK;
+}
+
+namespace {
+
+__global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+}  // namespace
+
+namespace gw {
+
+gw_status fill_zero(gw_ctx ctx, double* p, int64_t n) {
+  if (n <= 0) return GW_OK;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream, p, n);
+  return launch_check(ctx, "fill_zero_kernel");
+}
+
+}  // namespace gw
+
+extern "C" gw_status gw_polarizability_lt_batched(gw_ctx ctx, gw_precision prec, int n_lt,
+                                                  int n_jobs, const gw_chi_job* jobs,
+                                                  int accumulate, int finalize) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_polarizability_lt_batched: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_polarizability_lt_batched: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_lt >= 1 && n_lt <= 32 && n_jobs >= 0 && (n_jobs == 0 || jobs),
+             "gw_polarizability_lt_batched: bad sizes (n_lt=%d n_jobs=%d)", n_lt, n_jobs);
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_chi_job& j = jobs[d];
+    GW_REQUIRE(ctx, j.n_naf >= 1 && j.n_i >= 0 && j.n_virt >= 1,
+               "gw_polarizability_lt_batched: job %d: bad sizes", d);
+    GW_REQUIRE(ctx, j.x_lt && j.w_lt && j.M && j.eps_a && (j.n_i == 0 || (j.eps_i && j.R_chunk)),
+               "gw_polarizability_lt_batched: job %d: NULL argument", d);
+    GW_REQUIRE(ctx, j.ld_R == 0 || j.ld_R >= j.n_naf,
+               "gw_polarizability_lt_batched: job %d: ld_R < n_naf", d);
+  }
+  if (n_jobs == 0) return GW_OK;
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  const size_t esz = prec == GW_FP64 ? 8 : 4;
+  size_t scale_total = 0;
+  for (int d = 0; d < n_jobs; ++d)
+    scale_total += (size_t)n_lt * jobs[d].n_i * jobs[d].n_virt;
+  unsigned char* scale = static_cast<unsigned char*>(
+      gw::ws_get(ctx, WS_SYRK_SCALE, std::max<size_t>(scale_total, 1) * esz));
+  if (!scale) return GW_ENOMEM;
+  std::vector<gw::ScaleJob> sj;
+  std::vector<gw::SyrkJob> kj;
+  std::vector<gw::MirrorJob> mj;
+  size_t so = 0;
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_chi_job& j = jobs[d];
+    const int64_t k = (int64_t)j.n_i * j.n_virt;
+    void* sc = scale + so * esz;
+    if (k > 0) {
+      const double* dx = gw::stage_t(ctx, j.x_lt, n_lt);
+      const double* dw = gw::stage_t(ctx, j.w_lt, n_lt);
+      const double* dei = gw::stage_t(ctx, j.eps_i, j.n_i);
+      const double* dea = gw::stage_t(ctx, j.eps_a, j.n_virt);
+      if (!dx || !dw || !dei || !dea) return GW_EINVAL;
+      sj.push_back(gw::ScaleJob{n_lt, dx, dw, j.n_i, j.n_virt, dei, dea, sc});
+    }
+    // jobs without rows still zero (or keep) their output; their scale
+    // pointer is never read
+    kj.push_back(gw::SyrkJob{j.R_chunk, k, j.n_naf, j.ld_R ? j.ld_R : j.n_naf, n_lt, sc, 1.0,
+                             j.M, accumulate});
+    mj.push_back(gw::MirrorJob{j.M, n_lt, j.n_naf});
+    so += (size_t)n_lt * k;
+  }
+  GW_TRY(gw::lt_scale_batched(ctx, prec, sj));
+  GW_TRY(gw::syrk_batched_launch(ctx, prec, kj,
+                                 prec == GW_FP64 ? "chi_syrk_f64"
+                                 : (prec == GW_BF16X3 ? "chi_syrk_bf16x3" : "chi_syrk_f32")));
+  if (finalize) GW_TRY(gw::mirror_lower_batched(ctx, mj));
   return GW_OK;
 }

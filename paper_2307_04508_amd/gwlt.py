@@ -28,7 +28,10 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_set_stream", "gw_sync", "gw_last_error
            "gw_status_string", "gw_prepare", "gw_freq_grid_mgl", "gw_lt_grid_minimax",
            "gw_minimax_inverse", "gw_profile_enable", "gw_profile_get",
            "gw_naf_compress", "gw_naf_apply", "gw_polarizability_lt", "gw_screen",
-           "gw_sigma_diag", "gw_qp_solve", "gw_g0w0"]
+           "gw_sigma_diag", "gw_qp_solve", "gw_g0w0",
+           "gw_graph_begin", "gw_graph_end", "gw_graph_launch", "gw_graph_destroy",
+           "gw_polarizability_lt_batched", "gw_screen_batched", "gw_sigma_diag_batched",
+           "gw_qp_solve_batched", "gw_g0w0_batched"]
 
 c_int, c_i64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_DBL = ctypes.POINTER(ctypes.c_double)
@@ -47,6 +50,50 @@ class GwStats(ctypes.Structure):
                 ("t_chi_ms", c_dbl), ("t_screen_ms", c_dbl), ("t_sigma_ms", c_dbl),
                 ("t_qp_ms", c_dbl), ("t_total_ms", c_dbl)]
 
+
+class ChiJob(ctypes.Structure):
+    _fields_ = [("n_naf", c_int), ("n_i", c_int), ("n_virt", c_int), ("x_lt", P_DBL),
+                ("w_lt", P_DBL), ("eps_i", P_DBL), ("eps_a", P_DBL), ("R_chunk", c_vp),
+                ("ld_R", c_i64), ("M", c_vp)]
+
+
+class ScreenJob(ctypes.Structure):
+    _fields_ = [("n_naf", c_int), ("x_lt", P_DBL), ("M", c_vp), ("n_w", c_int),
+                ("omega", P_DBL), ("W_hat", c_vp)]
+
+
+class SigmaJob(ctypes.Structure):
+    _fields_ = [("n_naf", c_int), ("n_qp", c_int), ("n_mo", c_int), ("eps_mo", P_DBL),
+                ("eps_F", c_dbl), ("R_qp", c_vp), ("ld_R", c_i64), ("n_w", c_int),
+                ("omega", P_DBL), ("w_omega", P_DBL), ("W_hat", c_vp), ("n_pade", c_int),
+                ("omega_pade", P_DBL), ("sigma_iw", c_vp), ("W_nm", c_vp)]
+
+
+class QpJob(ctypes.Structure):
+    _fields_ = [("n_qp", c_int), ("eps_n", P_DBL), ("static_n", P_DBL), ("eps_F", c_dbl),
+                ("n_pade", c_int), ("omega_pade", P_DBL), ("sigma_iw", c_vp),
+                ("eps_qp", P_DBL), ("z_factor", P_DBL), ("status", P_INT)]
+
+
+class Mol(ctypes.Structure):
+    _fields_ = [("n_occ", c_int), ("n_fc", c_int), ("n_virt", c_int), ("n_aux", c_int),
+                ("n_qp", c_int), ("eps_naf", c_dbl), ("max_keep", c_int), ("eps", P_DBL),
+                ("qp", P_INT), ("static_n", P_DBL), ("R_oo", c_vp), ("R_ov", c_vp),
+                ("R_qp", c_vp), ("eps_qp", P_DBL), ("z_factor", P_DBL), ("status", P_INT),
+                ("sigma_iw", P_DBL), ("n_naf", c_int)]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [("n_lt", c_int), ("n_freq", c_int), ("n_pade", c_int), ("x0", c_dbl),
+                ("eta", c_dbl), ("tol", c_dbl), ("max_iter", c_int)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("t_naf_ms", c_dbl), ("t_rest_ms", c_dbl), ("t_total_ms", c_dbl),
+                ("graph_replayed", c_int)]
+
+
+GW_BATCH_GRAPH = 1
 
 _sig = {
     "gw_create": [ctypes.POINTER(c_vp), c_int, c_vp],
@@ -71,6 +118,17 @@ _sig = {
                     P_DBL, P_DBL, P_INT],
     "gw_g0w0": [c_vp, c_int, ctypes.POINTER(GwParams), P_DBL, P_INT, P_DBL, c_vp, c_vp, c_vp,
                 P_DBL, P_DBL, P_INT, P_DBL, ctypes.POINTER(GwStats)],
+    "gw_graph_begin": [c_vp],
+    "gw_graph_end": [c_vp, ctypes.POINTER(c_vp)],
+    "gw_graph_launch": [c_vp, c_vp],
+    "gw_graph_destroy": [c_vp],
+    "gw_polarizability_lt_batched": [c_vp, c_int, c_int, c_int, ctypes.POINTER(ChiJob), c_int,
+                                     c_int],
+    "gw_screen_batched": [c_vp, c_int, c_int, c_int, ctypes.POINTER(ScreenJob)],
+    "gw_sigma_diag_batched": [c_vp, c_int, c_int, ctypes.POINTER(SigmaJob), c_int],
+    "gw_qp_solve_batched": [c_vp, c_int, ctypes.POINTER(QpJob), c_dbl, c_dbl, c_int],
+    "gw_g0w0_batched": [c_vp, c_int, ctypes.POINTER(BatchParams), c_int, ctypes.POINTER(Mol),
+                        c_int, ctypes.POINTER(BatchStats)],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -285,3 +343,144 @@ def params_for(cfg, freq_batch: int = 0, tol: float = 1e-6, max_iter: int = 100)
                     n_lt=cfg.n_lt, n_freq=cfg.n_freq, n_pade=cfg.n_pade, n_qp=cfg.n_qp,
                     eps_naf=cfg.eps_naf, max_keep=cfg.max_keep, x0=cfg.x0, eta=cfg.eta,
                     tol=tol, max_iter=max_iter, freq_batch=freq_batch)
+
+
+# ------------------------------------------------------------------ graphs
+
+class Graph:
+    """A captured graph (gw_graph_end); released by close() or gw_graph_destroy."""
+
+    def __init__(self, handle, ctx):
+        self.handle = handle
+        self.ctx = ctx
+
+    def close(self):
+        if self.handle:
+            _lib.gw_graph_destroy(self.handle)
+            self.handle = None
+
+
+def gw_graph_begin(ctx):
+    _check(_lib.gw_graph_begin(ctx.handle), ctx)
+
+
+def gw_graph_end(ctx) -> Graph:
+    h = c_vp()
+    _check(_lib.gw_graph_end(ctx.handle, ctypes.byref(h)), ctx)
+    return Graph(h, ctx)
+
+
+def gw_graph_launch(ctx, graph: Graph):
+    _check(_lib.gw_graph_launch(ctx.handle, graph.handle), ctx)
+
+
+def gw_graph_destroy(graph: Graph):
+    graph.close()
+
+
+# ------------------------------------------------------------------ batched twins
+# Job arguments are dicts with the keyword names of the single-molecule call;
+# host arrays are converted and kept alive for the duration of the call.
+
+def _jobs(cls, rows):
+    arr = (cls * max(len(rows), 1))()
+    for i, r in enumerate(rows):
+        for k, v in r.items():
+            setattr(arr[i], k, v)
+    return arr
+
+
+def gw_polarizability_lt_batched(ctx, prec, n_lt, jobs, accumulate, finalize):
+    keep, rows = [], []
+    for j in jobs:
+        x, w, ei, ea = (_host(j["x_lt"]), _host(j["w_lt"]), _host(j["eps_i"]), _host(j["eps_a"]))
+        keep += [x, w, ei, ea]
+        R = j.get("R_chunk")
+        rows.append(dict(n_naf=j["n_naf"], n_i=j["n_i"], n_virt=j["n_virt"], x_lt=_dp(x),
+                         w_lt=_dp(w), eps_i=_dp(ei), eps_a=_dp(ea), R_chunk=_dev(R, True),
+                         ld_R=_ld(R, j["n_naf"]), M=_dev(j["M"])))
+    arr = _jobs(ChiJob, rows)
+    _check(_lib.gw_polarizability_lt_batched(ctx.handle, _prec(prec), n_lt, len(rows), arr,
+                                             int(accumulate), int(finalize)), ctx)
+
+
+def gw_screen_batched(ctx, prec, n_lt, jobs):
+    keep, rows = [], []
+    for j in jobs:
+        x, om = _host(j["x_lt"]), _host(j["omega"])
+        keep += [x, om]
+        rows.append(dict(n_naf=j["n_naf"], x_lt=_dp(x), M=_dev(j["M"]), n_w=len(om),
+                         omega=_dp(om), W_hat=_dev(j["W_hat"])))
+    arr = _jobs(ScreenJob, rows)
+    _check(_lib.gw_screen_batched(ctx.handle, _prec(prec), n_lt, len(rows), arr), ctx)
+
+
+def gw_sigma_diag_batched(ctx, prec, jobs, accumulate):
+    keep, rows = [], []
+    for j in jobs:
+        e, om, wt, op = (_host(j["eps_mo"]), _host(j["omega"]), _host(j["w_omega"]),
+                         _host(j["omega_pade"]))
+        keep += [e, om, wt, op]
+        R = j["R_qp"]
+        rows.append(dict(n_naf=j["n_naf"], n_qp=j["n_qp"], n_mo=j["n_mo"], eps_mo=_dp(e),
+                         eps_F=float(j["eps_F"]), R_qp=_dev(R, True), ld_R=_ld(R, j["n_naf"]),
+                         n_w=len(om), omega=_dp(om), w_omega=_dp(wt), W_hat=_dev(j["W_hat"]),
+                         n_pade=len(op), omega_pade=_dp(op), sigma_iw=_dev(j["sigma_iw"]),
+                         W_nm=_dev(j.get("W_nm"))))
+    arr = _jobs(SigmaJob, rows)
+    _check(_lib.gw_sigma_diag_batched(ctx.handle, _prec(prec), len(rows), arr, int(accumulate)),
+           ctx)
+
+
+def gw_qp_solve_batched(ctx, jobs, eta, tol=1e-6, max_iter=100):
+    """Returns a list of (eps_qp, z_factor, status) per job."""
+    keep, rows, outs = [], [], []
+    for j in jobs:
+        en, op = _host(j["eps_n"]), _host(j["omega_pade"])
+        st = None if j.get("static_n") is None else _host(j["static_n"])
+        q = len(en)
+        E, Z, S = np.empty(q), np.empty(q), np.empty(q, dtype=np.int32)
+        keep += [en, op, st]
+        outs.append((E, Z, S))
+        rows.append(dict(n_qp=q, eps_n=_dp(en), static_n=_dp(st), eps_F=float(j["eps_F"]),
+                         n_pade=len(op), omega_pade=_dp(op), sigma_iw=_dev(j["sigma_iw"]),
+                         eps_qp=_dp(E), z_factor=_dp(Z), status=_ip(S)))
+    arr = _jobs(QpJob, rows)
+    _check(_lib.gw_qp_solve_batched(ctx.handle, len(rows), arr, float(eta), float(tol),
+                                    int(max_iter)), ctx)
+    return outs
+
+
+def batch_params_for(cfg, tol: float = 1e-6, max_iter: int = 100) -> BatchParams:
+    return BatchParams(n_lt=cfg.n_lt, n_freq=cfg.n_freq, n_pade=cfg.n_pade, x0=cfg.x0,
+                       eta=cfg.eta, tol=tol, max_iter=max_iter)
+
+
+def gw_g0w0_batched(ctx, prec, params: BatchParams, mols, graph=True, want_sigma=False):
+    """mols: list of dicts with cfg (n_occ, n_fc, n_virt, n_aux, eps_naf, max_keep),
+    eps, qp, R_oo, R_ov, R_qp (device) and optionally static_n.  Returns
+    (list of (eps_qp, z, status, sigma or None, n_naf), BatchStats)."""
+    keep, rows, outs = [], [], []
+    for m in mols:
+        c = m["cfg"]
+        e, q = _host(m["eps"]), _host(m["qp"], np.int32)
+        st = None if m.get("static_n") is None else _host(m["static_n"])
+        nq = len(q)
+        E, Z, S = np.empty(nq), np.empty(nq), np.empty(nq, dtype=np.int32)
+        sig = np.empty(2 * nq * params.n_pade) if want_sigma else None
+        keep += [e, q, st]
+        outs.append((E, Z, S, sig))
+        rows.append(dict(n_occ=c.n_occ, n_fc=c.n_fc, n_virt=c.n_virt, n_aux=c.n_aux, n_qp=nq,
+                         eps_naf=float(c.eps_naf), max_keep=int(c.max_keep), eps=_dp(e),
+                         qp=_ip(q), static_n=_dp(st), R_oo=_dev(m["R_oo"]),
+                         R_ov=_dev(m["R_ov"]), R_qp=_dev(m["R_qp"]), eps_qp=_dp(E),
+                         z_factor=_dp(Z), status=_ip(S), sigma_iw=_dp(sig), n_naf=0))
+    arr = _jobs(Mol, rows)
+    stats = BatchStats()
+    _check(_lib.gw_g0w0_batched(ctx.handle, _prec(prec), ctypes.byref(params), len(rows), arr,
+                                GW_BATCH_GRAPH if graph else 0, ctypes.byref(stats)), ctx)
+    res = []
+    for i, (E, Z, S, sig) in enumerate(outs):
+        s2 = None if sig is None else (sig[0::2] + 1j * sig[1::2]).reshape(len(E), params.n_pade)
+        res.append((E, Z, S, s2, arr[i].n_naf))
+    return res, stats

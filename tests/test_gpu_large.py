@@ -52,7 +52,9 @@ def large():
     _say("generating the large problem on the device (FP64)")
     p = make_problem_device(get_config("large"), device="cuda", dtype=torch.float64)
     torch.cuda.synchronize()
-    return p
+    yield p
+    del p
+    torch.cuda.empty_cache()
 
 
 def _f32(t):

@@ -33,3 +33,15 @@ def test_device_problem_matches_host_problem():
     ch = d.ov_chunk(3, 6, torch.float32).numpy()
     assert np.max(np.abs(ch - h.R_ov[3 * v:6 * v])) <= 1e-6 * np.max(np.abs(h.R_ov))
     assert o * v == h.R_ov.shape[0]
+    oc = d.oo_chunk(2, 5, torch.float64).numpy()
+    assert np.max(np.abs(oc - h.R_oo[2:5].reshape(-1, cfg.n_aux))) <= 1e-14 * np.max(np.abs(a))
+
+
+def test_haar_on_device_matches_host_qr():
+    cfg = get_config("medium").with_(n_occ=12, n_fc=4, n_virt=30, n_aux=64, naf_target=32,
+                                     n_qp_occ=2, n_qp_virt=2)
+    h = make_problem(cfg)
+    d = make_problem_device(cfg, device="cpu", haar_on_device=True)
+    assert np.array_equal(h.eps, d.eps)
+    a, b = h.R_ov, d.R_ov.numpy()
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
