@@ -275,6 +275,31 @@ gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* params,
                   double* eps_qp, double* z_factor, int* status,
                   double* sigma_iw, gw_stats* stats);
 
+/* ----------------------------------------------------------- workspace */
+
+/* Largest sizes the per-step calls will see on a context. */
+typedef struct {
+  int n_aux;        /* raw auxiliary functions (NAF metric and transform)    */
+  int n_naf;        /* natural auxiliary functions                            */
+  int n_occ_act;    /* active occupied orbitals                               */
+  int n_virt;       /* virtual orbitals                                       */
+  int n_mo;         /* orbitals in the self-energy sum (active)               */
+  int n_qp;         /* QP states                                              */
+  int n_lt;         /* Laplace points                                         */
+  int n_w;          /* frequencies per gw_screen / gw_sigma_diag call         */
+  int n_pade;       /* Pade nodes                                             */
+  int chunk_i;      /* occupied orbitals per chunk of the chunked calls,
+                       0 = all of them                                        */
+} gw_dims;
+
+/* Grow the context's workspace now to what gw_naf_compress (metric part),
+ * gw_naf_apply, gw_polarizability_lt, gw_screen, gw_sigma_diag and
+ * gw_qp_solve need for sizes up to *dims in precision prec, so that later
+ * calls within those sizes allocate nothing (in particular while being
+ * captured into a graph).  The workspace never shrinks while the context
+ * lives. */
+gw_status gw_reserve(gw_ctx ctx, gw_precision prec, const gw_dims* dims);
+
 /* ------------------------------------------------------ graph capture */
 
 /* Capture the device work of the following calls on ctx into a HIP graph
@@ -305,6 +330,41 @@ gw_status gw_graph_destroy(gw_graph graph);
  * kernel: every work unit (tile, frequency, QP state) of every job goes
  * into one grid, longest units first.  Arguments per job mean what they
  * mean in the single call. */
+
+/* Eqs. 11-13 for each job (see gw_naf_compress): both metric contributions
+ * of every job in two launches, then the FP64 eigendecompositions as
+ * batched divide-and-conquer solves over groups of similar n_aux (each
+ * metric padded with a decoupled -1 diagonal block, which the exact block
+ * structure keeps out of the kept eigenvectors).  Always finalises: K is
+ * destroyed, U receives the eigenvectors as rows (descending), n_naf the
+ * kept count, eigvals (host, may be NULL) the eigenvalues.  Synchronises. */
+typedef struct {
+  int n_aux;
+  int64_t n_oo_rows;
+  const void* R_oo;         /* device [n_oo_rows][n_aux] */
+  int64_t n_ov_rows;
+  const void* R_ov;         /* device [n_ov_rows][n_aux] */
+  double* K;                /* device [n_aux][n_aux] FP64 work */
+  double eps_naf;
+  int max_keep;
+  double* U;                /* device [n_aux][n_aux] FP64 */
+  int n_naf;                /* out */
+  double* eigvals;          /* host [n_aux] or NULL */
+} gw_naf_job;
+gw_status gw_naf_compress_batched(gw_ctx ctx, gw_precision prec, int n_jobs,
+                                  gw_naf_job* jobs);
+
+/* Eq. 13 for each job (see gw_naf_apply), one launch. */
+typedef struct {
+  int n_aux, n_naf;
+  const double* U;          /* device, as from the compression */
+  int64_t n_rows;
+  const void* R_in;         /* device [n_rows][n_aux] */
+  void* R_out;              /* device [n_rows][ld_out] */
+  int64_t ld_out;           /* 0 = n_naf */
+} gw_naf_apply_job;
+gw_status gw_naf_apply_batched(gw_ctx ctx, gw_precision prec, int n_jobs,
+                               const gw_naf_apply_job* jobs);
 
 /* Eq. 10 for each job (see gw_polarizability_lt); all jobs share n_lt. */
 typedef struct {

@@ -189,6 +189,10 @@ struct NafGemmJob {
   int64_t ldc;
 };
 gw_status naf_gemm_batched(gw_ctx ctx, gw_precision prec, const std::vector<NafGemmJob>& jobs);
+// Workspace each call needs at given sizes (gw_reserve).
+size_t syrk_part_bytes(gw_precision prec, int64_t k_rows, int N, int L);
+void screen_ws_bytes(gw_precision prec, int N, int F, size_t* a_bytes, size_t* panel_bytes);
+void sigma_ws_bytes(int N, int64_t rows, int F, size_t* part_bytes, size_t* w_bytes);
 // Zero n doubles with a kernel (capturable, unlike hipMemsetAsync).
 gw_status fill_zero(gw_ctx ctx, double* p, int64_t n);
 gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L,

@@ -1,4 +1,5 @@
 // Context lifetime, workspace, staging and error reporting.
+#include <algorithm>
 #include <cstdarg>
 
 #include "common.hpp"
@@ -210,6 +211,48 @@ gw_status end_capture(gw_ctx ctx, gw_graph_s* out) {
 }  // namespace gw
 
 extern "C" {
+
+gw_status gw_reserve(gw_ctx ctx, gw_precision prec, const gw_dims* d) {
+  if (!ctx || !d) return gw::fail(ctx, GW_EINVAL, "gw_reserve: NULL argument");
+  gw::clear_error(ctx);
+  if (ctx->capturing) return gw::fail(ctx, GW_EUNSUPPORTED, "gw_reserve inside a graph capture");
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_reserve: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, d->n_aux >= 0 && d->n_naf >= 0 && d->n_occ_act >= 0 && d->n_virt >= 0 &&
+                      d->n_mo >= 0 && d->n_qp >= 0 && d->n_lt >= 0 && d->n_w >= 0 &&
+                      d->n_pade >= 0 && d->chunk_i >= 0,
+             "gw_reserve: negative size");
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  const int ci = d->chunk_i > 0 ? std::min(d->chunk_i, d->n_occ_act) : d->n_occ_act;
+  const int64_t k_chi = (int64_t)ci * d->n_virt;
+  const int64_t k_oo = (int64_t)ci * d->n_occ_act;
+  const gw_precision mp = prec == GW_FP64 ? GW_FP64 : GW_FP32;
+  const size_t esz = prec == GW_FP64 ? 8 : 4;
+  size_t part = 0;
+  if (d->n_naf > 0 && d->n_lt > 0) part = gw::syrk_part_bytes(prec, k_chi, d->n_naf, d->n_lt);
+  if (d->n_aux > 0) {
+    part = std::max(part, gw::syrk_part_bytes(mp, k_chi, d->n_aux, 1));
+    part = std::max(part, gw::syrk_part_bytes(mp, k_oo, d->n_aux, 1));
+  }
+  size_t sa = 0, sp = 0, gp = 0, gwb = 0;
+  if (d->n_naf > 0 && d->n_w > 0) {
+    gw::screen_ws_bytes(prec, d->n_naf, d->n_w, &sa, &sp);
+    gw::sigma_ws_bytes(d->n_naf, (int64_t)d->n_qp * d->n_mo, d->n_w, &gp, &gwb);
+  }
+  const struct { WsSlot slot; size_t bytes; } want[] = {
+      {WS_SYRK_PART, part},
+      {WS_SYRK_SCALE, (size_t)d->n_lt * k_chi * esz},
+      {WS_SCREEN_A, sa},
+      {WS_SCREEN_PANEL, sp},
+      {WS_SIGMA_PART, gp},
+      {WS_SIGMA_W, gwb},
+      {WS_EIG, (2 * (size_t)d->n_aux + 8) * sizeof(double)},
+      {WS_QP, 3 * (size_t)d->n_qp * sizeof(double)},
+  };
+  for (const auto& w : want)
+    if (w.bytes > 0 && !gw::ws_get(ctx, w.slot, w.bytes)) return GW_ENOMEM;
+  return GW_OK;
+}
 
 gw_status gw_graph_begin(gw_ctx ctx) {
   if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_graph_begin: ctx is NULL");

@@ -537,3 +537,74 @@ gw_status naf_gemm_batched(gw_ctx ctx, gw_precision prec, const std::vector<NafG
 }
 
 }  // namespace gw
+
+extern "C" gw_status gw_naf_compress_batched(gw_ctx ctx, gw_precision prec, int n_jobs,
+                                             gw_naf_job* jobs) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_naf_compress_batched: ctx is NULL");
+  gw::clear_error(ctx);
+  if (ctx->capturing)
+    return gw::fail(ctx, GW_EUNSUPPORTED,
+                    "gw_naf_compress_batched: the eigensolver synchronises and cannot be captured");
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_naf_compress_batched: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_jobs >= 0 && (n_jobs == 0 || jobs), "gw_naf_compress_batched: bad n_jobs");
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_naf_job& j = jobs[d];
+    GW_REQUIRE(ctx, j.n_aux >= 1 && j.n_oo_rows >= 0 && j.n_ov_rows >= 0 && j.max_keep >= 0,
+               "gw_naf_compress_batched: job %d: bad sizes", d);
+    GW_REQUIRE(ctx, j.K && j.U && (j.n_oo_rows == 0 || j.R_oo) && (j.n_ov_rows == 0 || j.R_ov),
+               "gw_naf_compress_batched: job %d: NULL argument", d);
+  }
+  if (n_jobs == 0) return GW_OK;
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  const gw_precision mp = prec == GW_FP64 ? GW_FP64 : GW_FP32;
+  std::vector<gw::SyrkJob> oo, ov;
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_naf_job& j = jobs[d];
+    oo.push_back(gw::SyrkJob{j.R_oo, j.n_oo_rows, j.n_aux, j.n_aux, 1, nullptr, 2.0, j.K, 0});
+    ov.push_back(gw::SyrkJob{j.R_ov, j.n_ov_rows, j.n_aux, j.n_aux, 1, nullptr, 4.0, j.K, 1});
+  }
+  GW_TRY(gw::syrk_batched_launch(ctx, mp, oo, "naf_syrk"));
+  GW_TRY(gw::syrk_batched_launch(ctx, mp, ov, "naf_syrk"));
+  std::vector<std::vector<double>> ev(n_jobs);
+  std::vector<gw::NafEigJob> ej;
+  for (int d = 0; d < n_jobs; ++d) {
+    ev[d].resize(jobs[d].n_aux);
+    ej.push_back(gw::NafEigJob{jobs[d].K, jobs[d].n_aux, jobs[d].U, ev[d].data()});
+  }
+  GW_TRY(gw::naf_eig_batched(ctx, ej));
+  for (int d = 0; d < n_jobs; ++d) {
+    gw_naf_job& j = jobs[d];
+    int keep = 0;
+    for (int p = 0; p < j.n_aux; ++p) {
+      if (ev[d][p] > j.eps_naf) ++keep; else break;
+    }
+    if (j.max_keep > 0) keep = std::min(keep, j.max_keep);
+    j.n_naf = keep;
+    if (j.eigvals) std::copy(ev[d].begin(), ev[d].end(), j.eigvals);
+  }
+  return GW_OK;
+}
+
+extern "C" gw_status gw_naf_apply_batched(gw_ctx ctx, gw_precision prec, int n_jobs,
+                                          const gw_naf_apply_job* jobs) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_naf_apply_batched: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_naf_apply_batched: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_jobs >= 0 && (n_jobs == 0 || jobs), "gw_naf_apply_batched: bad n_jobs");
+  std::vector<gw::NafGemmJob> gj;
+  for (int d = 0; d < n_jobs; ++d) {
+    const gw_naf_apply_job& j = jobs[d];
+    GW_REQUIRE(ctx, j.n_aux >= 1 && j.n_naf >= 1 && j.n_naf <= j.n_aux && j.n_rows >= 0,
+               "gw_naf_apply_batched: job %d: bad sizes", d);
+    GW_REQUIRE(ctx, j.U && (j.n_rows == 0 || (j.R_in && j.R_out)),
+               "gw_naf_apply_batched: job %d: NULL argument", d);
+    const int64_t ld = j.ld_out ? j.ld_out : j.n_naf;
+    GW_REQUIRE(ctx, ld >= j.n_naf, "gw_naf_apply_batched: job %d: ld_out < n_naf", d);
+    gj.push_back(gw::NafGemmJob{j.R_in, j.U, j.R_out, j.n_rows, j.n_aux, j.n_naf, ld});
+  }
+  if (n_jobs == 0) return GW_OK;
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  return gw::naf_gemm_batched(ctx, prec, gj);
+}

@@ -572,3 +572,12 @@ extern "C" gw_status gw_screen_batched(gw_ctx ctx, gw_precision prec, int n_lt, 
                                                  : finish_batched_kernel<float>,
                                  "finish_batched_kernel");
 }
+
+namespace gw {
+
+void screen_ws_bytes(gw_precision prec, int N, int F, size_t* a_bytes, size_t* panel_bytes) {
+  *a_bytes = prec == GW_FP64 ? 0 : (size_t)F * N * N * sizeof(double);
+  *panel_bytes = (2 * (size_t)F * N * B + (size_t)F * B * B) * sizeof(double);
+}
+
+}  // namespace gw

@@ -720,3 +720,12 @@ extern "C" gw_status gw_sigma_diag_batched(gw_ctx ctx, gw_precision prec, int n_
                      ctx->stream, bq);
   return gw::launch_check(ctx, "sigma_quad_batched_kernel");
 }
+
+namespace gw {
+
+void sigma_ws_bytes(int N, int64_t rows, int F, size_t* part_bytes, size_t* w_bytes) {
+  *part_bytes = (size_t)F * 2 * ((N + BM - 1) / BM) * rows * sizeof(double);
+  *w_bytes = (size_t)F * rows * sizeof(double);
+}
+
+}  // namespace gw

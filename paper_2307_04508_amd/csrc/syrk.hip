@@ -887,3 +887,15 @@ extern "C" gw_status gw_polarizability_lt_batched(gw_ctx ctx, gw_precision prec,
   if (finalize) GW_TRY(gw::mirror_lower_batched(ctx, mj));
   return GW_OK;
 }
+
+namespace gw {
+
+size_t syrk_part_bytes(gw_precision prec, int64_t k_rows, int N, int L) {
+  (void)prec;
+  const int T = (N + BM - 1) / BM;
+  const int n_tiles = T * (T + 1) / 2;
+  const int S = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
+  return (size_t)S * L * n_tiles * BM * BM * sizeof(double);
+}
+
+}  // namespace gw

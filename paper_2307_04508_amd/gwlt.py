@@ -31,7 +31,8 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_set_stream", "gw_sync", "gw_last_error
            "gw_sigma_diag", "gw_qp_solve", "gw_g0w0",
            "gw_graph_begin", "gw_graph_end", "gw_graph_launch", "gw_graph_destroy",
            "gw_polarizability_lt_batched", "gw_screen_batched", "gw_sigma_diag_batched",
-           "gw_qp_solve_batched", "gw_g0w0_batched"]
+           "gw_qp_solve_batched", "gw_g0w0_batched", "gw_reserve", "gw_naf_compress_batched",
+           "gw_naf_apply_batched"]
 
 c_int, c_i64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_DBL = ctypes.POINTER(ctypes.c_double)
@@ -95,6 +96,23 @@ class BatchStats(ctypes.Structure):
 
 GW_BATCH_GRAPH = 1
 
+
+class Dims(ctypes.Structure):
+    _fields_ = [("n_aux", c_int), ("n_naf", c_int), ("n_occ_act", c_int), ("n_virt", c_int),
+                ("n_mo", c_int), ("n_qp", c_int), ("n_lt", c_int), ("n_w", c_int),
+                ("n_pade", c_int), ("chunk_i", c_int)]
+
+
+class NafJob(ctypes.Structure):
+    _fields_ = [("n_aux", c_int), ("n_oo_rows", c_i64), ("R_oo", c_vp), ("n_ov_rows", c_i64),
+                ("R_ov", c_vp), ("K", c_vp), ("eps_naf", c_dbl), ("max_keep", c_int),
+                ("U", c_vp), ("n_naf", c_int), ("eigvals", P_DBL)]
+
+
+class NafApplyJob(ctypes.Structure):
+    _fields_ = [("n_aux", c_int), ("n_naf", c_int), ("U", c_vp), ("n_rows", c_i64),
+                ("R_in", c_vp), ("R_out", c_vp), ("ld_out", c_i64)]
+
 _sig = {
     "gw_create": [ctypes.POINTER(c_vp), c_int, c_vp],
     "gw_destroy": [c_vp],
@@ -118,6 +136,9 @@ _sig = {
                     P_DBL, P_DBL, P_INT],
     "gw_g0w0": [c_vp, c_int, ctypes.POINTER(GwParams), P_DBL, P_INT, P_DBL, c_vp, c_vp, c_vp,
                 P_DBL, P_DBL, P_INT, P_DBL, ctypes.POINTER(GwStats)],
+    "gw_reserve": [c_vp, c_int, ctypes.POINTER(Dims)],
+    "gw_naf_compress_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafJob)],
+    "gw_naf_apply_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafApplyJob)],
     "gw_graph_begin": [c_vp],
     "gw_graph_end": [c_vp, ctypes.POINTER(c_vp)],
     "gw_graph_launch": [c_vp, c_vp],
@@ -484,3 +505,42 @@ def gw_g0w0_batched(ctx, prec, params: BatchParams, mols, graph=True, want_sigma
         s2 = None if sig is None else (sig[0::2] + 1j * sig[1::2]).reshape(len(E), params.n_pade)
         res.append((E, Z, S, s2, arr[i].n_naf))
     return res, stats
+
+
+def gw_reserve(ctx, prec, **dims):
+    """Grow ctx's workspace for per-step calls up to the given sizes (the
+    fields of gw_dims as keywords; missing ones are 0)."""
+    d = Dims(**dims)
+    _check(_lib.gw_reserve(ctx.handle, _prec(prec), ctypes.byref(d)), ctx)
+
+
+def gw_naf_compress_batched(ctx, prec, jobs):
+    """jobs: dicts with n_aux, R_oo, R_ov (device, or None), K, U (device),
+    eps_naf, max_keep.  Returns [(n_naf, eigvals)] per job."""
+    rows, evs = [], []
+    for j in jobs:
+        A = j["n_aux"]
+        ev = np.empty(A)
+        evs.append(ev)
+        Roo, Rov = j.get("R_oo"), j.get("R_ov")
+        rows.append(dict(n_aux=A, n_oo_rows=0 if Roo is None else Roo.numel() // A,
+                         R_oo=_dev(Roo), n_ov_rows=0 if Rov is None else Rov.numel() // A,
+                         R_ov=_dev(Rov), K=_dev(j["K"]), eps_naf=float(j["eps_naf"]),
+                         max_keep=int(j.get("max_keep", 0)), U=_dev(j["U"]), n_naf=0,
+                         eigvals=_dp(ev)))
+    arr = _jobs(NafJob, rows)
+    _check(_lib.gw_naf_compress_batched(ctx.handle, _prec(prec), len(rows), arr), ctx)
+    return [(arr[i].n_naf, evs[i]) for i in range(len(rows))]
+
+
+def gw_naf_apply_batched(ctx, prec, jobs):
+    """jobs: dicts with n_aux, n_naf, U, R_in, R_out (device)."""
+    rows = []
+    for j in jobs:
+        A = j["n_aux"]
+        R_out = j["R_out"]
+        rows.append(dict(n_aux=A, n_naf=j["n_naf"], U=_dev(j["U"]),
+                         n_rows=j["R_in"].numel() // A, R_in=_dev(j["R_in"]),
+                         R_out=_dev(R_out), ld_out=R_out.shape[-1]))
+    arr = _jobs(NafApplyJob, rows)
+    _check(_lib.gw_naf_apply_batched(ctx.handle, _prec(prec), len(rows), arr), ctx)

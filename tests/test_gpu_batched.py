@@ -341,3 +341,97 @@ def test_g0w0_batched_smallest_against_oracle(gw, ctx, batch64):
         err = np.abs(E - ref.eps_qp) * HARTREE_MEV
         _say(f"  n_occ={c.n_occ}: precision part {err.max():.2e} meV")
         assert np.all(err < 1.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_naf_batched_matches_single(gw, ctx, prec):
+    """Batched metric + bucketed padded eigensolves against the oracle's
+    metric and eigenvalues, and the kept subspaces against the oracle's
+    projector, for uneven jobs."""
+    from oracle import naf as onaf
+    _say(f"naf batched {prec}")
+    rng = np.random.default_rng(71)
+    shapes = [(150, 300, 600), (97, 40, 250), (130, 0, 700), (64, 100, 64)]
+    jobs, refs = [], []
+    for A, n_oo, n_ov in shapes:
+        s = np.exp(-np.arange(A) / (A / 6.0))
+        Roo = rng.standard_normal((n_oo, A)) * s / np.sqrt(A)
+        Rov = rng.standard_normal((n_ov, A)) * s / np.sqrt(A)
+        dt = np.float64 if prec == "fp64" else np.float32
+        K_ref = onaf.naf_metric(Roo.astype(dt).astype(np.float64), Rov.astype(dt).astype(np.float64))
+        lam = np.sort(np.linalg.eigvalsh(K_ref))[::-1]
+        keep = A // 2
+        cut = 0.5 * (lam[keep - 1] + lam[keep])
+        _, U_ref = onaf.naf_basis(K_ref, cut)
+        refs.append((K_ref, lam, U_ref, cut))
+        jobs.append(dict(n_aux=A, R_oo=dev(Roo, prec) if n_oo else None, R_ov=dev(Rov, prec),
+                         K=torch.zeros((A, A), dtype=torch.float64, device="cuda"),
+                         U=torch.zeros((A, A), dtype=torch.float64, device="cuda"),
+                         eps_naf=cut, max_keep=0))
+    out = gw.gw_naf_compress_batched(ctx, prec, jobs)
+    for (n, ev), (K_ref, lam, U_ref, cut), j in zip(out, refs, jobs):
+        A = j["n_aux"]
+        assert n == A // 2
+        dK = 1e-13 if prec == "fp64" else 1e-6
+        assert np.max(np.abs(ev - lam)) <= dK * 10 * lam[0]
+        Uh = j["U"].cpu().numpy()[:n].T
+        assert np.allclose(Uh.T @ Uh, np.eye(n), atol=1e-12)
+        P, P_ref = Uh @ Uh.T, U_ref @ U_ref.T
+        gap = lam[n - 1] - lam[n]
+        assert np.linalg.norm(P - P_ref) <= np.sqrt(2) * (dK * 10 * lam[0] * A) / (0.5 * gap)
+    # transform: batched equals single-call output bitwise (same kernel)
+    Rin = [dev(rng.standard_normal((333, j["n_aux"])), prec) for j in jobs]
+    outs_b = [torch.zeros((333, 128 * ((n + 127) // 128)), dtype=r.dtype, device="cuda")
+              for (n, _), r in zip(out, Rin)]
+    gw.gw_naf_apply_batched(ctx, prec, [dict(n_aux=j["n_aux"], n_naf=n, U=j["U"], R_in=r, R_out=o)
+                                        for j, (n, _), r, o in zip(jobs, out, Rin, outs_b)])
+    for j, (n, _), r, o in zip(jobs, out, Rin, outs_b):
+        o1 = torch.zeros_like(o)
+        gw.gw_naf_apply(ctx, prec, j["n_aux"], n, j["U"], r, o1)
+        gw.gw_sync(ctx)
+        assert torch.equal(o, o1)
+
+
+def test_reserve_then_capture_without_eager_run(gw):
+    """On a fresh context, gw_reserve sizes the workspace so the calls can be
+    captured without ever running eagerly; the replay matches an eager run
+    on a second context."""
+    o, v, N, L, F, Q, Mo = 5, 70, 130, 3, 3, 2, 30
+    eps_i, eps_a, R, x, w = _lt_case(9, o, v, N, L)
+    rng = np.random.default_rng(10)
+    Rq = rng.standard_normal((Q, Mo, N)) / np.sqrt(N)
+    eps_m = np.sort(rng.uniform(-2, 2, Mo))
+    om, wom = grids.modified_gauss_legendre(F, 0.5)
+    op, _ = grids.modified_gauss_legendre(5, 0.5)
+    Rd, Rqd = dev(R * 0.3, "fp32"), dev(Rq, "fp32")
+
+    def run(c):
+        M = torch.zeros((L, N, N), dtype=torch.float64, device="cuda")
+        W = torch.zeros((F, N, N), dtype=torch.float32, device="cuda")
+        sig = torch.zeros((Q, len(op), 2), dtype=torch.float64, device="cuda")
+
+        def seq():
+            gw.gw_polarizability_lt(c, "fp32", N, x, w, o, v, eps_i, eps_a, Rd, 0, 1, M)
+            gw.gw_screen(c, "fp32", N, x, M, om, W)
+            gw.gw_sigma_diag(c, "fp32", N, Q, Mo, eps_m, 0.01, Rqd, om, wom, W, op, 0, sig)
+        return M, W, sig, seq
+
+    c1 = gw.Context(0)
+    try:
+        gw.gw_reserve(c1, "fp32", n_naf=N, n_occ_act=o, n_virt=v, n_mo=Mo, n_qp=Q, n_lt=L,
+                      n_w=F, n_pade=len(op))
+        M1, W1, s1, seq1 = run(c1)
+        gw.gw_graph_begin(c1)
+        seq1()
+        g = gw.gw_graph_end(c1)
+        gw.gw_graph_launch(c1, g)
+        gw.gw_sync(c1)
+        c2 = gw.Context(0)
+        M2, W2, s2, seq2 = run(c2)
+        seq2()
+        gw.gw_sync(c2)
+        c2.close()
+        assert torch.equal(M1, M2) and torch.equal(W1, W2) and torch.equal(s1, s2)
+        g.close()
+    finally:
+        c1.close()
