@@ -187,14 +187,20 @@ def run_streamed(args, cfg, gw, torch):
             del Rt
         del ov
         log(f"polarizability pass: occupied {i1}/{o}")
+    Rt_qps = {}
+    for m in metric_precs:
+        Rqp = p.R_qp if m == "fp64" else p.R_qp.float()
+        Rt_qps[m] = torch.empty((Q, Mo, ld[m]), dtype=Rqp.dtype, device="cuda")
+        timed(m, "naf_transform", lambda: gw.gw_naf_apply(ctx, m, A, n_naf[m], U[m], Rqp,
+                                                          Rt_qps[m]))
+        del Rqp
+    del U
+    torch.cuda.empty_cache()
     out = {}
     for q in precs:
         m = mprec[q]
         N = n_naf[m]
-        Rqp = p.R_qp if m == "fp64" else p.R_qp.float()
-        Rt_qp = torch.empty((Q, Mo, ld[m]), dtype=Rqp.dtype, device="cuda")
-        timed(q, "naf_transform", lambda: gw.gw_naf_apply(ctx, m, A, N, U[m], Rqp, Rt_qp))
-        del Rqp
+        Rt_qp = Rt_qps[m]
         esz = 8 if q == "fp64" else 4
         fb = max(1, min(F, int(args.screen_gb * 1e9 // (N * N * (esz + (0 if q == "fp64" else 8))))))
         sig = torch.zeros((Q, Pd, 2), dtype=f64, device="cuda")
@@ -210,7 +216,6 @@ def run_streamed(args, cfg, gw, torch):
         E, Z, S = timed(q, "qp", lambda: gw.gw_qp_solve(ctx, p.eps[p.qp], None, eF, omp, sig,
                                                          c.eta, 1e-6, 100))
         out[q] = (E, S)
-        del Rt_qp
         torch.cuda.empty_cache()
         log(f"{q}: QP done, status {S.tolist()}")
     # totals per precision: the BF16x3 path's NAF is the FP32 path's

@@ -63,7 +63,10 @@ typedef struct gw_ctx_s* gw_ctx;
 /* ------------------------------------------------------------------ context */
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
- * (a hipStream_t; NULL = the default stream).  The stream is borrowed. */
+ * (a hipStream_t; NULL = the default stream).  The stream is borrowed.
+ * GW_EINVAL: `out` is NULL or no such device; GW_EDEVICE: the HIP runtime
+ * reports no usable device (its message is in gw_last_error(NULL));
+ * GW_ENOMEM: the staging buffers could not be allocated. */
 gw_status gw_create(gw_ctx* out, int device, void* hip_stream);
 /* Release the context and its workspace (waits for its stream first). */
 gw_status gw_destroy(gw_ctx ctx);
@@ -274,6 +277,20 @@ gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* params,
                   const void* R_oo, const void* R_ov, const void* R_qp,
                   double* eps_qp, double* z_factor, int* status,
                   double* sigma_iw, gw_stats* stats);
+
+/* ------------------------------------------------------------ autotuner */
+
+/* Launch-shape autotuning.  With tuning on (the default), the first call of
+ * a kernel family on a new shape times its candidate launch shapes with HIP
+ * events and keeps the fastest for that shape on this context: the outer
+ * pivot width of the screening sweep (64, 128 or 256 columns, i.e. the rank
+ * of its trailing update) and the split-K factor of the Laplace SYRK.  Later
+ * calls on the shape, and calls inside a graph capture, use the kept choice
+ * (or the default when none is kept yet).  Results do not depend on the
+ * choice beyond rounding order.  enable: 0 off (defaults), 1 on, 2 on and
+ * forget the kept choices, -1 leave as is; *n_tuned (may be NULL) receives
+ * the number of kept choices. */
+gw_status gw_autotune(gw_ctx ctx, int enable, int* n_tuned);
 
 /* ----------------------------------------------------------- workspace */
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -85,6 +86,9 @@ struct gw_ctx_s {
   std::vector<unsigned char> arena_host;
   int live_graphs = 0;                   // caller-held graphs (workspace pinned)
   BatchGraph* batch_graph = nullptr;     // gw_g0w0_batched's cached graph
+  // launch-shape autotuner (gw_autotune): chosen candidate per shape key
+  bool autotune = true;
+  std::map<std::string, int> tuned;
 };
 
 // A captured, instantiated graph and the arena its kernels read.
@@ -107,6 +111,13 @@ template <typename T>
 inline const T* stage_t(gw_ctx ctx, const T* host, size_t n) {
   return static_cast<const T*>(stage(ctx, host, n * sizeof(T)));
 }
+// Launch-shape autotuner: the first time `key` is seen (tuning on, not
+// capturing), time trial(c) for every candidate with HIP events on the
+// context's stream and keep the fastest; later calls (and capture, or tuning
+// off: the first candidate) return the kept choice without trials.  trial
+// must be free of side effects beyond scratch, or idempotent.
+int tune(gw_ctx ctx, const std::string& key, const std::vector<int>& cand,
+         const std::function<gw_status(int)>& trial);
 // Begin / end a capture on the context (used by the public graph calls and
 // the batched driver).  end_capture instantiates the graph into *out.
 gw_status begin_capture(gw_ctx ctx);

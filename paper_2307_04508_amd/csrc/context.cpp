@@ -152,6 +152,41 @@ static void prof_resolve(gw_ctx ctx) {
   ctx->prof_pending.clear();
 }
 
+int tune(gw_ctx ctx, const std::string& key, const std::vector<int>& cand,
+         const std::function<gw_status(int)>& trial) {
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) return it->second;
+  if (!ctx->autotune || ctx->capturing || cand.size() < 2) return cand.empty() ? 0 : cand[0];
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) hipEventDestroy(a);
+    return cand[0];
+  }
+  int best = cand[0];
+  float best_ms = 1e30f;
+  for (int c : cand) {
+    for (int rep = 0; rep < 2; ++rep) {   // the first run warms caches and workspace
+      hipEventRecord(a, ctx->stream);
+      const gw_status st = trial(c);
+      hipEventRecord(b, ctx->stream);
+      float ms = 0.f;
+      if (st != GW_OK || hipEventSynchronize(b) != hipSuccess ||
+          hipEventElapsedTime(&ms, a, b) != hipSuccess)
+        break;
+      if (rep == 1 && ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  (void)hipGetLastError();
+  clear_error(ctx);
+  ctx->tuned[key] = best;
+  return best;
+}
+
 gw_status begin_capture(gw_ctx ctx) {
   if (ctx->capturing) return fail(ctx, GW_EINVAL, "a graph capture is already in progress");
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -254,6 +289,15 @@ gw_status gw_reserve(gw_ctx ctx, gw_precision prec, const gw_dims* d) {
   return GW_OK;
 }
 
+gw_status gw_autotune(gw_ctx ctx, int enable, int* n_tuned) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_autotune: ctx is NULL");
+  gw::clear_error(ctx);
+  if (enable >= 0) ctx->autotune = enable != 0;
+  if (enable == 2) ctx->tuned.clear();
+  if (n_tuned) *n_tuned = (int)ctx->tuned.size();
+  return GW_OK;
+}
+
 gw_status gw_graph_begin(gw_ctx ctx) {
   if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_graph_begin: ctx is NULL");
   gw::clear_error(ctx);
@@ -323,8 +367,12 @@ gw_status gw_create(gw_ctx* out, int device, void* hip_stream) {
   if (!out) return gw::fail(nullptr, GW_EINVAL, "gw_create: out is NULL");
   *out = nullptr;
   int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
-    return gw::fail(nullptr, GW_EINVAL, "gw_create: no HIP device %d", device);
+  const hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess)
+    return gw::fail(nullptr, GW_EDEVICE, "gw_create: hipGetDeviceCount failed: %s",
+                    hipGetErrorString(e));
+  if (device < 0 || device >= n)
+    return gw::fail(nullptr, GW_EINVAL, "gw_create: no HIP device %d (%d visible)", device, n);
   if (hipSetDevice(device) != hipSuccess)
     return gw::fail(nullptr, GW_EDEVICE, "gw_create: hipSetDevice failed");
   gw_ctx c = new gw_ctx_s();

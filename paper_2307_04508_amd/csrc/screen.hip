@@ -2,16 +2,21 @@
 // W^_j = A_j^-1 - 1 (Eq. 2), in FP64, batched over frequencies.
 //
 // The inverse uses the symmetric sweep (block Gauss-Jordan) form: for each
-// pivot block K of 64 columns, with D = A_KK and the rest R,
+// pivot block K, with D = A_KK and the rest R,
 //     A_RR <- A_RR - A_RK D^-1 A_KR,   A_RK <- A_RK D^-1,   A_KK <- -D^-1,
 // which keeps every intermediate symmetric, so only the lower triangle is
-// stored and updated; after the last block A holds -A^-1.  The pivots D are
-// Schur complements of the symmetric positive definite 1 - Pi, so no pivoting
-// is needed; a non-positive pivot raises the deferred GW_ENOTSPD flag.  The
-// rank-64 update of each step runs on v_mfma_f64_16x16x4f64 and is the whole
-// O(N^3) cost (N^3 flops per matrix with the triangle).
+// stored and updated; after the last block A holds -A^-1.  Sweeping a block
+// equals sweeping its sub-blocks in turn, which gives two levels: 256-wide
+// outer blocks, whose 256 x 256 pivot D is inverted by sweeping a dense copy
+// of it with 64-wide inner blocks (each 64 x 64 pivot inverted in
+// registers).  The pivots are Schur complements of the symmetric positive
+// definite 1 - Pi, so no pivoting is needed; a non-positive pivot raises the
+// deferred GW_ENOTSPD flag.  The rank-256 trailing update (the whole O(N^3)
+// cost, N^3 flops per matrix on the triangle) and the panel product run on
+// v_mfma_f64_16x16x4f64; the matrices are streamed once per 256 columns.
 #include <algorithm>
 #include <cmath>
+#include <string>
 
 #include "common.hpp"
 
@@ -77,37 +82,37 @@ __global__ void assemble_batched_kernel(Batch bt) {
 }
 
 // Arguments of one sweep step (pivot block kt, columns kb .. kb + bw - 1)
-// for one batch of F matrices.
+// for one set of F matrices.  The inner level sweeps 64-wide pivot blocks
+// (pw = 64), inverting each 64 x 64 pivot in registers; the outer level
+// sweeps 256-wide blocks (pw = 256), inverting each 256 x 256 pivot block
+// by an inner-level sweep of a dense copy of it (Dw), so the O(N^3) trailing
+// update is a rank-256 MFMA product and the matrices are streamed through
+// HBM once per 256 columns.
 struct SwArgs {
   double* A;            // [F][N][N] lower triangle
-  double* C;            // [F][N][B] pivot column panel
-  double* P;            // [F][N][B] scaled panel
-  double* Dinv;         // [F][B][B]
+  double* C;            // [F][N][pw] pivot column panel
+  double* P;            // [F][N][pw] scaled panel
+  double* Dinv;         // inner: [F][B][B] D^-1
+  double* Dw;           // outer: [F][bw][bw] pivot block, -D^-1 after its sweep
   int N, F, kb, bw, T, kt;
-  int flag_base;        // flag value offset of this batch's first matrix
-  int panel_blocks;     // batched panel kernel: workgroups per matrix
+  int pw;               // panel width (B or BO)
+  int flag_base;        // flag value offset of this set's first matrix
+  int panel_blocks;     // inner panel kernel: workgroups per matrix
 };
 
 // C[j][r][c] = A_j(r, kb + c) read from the lower triangle; zero for c >= bw.
 __device__ __forceinline__ void gather_elem(const SwArgs& a, int64_t idx) {
   const int64_t NN = (int64_t)a.N * a.N;
-  if (idx >= (int64_t)a.F * a.N * B) return;
-  const int c = (int)(idx % B);
-  const int r = (int)((idx / B) % a.N);
-  const int j = (int)(idx / ((int64_t)B * a.N));
+  if (idx >= (int64_t)a.F * a.N * a.pw) return;
+  const int c = (int)(idx % a.pw);
+  const int r = (int)((idx / a.pw) % a.N);
+  const int j = (int)(idx / ((int64_t)a.pw * a.N));
   double v = 0.0;
   if (c < a.bw) {
     const int col = a.kb + c;
     v = (r >= col) ? a.A[j * NN + (int64_t)r * a.N + col] : a.A[j * NN + (int64_t)col * a.N + r];
   }
   a.C[idx] = v;
-}
-
-__global__ void gather_panel_kernel(SwArgs a) {
-  const int64_t total = (int64_t)a.F * a.N * B;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x)
-    gather_elem(a, idx);
 }
 
 __global__ void gather_panel_batched_kernel(Batch bt) {
@@ -117,17 +122,34 @@ __global__ void gather_panel_batched_kernel(Batch bt) {
   for (int e = 0; e < kBatchElems; e += 256) gather_elem(a, first + e + threadIdx.x);
 }
 
-// One workgroup per frequency sweeps the 64 x 64 pivot block, stored in
-// registers: thread (tr, tc) owns rows 4 tr .. 4 tr + 3 and columns
-// 4 tc .. 4 tc + 3.  Each step the owners of pivot column k and row k publish
-// them through double-buffered LDS (one barrier per step).  A partial block
-// (bw < 64) is padded with the identity, which the sweep leaves as -1 and
-// does not couple to the valid part.  Stores D^-1 (zero-padded).
+// Outer level: Dw[j][p][q] = D[p][q] (the pivot block, from the panel rows).
+__device__ __forceinline__ void extract_elem(const SwArgs& a, int64_t idx) {
+  const int64_t bb = (int64_t)a.bw * a.bw;
+  if (idx >= (int64_t)a.F * bb) return;
+  const int j = (int)(idx / bb);
+  const int p = (int)((idx % bb) / a.bw), q = (int)(idx % a.bw);
+  a.Dw[idx] = a.C[((int64_t)j * a.N + a.kb + p) * a.pw + q];
+}
+
+__global__ void extract_pivot_batched_kernel(Batch bt) {
+  SwArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) extract_elem(a, first + e + threadIdx.x);
+}
+
+// Inner level: one workgroup per matrix sweeps the 64 x 64 pivot block,
+// stored in registers: thread (tr, tc) owns rows 4 tr .. 4 tr + 3 and
+// columns 4 tc .. 4 tc + 3.  Each step the owners of pivot column k and row
+// k publish them through double-buffered LDS (one barrier per step).  A
+// partial block (bw < 64) is padded with the identity, which the sweep
+// leaves as -1 and does not couple to the valid part.  Stores D^-1
+// (zero-padded).
 constexpr int PIV_THREADS = 256;
 __device__ __forceinline__ void pivot_unit(const SwArgs& a, int j, int* __restrict__ flags) {
   __shared__ double colb[2][B], rowb[2][B];
   const int N = a.N, kb = a.kb, bw = a.bw;
-  const double* Cj = a.C + (int64_t)j * N * B;
+  const double* Cj = a.C + (int64_t)j * N * a.pw;
   const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
   double d[4][4];
 #pragma unroll
@@ -135,7 +157,7 @@ __device__ __forceinline__ void pivot_unit(const SwArgs& a, int j, int* __restri
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int gr = 4 * tr + r, gc = 4 * tc + c;
-      d[r][c] = (gr < bw && gc < bw) ? Cj[(int64_t)(kb + gr) * B + gc] : (gr == gc ? 1.0 : 0.0);
+      d[r][c] = (gr < bw && gc < bw) ? Cj[(int64_t)(kb + gr) * a.pw + gc] : (gr == gc ? 1.0 : 0.0);
     }
   bool bad = false;
   for (int k4 = 0; k4 < B / 4; ++k4) {
@@ -186,10 +208,6 @@ __device__ __forceinline__ void pivot_unit(const SwArgs& a, int j, int* __restri
     }
 }
 
-__global__ __launch_bounds__(PIV_THREADS) void pivot_kernel(SwArgs a, int* __restrict__ flags) {
-  pivot_unit(a, blockIdx.x, flags);
-}
-
 __global__ __launch_bounds__(PIV_THREADS) void pivot_batched_kernel(Batch bt,
                                                                     int* __restrict__ flags) {
   const int d = find_problem(bt.off, bt.n, blockIdx.x);
@@ -197,7 +215,7 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_batched_kernel(Batch bt,
   pivot_unit(a, (int)(blockIdx.x - bt.off[d]), flags);
 }
 
-// P[j][r][c] = sum_c' C[j][r][c'] Dinv[j][c'][c] for every row r; this
+// Inner level: P[j][r][c] = sum_c' C[j][r][c'] Dinv[j][c'][c] for every row r; this
 // workgroup takes row groups blk, blk + nblk, ... of 4 rows.
 __device__ __forceinline__ void panel_unit(const SwArgs& a, int j, int blk, int nblk) {
   __shared__ double Ds[B][B + 1];
@@ -220,10 +238,6 @@ __device__ __forceinline__ void panel_unit(const SwArgs& a, int j, int blk, int 
   }
 }
 
-__global__ __launch_bounds__(256) void panel_kernel(SwArgs a) {
-  panel_unit(a, blockIdx.y, blockIdx.x, gridDim.x);
-}
-
 __global__ __launch_bounds__(256) void panel_batched_kernel(Batch bt) {
   const int d = find_problem(bt.off, bt.n, blockIdx.x);
   const SwArgs a = static_cast<const SwArgs*>(bt.descs)[d];
@@ -231,28 +245,104 @@ __global__ __launch_bounds__(256) void panel_batched_kernel(Batch bt) {
   panel_unit(a, u / a.panel_blocks, u % a.panel_blocks, a.panel_blocks);
 }
 
-// A[I][J] -= P[I rows] C[J rows]^T for lower tiles I >= J, I, J != pivot tile.
-__global__ __launch_bounds__(256) void update_kernel(SwArgs a0, Batch bt) {
+
+// One 64-wide k chunk of a 64 x 64 tile product on FP64 MFMA (16x16x4):
+// acc[a][b] += Xs[rows of wave][k] Ys[cols of wave][k].  4 waves of 32 x 32.
+__device__ __forceinline__ void mfma_chunk(const double (*Xs)[LDP], const double (*Ys)[LDP],
+                                           f64x4 (&acc)[2][2], int wy, int wx, int lane) {
+#pragma unroll 4
+  for (int k = 0; k < B; k += 4) {
+    const int kr = k + (lane >> 4);
+    double af[2], bf[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      af[a] = Xs[wy * 32 + a * 16 + (lane & 15)][kr];
+      bf[a] = Ys[wx * 32 + a * 16 + (lane & 15)][kr];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+  }
+}
+
+// Tile coordinates (I >= J) of lower tile t.
+__device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
+  I = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  J = t - I * (I + 1) / 2;
+}
+
+// Outer level: P[j][r][c] = -sum_k C[j][r][k] Dsym[j][k][c] (Dw holds -D^-1
+// in its lower triangle, so P = C D^-1), 64 x 64 output tiles, k in chunks
+// of 64 over the bw pivot columns; columns c >= bw are zero.
+__global__ __launch_bounds__(256) void panel_gemm_batched_kernel(Batch bt) {
+  __shared__ double Xs[B][LDP];
+  __shared__ double Ys[B][LDP];
+  SwArgs sa;
+  int64_t lid;
+  if (!unit_of(SwArgs{}, bt, sa, lid)) return;
+  const int N = sa.N, bw = sa.bw, pw = sa.pw;
+  const int ct = pw / B, rt = (N + B - 1) / B;
+  const int j = (int)(lid / ((int64_t)rt * ct));
+  const int rem = (int)(lid % ((int64_t)rt * ct));
+  const int I = rem / ct, J = rem % ct;
+  const double* Cj = sa.C + (int64_t)j * N * pw;
+  const double* Dj = sa.Dw + (int64_t)j * bw * bw;
+  double* Pj = sa.P + (int64_t)j * N * pw;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < bw; k0 += B) {
+    for (int i = tid; i < B * B; i += 256) {
+      const int r = i / B, k = i % B;
+      const int gr = I * B + r, gk = k0 + k, gc = J * B + r;
+      Xs[r][k] = (gr < N && gk < bw) ? Cj[(int64_t)gr * pw + gk] : 0.0;
+      double y = 0.0;
+      if (gc < bw && gk < bw) y = gc >= gk ? Dj[(int64_t)gc * bw + gk] : Dj[(int64_t)gk * bw + gc];
+      Ys[r][k] = y;
+    }
+    __syncthreads();
+    mfma_chunk(Xs, Ys, acc, wy, wx, lane);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = I * B + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int col = J * B + wx * 32 + b * 16 + (lane & 15);
+        if (row < N) Pj[(int64_t)row * pw + col] = col < bw ? -acc[a][b][r] : 0.0;
+      }
+}
+
+// A[I][J] -= sum_k P[I rows][k] C[J rows][k] (k < bw) for lower 64-tiles
+// I >= J outside the pivot block's rows and columns.
+__global__ __launch_bounds__(256) void update_batched_kernel(Batch bt) {
   __shared__ double Ps[B][LDP];
   __shared__ double Cs[B][LDP];
   SwArgs sa;
   int64_t lid;
-  if (!unit_of(a0, bt, sa, lid)) return;
-  const int N = sa.N, T = sa.T, kt = sa.kt;
-  double* __restrict__ A = sa.A;
-  const double* __restrict__ P = sa.P;
-  const double* __restrict__ C = sa.C;
+  if (!unit_of(SwArgs{}, bt, sa, lid)) return;
+  const int N = sa.N, pw = sa.pw, bw = sa.bw;
+  const int T = (N + B - 1) / B;
   const int n_tiles = T * (T + 1) / 2;
   const int j = (int)(lid / n_tiles);
-  const int t = (int)(lid % n_tiles);
-  int I = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  while (I * (I + 1) / 2 > t) --I;
-  const int J = t - I * (I + 1) / 2;
-  if (I == kt || J == kt) return;
-  const double* Pj = P + (int64_t)j * N * B;
-  const double* Cj = C + (int64_t)j * N * B;
-  double* Aj = A + (int64_t)j * N * N;
+  int I, J;
+  lower_tile((int)(lid % n_tiles), I, J);
+  const int k_lo = sa.kb / B, k_hi = (sa.kb + bw - 1) / B;   // pivot block, in tiles
+  if ((I >= k_lo && I <= k_hi) || (J >= k_lo && J <= k_hi)) return;
+  const double* Pj = sa.P + (int64_t)j * N * pw;
+  const double* Cj = sa.C + (int64_t)j * N * pw;
+  double* Aj = sa.A + (int64_t)j * N * N;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wy = wave >> 1, wx = wave & 1;
@@ -269,35 +359,25 @@ __global__ __launch_bounds__(256) void update_kernel(SwArgs a0, Batch bt) {
         const int col = J * B + wx * 32 + b * 16 + (lane & 15);
         av[a][b][r] = (row < N && col < N) ? Aj[(int64_t)row * N + col] : 0.0;
       }
-  for (int i = tid; i < B * B / 2; i += 256) {
-    const int r = i / (B / 2), c2 = (i % (B / 2)) * 2;
-    const int gr = I * B + r, gc = J * B + r;
-    double2 pv = make_double2(0.0, 0.0), cv = pv;
-    if (gr < N) pv = *reinterpret_cast<const double2*>(Pj + (int64_t)gr * B + c2);
-    if (gc < N) cv = *reinterpret_cast<const double2*>(Cj + (int64_t)gc * B + c2);
-    *reinterpret_cast<double2*>(&Ps[r][c2]) = pv;
-    *reinterpret_cast<double2*>(&Cs[r][c2]) = cv;
-  }
-  __syncthreads();
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int k = 0; k < B; k += 4) {
-    const int kr = k + (lane >> 4);
-    double af[2], bf[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      af[a] = Ps[wy * 32 + a * 16 + (lane & 15)][kr];
-      bf[a] = Cs[wx * 32 + a * 16 + (lane & 15)][kr];
+  for (int k0 = 0; k0 < bw; k0 += B) {
+    for (int i = tid; i < B * B / 2; i += 256) {
+      const int r = i / (B / 2), c2 = (i % (B / 2)) * 2;
+      const int gr = I * B + r, gc = J * B + r;
+      double2 pv = make_double2(0.0, 0.0), cv = pv;
+      // panel columns bw .. pw-1 hold zeros, so whole 64-chunks load as pairs
+      if (gr < N) pv = *reinterpret_cast<const double2*>(Pj + (int64_t)gr * pw + k0 + c2);
+      if (gc < N) cv = *reinterpret_cast<const double2*>(Cj + (int64_t)gc * pw + k0 + c2);
+      *reinterpret_cast<double2*>(&Ps[r][c2]) = pv;
+      *reinterpret_cast<double2*>(&Cs[r][c2]) = cv;
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    __syncthreads();
+    mfma_chunk(Ps, Cs, acc, wy, wx, lane);
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -311,32 +391,28 @@ __global__ __launch_bounds__(256) void update_kernel(SwArgs a0, Batch bt) {
       }
 }
 
-// Pivot row / column after the update: A(r, K) <- P[r] for r outside K,
-// A(K, K) <- -D^-1 (lower triangle storage).
+// Pivot rows / columns after the update: A(r, K) <- P[r] for r outside K;
+// A(K, K) <- -D^-1 (inner: from Dinv; outer: Dw already holds it), lower
+// triangle storage.
 __device__ __forceinline__ void writeback_elem(const SwArgs& a, int64_t idx) {
   const int64_t NN = (int64_t)a.N * a.N;
-  if (idx >= (int64_t)a.F * a.N * B) return;
-  const int c = (int)(idx % B);
-  const int r = (int)((idx / B) % a.N);
-  const int j = (int)(idx / ((int64_t)B * a.N));
+  if (idx >= (int64_t)a.F * a.N * a.pw) return;
+  const int c = (int)(idx % a.pw);
+  const int r = (int)((idx / a.pw) % a.N);
+  const int j = (int)(idx / ((int64_t)a.pw * a.N));
   if (c >= a.bw) return;
   const int col = a.kb + c;
   double* Aj = a.A + j * NN;
   if (r >= a.kb && r < a.kb + a.bw) {
     const int rr = r - a.kb;
-    if (rr >= c) Aj[(int64_t)r * a.N + col] = -a.Dinv[((int64_t)j * B + rr) * B + c];
+    if (rr >= c)
+      Aj[(int64_t)r * a.N + col] = a.Dw ? a.Dw[((int64_t)j * a.bw + rr) * a.bw + c]
+                                        : -a.Dinv[((int64_t)j * B + rr) * B + c];
   } else {
     const double v = a.P[idx];
     if (r > col) Aj[(int64_t)r * a.N + col] = v;
     else Aj[(int64_t)col * a.N + r] = v;
   }
-}
-
-__global__ void writeback_kernel(SwArgs a) {
-  const int64_t total = (int64_t)a.F * a.N * B;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x)
-    writeback_elem(a, idx);
 }
 
 __global__ void writeback_batched_kernel(Batch bt) {
@@ -382,6 +458,182 @@ __global__ void finish_batched_kernel(Batch bt) {
   for (int e = 0; e < kBatchElems; e += 256) finish_elem<T>(a, first + e + threadIdx.x);
 }
 
+// ------------------------------------------------------------------ host
+
+// One set of F matrices of order N being swept, and its scratch.
+struct SweepSet {
+  double* A;
+  int N, F, flag_base;
+};
+
+constexpr int BO = 256;   // outer pivot block width
+
+// Scratch (doubles) of a two-level sweep of the given sets.
+size_t sweep_scratch(const std::vector<SweepSet>& sets) {
+  size_t t = 0;
+  for (const SweepSet& s : sets) {
+    t += 2 * (size_t)s.F * s.N * BO;               // outer C, P
+    t += (size_t)s.F * BO * BO;                    // outer Dw
+    t += 2 * (size_t)s.F * BO * B;                 // inner C, P (over Dw)
+    t += (size_t)s.F * B * B;                      // inner Dinv
+  }
+  return t;
+}
+
+template <typename F>
+gw_status launch_units(gw_ctx ctx, const SwArgs* dst, const std::vector<SwArgs>& st, F units,
+                       int chunk, bool elems, void (*kern)(Batch), int threads,
+                       const char* what) {
+  std::vector<int64_t> off(1, 0);
+  for (const SwArgs& a : st) {
+    const int64_t u = units(a);
+    off.push_back(off.back() + (elems ? (u + kBatchElems - 1) / kBatchElems : u));
+  }
+  if (off.back() == 0) return GW_OK;
+  const int64_t* doff = gw::stage_t(ctx, off.data(), off.size());
+  if (!doff) return GW_EINVAL;
+  const Batch bt{dst, doff, (int)st.size(), chunk, off.back()};
+  const int64_t grid = chunk > 1 ? (off.back() + 8 * chunk - 1) / (8 * chunk) * (8 * chunk)
+                                 : off.back();
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), 0, ctx->stream, bt);
+  return gw::launch_check(ctx, what);
+}
+
+// Sweep every set to -A^-1 with pivot blocks of width pw: B (one level, each
+// 64 x 64 pivot inverted in registers) or 128 / 256 (outer level, whose pivot
+// blocks are inverted by a one-level sweep of their copies).  `scr` holds
+// sweep_scratch(sets) doubles.
+gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* scr) {
+  const int n = (int)sets.size();
+  std::vector<double*> C(n), P(n), X(n);   // X: Dw (outer) or Dinv (inner)
+  std::vector<SweepSet> inner(n);
+  size_t o = 0;
+  for (int d = 0; d < n; ++d) {
+    const SweepSet& s = sets[d];
+    C[d] = scr + o;
+    o += (size_t)s.F * s.N * pw;
+    P[d] = scr + o;
+    o += (size_t)s.F * s.N * pw;
+    X[d] = scr + o;
+    o += pw > B ? (size_t)s.F * pw * pw : (size_t)s.F * B * B;
+  }
+  double* inner_scr = scr + o;              // outer level: scratch of the inner sweeps
+  int T_max = 0;
+  for (const SweepSet& s : sets) T_max = std::max(T_max, (s.N + pw - 1) / pw);
+  for (int kt = 0; kt < T_max; ++kt) {
+    std::vector<SwArgs> st;
+    std::vector<SweepSet> dsets;
+    for (int d = 0; d < n; ++d) {
+      const SweepSet& s = sets[d];
+      const int kb = kt * pw;
+      if (kb >= s.N) continue;
+      const int bw = std::min(pw, s.N - kb);
+      SwArgs a{s.A, C[d], P[d], pw == B ? X[d] : nullptr, pw > B ? X[d] : nullptr, s.N, s.F,
+               kb, bw, (s.N + B - 1) / B, kt, pw, s.flag_base, std::min(1024, (s.N + 15) / 16)};
+      st.push_back(a);
+      if (pw > B) dsets.push_back(SweepSet{X[d], bw, s.F, s.flag_base});
+    }
+    const SwArgs* dst = static_cast<const SwArgs*>(gw::stage(ctx, st.data(), st.size() * sizeof(SwArgs)));
+    if (!dst) return GW_EINVAL;
+    GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; },
+                        1, true, gather_panel_batched_kernel, 256, "gather_panel"));
+    if (pw == B) {
+      std::vector<int64_t> off(1, 0);
+      for (const SwArgs& a : st) off.push_back(off.back() + a.F);
+      const int64_t* doff = gw::stage_t(ctx, off.data(), off.size());
+      if (!doff) return GW_EINVAL;
+      hipLaunchKernelGGL(pivot_batched_kernel, dim3((unsigned)off.back()), dim3(PIV_THREADS), 0,
+                         ctx->stream, Batch{dst, doff, (int)st.size(), 1, off.back()},
+                         ctx->d_flags);
+      GW_TRY(gw::launch_check(ctx, "pivot_batched_kernel"));
+      GW_TRY(launch_units(ctx, dst, st,
+                          [](const SwArgs& a) { return (int64_t)a.F * a.panel_blocks; }, 1, false,
+                          panel_batched_kernel, 256, "panel_batched_kernel"));
+    } else {
+      GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.bw * a.bw; },
+                          1, true, extract_pivot_batched_kernel, 256, "extract_pivot"));
+      GW_TRY(sweep(ctx, dsets, B, inner_scr));
+      GW_TRY(launch_units(ctx, dst, st,
+                          [](const SwArgs& a) {
+                            return (int64_t)a.F * ((a.N + B - 1) / B) * (a.pw / B);
+                          },
+                          8, false, panel_gemm_batched_kernel, 256, "panel_gemm"));
+    }
+    GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.T * (a.T + 1) / 2; },
+                        8, false, update_batched_kernel, 256, "update_kernel"));
+    GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; },
+                        1, true, writeback_batched_kernel, 256, "writeback"));
+  }
+  return GW_OK;
+}
+
+// Assemble, sweep and finish the given screening jobs (device pointers,
+// staged x and omega).
+struct ScreenJob {
+  const double* M;      // device [L][N][N]
+  const double* x;      // device [L]
+  const double* omega;  // device [F]
+  int N, F;
+  void* W_hat;
+};
+
+gw_status screen_jobs(gw_ctx ctx, gw_precision prec, int L, const std::vector<ScreenJob>& jobs) {
+  size_t a_tot = 0;
+  std::vector<SweepSet> sets;
+  int flag_base = 0, smem = 0;
+  double flops = 0, bytes = 0;
+  for (const ScreenJob& j : jobs) {
+    if (prec != GW_FP64) a_tot += (size_t)j.F * j.N * j.N;
+    smem = std::max(smem, j.F * L);
+  }
+  double* Aws = nullptr;
+  if (a_tot) {
+    Aws = static_cast<double*>(gw::ws_get(ctx, WS_SCREEN_A, a_tot * sizeof(double)));
+    if (!Aws) return GW_ENOMEM;
+  }
+  std::vector<AsmArgs> asm_d;
+  std::vector<FinArgs> fin_d;
+  std::vector<int64_t> n_asm, n_fin;
+  size_t ao = 0;
+  for (const ScreenJob& j : jobs) {
+    double* A = prec == GW_FP64 ? static_cast<double*>(j.W_hat) : Aws + ao;
+    if (prec != GW_FP64) ao += (size_t)j.F * j.N * j.N;
+    sets.push_back(SweepSet{A, j.N, j.F, flag_base});
+    flag_base += j.F;
+    asm_d.push_back(AsmArgs{j.M, L, j.N, j.x, j.omega, j.F, A});
+    n_asm.push_back((int64_t)j.N * j.N);
+    fin_d.push_back(FinArgs{A, j.N, j.F, j.W_hat});
+    n_fin.push_back((int64_t)j.F * j.N * j.N);
+    flops += (double)j.F * j.N * (double)j.N * j.N;
+    bytes += (double)j.F * j.N * (double)j.N * 8.0 * 2.0;
+  }
+  double* scr = static_cast<double*>(
+      gw::ws_get(ctx, WS_SCREEN_PANEL, sweep_scratch(sets) * sizeof(double)));
+  if (!scr) return GW_ENOMEM;
+  // assemble (the sweep works in place), sweep, finish: rerunnable as a whole
+  auto run = [&](int pw, bool timed) -> gw_status {
+    const int pi = timed ? gw::prof_begin(ctx) : -1;
+    std::vector<int64_t> off(1, 0);
+    for (int64_t nn : n_asm) off.push_back(off.back() + (nn + kBatchElems - 1) / kBatchElems);
+    Batch bt;
+    GW_TRY(gw::stage_batch(ctx, asm_d, off, 1, bt));
+    hipLaunchKernelGGL(assemble_batched_kernel, dim3((unsigned)off.back()), dim3(256),
+                       (size_t)smem * sizeof(double), ctx->stream, bt);
+    GW_TRY(gw::launch_check(ctx, "assemble_batched_kernel"));
+    GW_TRY(sweep(ctx, sets, pw, scr));
+    if (timed) gw::prof_end(ctx, pi, "screen_sweep", flops, bytes);
+    return gw::elementwise_batched(ctx, fin_d, n_fin,
+                                   prec == GW_FP64 ? finish_batched_kernel<double>
+                                                   : finish_batched_kernel<float>,
+                                   "finish_batched_kernel");
+  };
+  // outer pivot width: the rank of the trailing update (autotuned per shape)
+  std::string key = "screen";
+  for (const ScreenJob& j : jobs) key += ":" + std::to_string(j.N) + "x" + std::to_string(j.F);
+  const int pw = gw::tune(ctx, key, {BO, 128, B}, [&](int c) { return run(c, false); });
+  return run(pw, true);
+}
+
 }  // namespace
 
 extern "C" gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_lt,
@@ -395,59 +647,10 @@ extern "C" gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_l
              "gw_screen: bad sizes (n_naf=%d n_lt=%d n_w=%d)", n_naf, n_lt, n_w);
   GW_REQUIRE(ctx, x_lt && M && omega && W_hat, "gw_screen: NULL argument");
   GW_HIP(ctx, hipSetDevice(ctx->device));
-  const int N = n_naf, F = n_w;
-  const int64_t NN = (int64_t)N * N;
   const double* dx = gw::stage_t(ctx, x_lt, n_lt);
   const double* dw = gw::stage_t(ctx, omega, n_w);
   if (!dx || !dw) return GW_EINVAL;
-  double* A = nullptr;
-  if (prec == GW_FP64) {
-    A = static_cast<double*>(W_hat);
-  } else {
-    A = static_cast<double*>(gw::ws_get(ctx, WS_SCREEN_A, (size_t)F * NN * sizeof(double)));
-    if (!A) return GW_ENOMEM;
-  }
-  const size_t panel = (size_t)F * N * B;
-  double* pan = static_cast<double*>(
-      gw::ws_get(ctx, WS_SCREEN_PANEL, (2 * panel + (size_t)F * B * B) * sizeof(double)));
-  if (!pan) return GW_ENOMEM;
-  double* C = pan;
-  double* P = pan + panel;
-  double* Dinv = pan + 2 * panel;
-
-  const int pi = gw::prof_begin(ctx);
-  hipLaunchKernelGGL(assemble_kernel, dim3(grid_for(NN, 256)), dim3(256),
-                     (size_t)F * n_lt * sizeof(double), ctx->stream,
-                     AsmArgs{M, n_lt, N, dx, dw, F, A});
-  GW_TRY(gw::launch_check(ctx, "assemble_kernel"));
-  const int T = (N + B - 1) / B;
-  const int n_tiles = T * (T + 1) / 2;
-  for (int kt = 0; kt < T; ++kt) {
-    const int kb = kt * B, bw = std::min(B, N - kb);
-    const SwArgs sa{A, C, P, Dinv, N, F, kb, bw, T, kt, 0, 0};
-    hipLaunchKernelGGL(gather_panel_kernel, dim3(grid_for((int64_t)F * N * B, 256)), dim3(256),
-                       0, ctx->stream, sa);
-    hipLaunchKernelGGL(pivot_kernel, dim3(F), dim3(PIV_THREADS), 0, ctx->stream, sa,
-                       ctx->d_flags);
-    hipLaunchKernelGGL(panel_kernel, dim3(std::min(1024, (N + 3) / 4), F), dim3(256), 0,
-                       ctx->stream, sa);
-    if (T > 1)
-      hipLaunchKernelGGL(update_kernel, dim3((unsigned)((int64_t)F * n_tiles)), dim3(256), 0,
-                         ctx->stream, sa, Batch{});
-    hipLaunchKernelGGL(writeback_kernel, dim3(grid_for((int64_t)F * N * B, 256)), dim3(256), 0,
-                       ctx->stream, sa);
-    GW_TRY(gw::launch_check(ctx, "screening sweep"));
-  }
-  gw::prof_end(ctx, pi, "screen_sweep", (double)F * N * (double)N * N,
-               (double)F * N * (double)N * 8.0 * 2.0);
-  const FinArgs fa{A, N, F, W_hat};
-  if (prec == GW_FP64)
-    hipLaunchKernelGGL(finish_kernel<double>, dim3(grid_for(F * NN, 256)), dim3(256), 0,
-                       ctx->stream, fa);
-  else
-    hipLaunchKernelGGL(finish_kernel<float>, dim3(grid_for(F * NN, 256)), dim3(256), 0,
-                       ctx->stream, fa);
-  return gw::launch_check(ctx, "finish_kernel");
+  return screen_jobs(ctx, prec, n_lt, {ScreenJob{M, dx, dw, n_naf, n_w, W_hat}});
 }
 
 extern "C" gw_status gw_screen_batched(gw_ctx ctx, gw_precision prec, int n_lt, int n_jobs,
@@ -466,118 +669,22 @@ extern "C" gw_status gw_screen_batched(gw_ctx ctx, gw_precision prec, int n_lt, 
   }
   if (n_jobs == 0) return GW_OK;
   GW_HIP(ctx, hipSetDevice(ctx->device));
-
-  // workspace: FP64 working matrices (in place for FP64), panels, pivots
-  size_t a_tot = 0, p_tot = 0, d_tot = 0;
-  for (int d = 0; d < n_jobs; ++d) {
-    const size_t N = jobs[d].n_naf, F = jobs[d].n_w;
-    if (prec != GW_FP64) a_tot += F * N * N;
-    p_tot += F * N * B;
-    d_tot += F * B * B;
-  }
-  double* Aws = nullptr;
-  if (a_tot) {
-    Aws = static_cast<double*>(gw::ws_get(ctx, WS_SCREEN_A, a_tot * sizeof(double)));
-    if (!Aws) return GW_ENOMEM;
-  }
-  double* pan = static_cast<double*>(
-      gw::ws_get(ctx, WS_SCREEN_PANEL, (2 * p_tot + d_tot) * sizeof(double)));
-  if (!pan) return GW_ENOMEM;
-
-  std::vector<AsmArgs> asm_d;
-  std::vector<FinArgs> fin_d;
-  std::vector<SwArgs> base;
-  std::vector<int64_t> n_asm, n_fin;
-  size_t ao = 0, po = 0, dof = 0;
-  int flag_base = 0, T_max = 0, smem = 0;
-  double flops = 0, bytes = 0;
+  std::vector<ScreenJob> sj;
   for (int d = 0; d < n_jobs; ++d) {
     const gw_screen_job& j = jobs[d];
-    const int N = j.n_naf, F = j.n_w;
     const double* dx = gw::stage_t(ctx, j.x_lt, n_lt);
-    const double* dw = gw::stage_t(ctx, j.omega, F);
+    const double* dw = gw::stage_t(ctx, j.omega, j.n_w);
     if (!dx || !dw) return GW_EINVAL;
-    double* A = prec == GW_FP64 ? static_cast<double*>(j.W_hat) : Aws + ao;
-    if (prec != GW_FP64) ao += (size_t)F * N * N;
-    SwArgs sa{A, pan + po, pan + p_tot + po, pan + 2 * p_tot + dof, N, F, 0, 0,
-              (N + B - 1) / B, 0, flag_base, std::min(1024, (N + 15) / 16)};
-    po += (size_t)F * N * B;
-    dof += (size_t)F * B * B;
-    flag_base += F;
-    T_max = std::max(T_max, sa.T);
-    smem = std::max(smem, F * n_lt);
-    base.push_back(sa);
-    asm_d.push_back(AsmArgs{j.M, n_lt, N, dx, dw, F, A});
-    n_asm.push_back((int64_t)N * N);
-    fin_d.push_back(FinArgs{A, N, F, j.W_hat});
-    n_fin.push_back((int64_t)F * N * N);
-    flops += (double)F * N * (double)N * N;
-    bytes += (double)F * N * (double)N * 8.0 * 2.0;
+    sj.push_back(ScreenJob{j.M, dx, dw, j.n_naf, j.n_w, j.W_hat});
   }
-
-  const int pi = gw::prof_begin(ctx);
-  {
-    std::vector<int64_t> off(1, 0);
-    for (int64_t n : n_asm) off.push_back(off.back() + (n + kBatchElems - 1) / kBatchElems);
-    Batch bt;
-    GW_TRY(gw::stage_batch(ctx, asm_d, off, 1, bt));
-    hipLaunchKernelGGL(assemble_batched_kernel, dim3((unsigned)off.back()), dim3(256),
-                       (size_t)smem * sizeof(double), ctx->stream, bt);
-    GW_TRY(gw::launch_check(ctx, "assemble_batched_kernel"));
-  }
-  for (int kt = 0; kt < T_max; ++kt) {
-    std::vector<SwArgs> st;
-    std::vector<int64_t> o_el(1, 0), o_piv(1, 0), o_pan(1, 0), o_upd(1, 0);
-    for (const SwArgs& b0 : base) {
-      if (kt >= b0.T) continue;
-      SwArgs sa = b0;
-      sa.kt = kt;
-      sa.kb = kt * B;
-      sa.bw = std::min(B, sa.N - sa.kb);
-      st.push_back(sa);
-      const int64_t el = (int64_t)sa.F * sa.N * B;
-      o_el.push_back(o_el.back() + (el + kBatchElems - 1) / kBatchElems);
-      o_piv.push_back(o_piv.back() + sa.F);
-      o_pan.push_back(o_pan.back() + (int64_t)sa.F * sa.panel_blocks);
-      o_upd.push_back(o_upd.back() + (int64_t)sa.F * sa.T * (sa.T + 1) / 2);
-    }
-    const SwArgs* dst = static_cast<const SwArgs*>(gw::stage(ctx, st.data(), st.size() * sizeof(SwArgs)));
-    const int64_t* d_el = gw::stage_t(ctx, o_el.data(), o_el.size());
-    const int64_t* d_piv = gw::stage_t(ctx, o_piv.data(), o_piv.size());
-    const int64_t* d_pan = gw::stage_t(ctx, o_pan.data(), o_pan.size());
-    const int64_t* d_upd = gw::stage_t(ctx, o_upd.data(), o_upd.size());
-    if (!dst || !d_el || !d_piv || !d_pan || !d_upd) return GW_EINVAL;
-    const int n = (int)st.size();
-    constexpr int CHUNK = 8;
-    const Batch b_el{dst, d_el, n, 1, o_el.back()};
-    const Batch b_piv{dst, d_piv, n, 1, o_piv.back()};
-    const Batch b_pan{dst, d_pan, n, 1, o_pan.back()};
-    const Batch b_upd{dst, d_upd, n, CHUNK, o_upd.back()};
-    hipLaunchKernelGGL(gather_panel_batched_kernel, dim3((unsigned)o_el.back()), dim3(256), 0,
-                       ctx->stream, b_el);
-    hipLaunchKernelGGL(pivot_batched_kernel, dim3((unsigned)o_piv.back()), dim3(PIV_THREADS), 0,
-                       ctx->stream, b_piv, ctx->d_flags);
-    hipLaunchKernelGGL(panel_batched_kernel, dim3((unsigned)o_pan.back()), dim3(256), 0,
-                       ctx->stream, b_pan);
-    const int64_t g_upd = (o_upd.back() + 8 * CHUNK - 1) / (8 * CHUNK) * (8 * CHUNK);
-    hipLaunchKernelGGL(update_kernel, dim3((unsigned)g_upd), dim3(256), 0, ctx->stream,
-                       SwArgs{}, b_upd);
-    hipLaunchKernelGGL(writeback_batched_kernel, dim3((unsigned)o_el.back()), dim3(256), 0,
-                       ctx->stream, b_el);
-    GW_TRY(gw::launch_check(ctx, "batched screening sweep"));
-  }
-  gw::prof_end(ctx, pi, "screen_sweep", flops, bytes);
-  return gw::elementwise_batched(ctx, fin_d, n_fin,
-                                 prec == GW_FP64 ? finish_batched_kernel<double>
-                                                 : finish_batched_kernel<float>,
-                                 "finish_batched_kernel");
+  return screen_jobs(ctx, prec, n_lt, sj);
 }
 
 namespace gw {
 
 void screen_ws_bytes(gw_precision prec, int N, int F, size_t* a_bytes, size_t* panel_bytes) {
   *a_bytes = prec == GW_FP64 ? 0 : (size_t)F * N * N * sizeof(double);
-  *panel_bytes = (2 * (size_t)F * N * B + (size_t)F * B * B) * sizeof(double);
+  *panel_bytes = sweep_scratch({SweepSet{nullptr, N, F, 0}}) * sizeof(double);
 }
 
 }  // namespace gw

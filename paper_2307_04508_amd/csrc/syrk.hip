@@ -14,6 +14,7 @@
 //  FP64:          v_mfma_f64_16x16x4f64.
 #include <algorithm>
 #include <cmath>
+#include <string>
 
 #include "common.hpp"
 
@@ -640,17 +641,34 @@ gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_ro
                       double* out, int accumulate, const char* prof_name) {
   const int T = (N + BM - 1) / BM;
   const int n_tiles = T * (T + 1) / 2;
-  const int S = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
+  const int S0 = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
+  // split-K candidates around the occupancy-based choice (autotuned per shape)
+  std::vector<int> cand{S0};
+  if (S0 > 1) cand.push_back(std::max(1, S0 / 2));
+  if (2 * S0 <= 16 && k_rows / (2 * S0) >= 1024) cand.push_back(2 * S0);
+  const int S_max = *std::max_element(cand.begin(), cand.end());
   const int64_t align = split_align(prec);
-  int64_t rps = (k_rows + S - 1) / S;
-  rps = (rps + align - 1) / align * align;
-  const size_t part_bytes = (size_t)S * L * n_tiles * BM * BM * sizeof(double);
-  double* part = static_cast<double*>(ws_get(ctx, WS_SYRK_PART, part_bytes));
+  double* part = static_cast<double*>(
+      ws_get(ctx, WS_SYRK_PART, (size_t)S_max * L * n_tiles * BM * BM * sizeof(double)));
   if (!part) return GW_ENOMEM;
-  SyrkArgs a{X, k_rows, N, ld, L, scale, cscale, T, n_tiles, S, rps, part};
+  const bool fast = fast_rows(prec, X, ld);
+  auto args = [&](int S) {
+    int64_t rps = (k_rows + S - 1) / S;
+    rps = (rps + align - 1) / align * align;
+    return SyrkArgs{X, k_rows, N, ld, L, scale, cscale, T, n_tiles, S, rps, part};
+  };
+  const std::string key = "syrk:" + std::to_string((int)prec) + ":" + std::to_string(N) + ":" +
+                          std::to_string(L) + ":" + std::to_string(k_rows) + ":" +
+                          std::to_string(scale != nullptr) + std::to_string(fast);
+  const int S = k_rows > 0 ? tune(ctx, key, cand, [&](int c) {
+    launch_syrk_kernel(ctx, prec, fast, scale != nullptr, args(c), Batch{},
+                       (int64_t)c * L * n_tiles);
+    return launch_check(ctx, "syrk kernel");
+  }) : 1;
+  const SyrkArgs a = args(S);
   const int64_t grid = (int64_t)S * L * n_tiles;
   const int pi = prof_begin(ctx);
-  launch_syrk_kernel(ctx, prec, fast_rows(prec, X, ld), scale != nullptr, a, Batch{}, grid);
+  launch_syrk_kernel(ctx, prec, fast, scale != nullptr, a, Batch{}, grid);
   // algorithmic work: L lower-triangle products of 2 k flops each; X read
   // once, the triangle written once
   const double esz = prec == GW_FP64 ? 8.0 : 4.0;
@@ -894,7 +912,8 @@ size_t syrk_part_bytes(gw_precision prec, int64_t k_rows, int N, int L) {
   (void)prec;
   const int T = (N + BM - 1) / BM;
   const int n_tiles = T * (T + 1) / 2;
-  const int S = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
+  int S = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
+  if (2 * S <= 16 && k_rows / (2 * S) >= 1024) S *= 2;   // largest autotuning candidate
   return (size_t)S * L * n_tiles * BM * BM * sizeof(double);
 }
 

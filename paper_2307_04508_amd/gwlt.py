@@ -17,6 +17,12 @@ LIB_PATH = os.path.join(_HERE, "libgwlt.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} not found: build it with "
                       "`python paper_2307_04508_amd/build.py`")
+# The library must use the HIP runtime that owns the tensors and streams it
+# is handed.  torch ships its own libamdhip64.so.7; loading torch first makes
+# the dynamic loader resolve the library's libamdhip64.so.7 to that copy
+# instead of pulling a second runtime in from the ROCm install.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_ENOTSPD, GW_EPADE, GW_ENOCONV, \
@@ -32,7 +38,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_set_stream", "gw_sync", "gw_last_error
            "gw_graph_begin", "gw_graph_end", "gw_graph_launch", "gw_graph_destroy",
            "gw_polarizability_lt_batched", "gw_screen_batched", "gw_sigma_diag_batched",
            "gw_qp_solve_batched", "gw_g0w0_batched", "gw_reserve", "gw_naf_compress_batched",
-           "gw_naf_apply_batched"]
+           "gw_naf_apply_batched", "gw_autotune"]
 
 c_int, c_i64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_DBL = ctypes.POINTER(ctypes.c_double)
@@ -137,6 +143,7 @@ _sig = {
     "gw_g0w0": [c_vp, c_int, ctypes.POINTER(GwParams), P_DBL, P_INT, P_DBL, c_vp, c_vp, c_vp,
                 P_DBL, P_DBL, P_INT, P_DBL, ctypes.POINTER(GwStats)],
     "gw_reserve": [c_vp, c_int, ctypes.POINTER(Dims)],
+    "gw_autotune": [c_vp, c_int, P_INT],
     "gw_naf_compress_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafJob)],
     "gw_naf_apply_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafApplyJob)],
     "gw_graph_begin": [c_vp],
@@ -544,3 +551,11 @@ def gw_naf_apply_batched(ctx, prec, jobs):
                          R_out=_dev(R_out), ld_out=R_out.shape[-1]))
     arr = _jobs(NafApplyJob, rows)
     _check(_lib.gw_naf_apply_batched(ctx.handle, _prec(prec), len(rows), arr), ctx)
+
+
+def gw_autotune(ctx, enable: int = -1) -> int:
+    """Switch launch-shape autotuning (0 off, 1 on, 2 on and forget, -1 keep);
+    returns the number of kept choices."""
+    n = ctypes.c_int(0)
+    _check(_lib.gw_autotune(ctx.handle, int(enable), ctypes.byref(n)), ctx)
+    return n.value

@@ -80,3 +80,12 @@ def test_argument_errors_are_status_codes():
     assert lib.gw_screen(None, 0, 1, 1, None, None, 1, None, None) == gwlt.GW_EINVAL
     assert lib.gw_sync(None) == gwlt.GW_EINVAL
     assert b"NULL" in lib.gw_last_error(None) or lib.gw_last_error(None) != b""
+
+
+def test_binding_uses_a_single_hip_runtime():
+    """The library is bound to torch's HIP runtime: after the binding is
+    imported only one libamdhip64 is mapped in the process (a second one
+    would own neither torch's tensors nor its streams)."""
+    with open("/proc/self/maps") as f:
+        libs = {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    assert len({os.path.realpath(p) for p in libs}) == 1, libs

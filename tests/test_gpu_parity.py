@@ -148,7 +148,8 @@ def _spd_m(seed, L, N):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-7)])
-@pytest.mark.parametrize("N,F", [(150, 5), (333, 3), (64, 2), (1, 2)])
+@pytest.mark.parametrize("N,F", [(150, 5), (333, 3), (64, 2), (1, 2), (520, 2), (256, 2),
+                                 (257, 1)])
 def test_screen_matches_oracle(gw, ctx, prec, tol, N, F):
     _say(f"screen {prec} N={N} F={F}")
     L = 3
@@ -412,3 +413,44 @@ def test_g0w0_medium_matches_golden(gw, ctx, medium_problem, prec):
     S_ref = np.array(g["sigma_lt_re"]) + 1j * np.array(g["sigma_lt_im"])
     stol = 1e-4 if prec != "bf16x3" else 1e-3
     assert np.max(np.abs(sig - S_ref)) < stol * np.max(np.abs(S_ref))
+
+
+def test_autotuner_keeps_choices_and_results(gw, ctx):
+    """The first call on a shape times the candidate launch shapes and keeps
+    one; a second call reuses it (no new entry) and gives the same result
+    bitwise; with tuning off the defaults give the oracle result too."""
+    N, F, L = 520, 2, 3
+    M = _spd_m(41, L, N)
+    x = np.array([0.05, 0.5, 3.0])
+    om, _ = grids.modified_gauss_legendre(F, 0.5)
+    ref = rpa.screen(rpa.pi_lt(M, x, om))
+    Md = dev(M, "fp64")
+    n0 = gw.gw_autotune(ctx, 2)
+    assert n0 == 0
+    outs = []
+    for _ in range(2):
+        W = torch.zeros((F, N, N), dtype=torch.float64, device="cuda")
+        gw.gw_screen(ctx, "fp64", N, x, Md, om, W)
+        gw.gw_sync(ctx)
+        outs.append(W)
+    assert gw.gw_autotune(ctx) == 1
+    assert torch.equal(outs[0], outs[1])
+    o, v = 9, 700
+    eps_i, eps_a, R, xl, wl = _lt_case(17, o, v, 300, 4)
+    Mm = torch.zeros((4, 300, 300), dtype=torch.float64, device="cuda")
+    gw.gw_polarizability_lt(ctx, "fp32", 300, xl, wl, o, v, eps_i, eps_a, dev(R, "fp32"), 0, 1, Mm)
+    gw.gw_sync(ctx)
+    assert gw.gw_autotune(ctx) == 2
+    d = (eps_a[None, :] - eps_i[:, None]).ravel()
+    refm = rpa.m_lt(R, d, xl, wl)
+    for m in range(4):
+        assert rel_fro(Mm[m].cpu().numpy(), refm[m]) < 1e-6
+    gw.gw_autotune(ctx, 0)
+    W = torch.zeros((F, N, N), dtype=torch.float64, device="cuda")
+    gw.gw_screen(ctx, "fp64", N, x, Md, om, W)
+    gw.gw_sync(ctx)
+    gw.gw_autotune(ctx, 1)
+    for Wt in (outs[0], W):
+        Wh = Wt.cpu().numpy()
+        for j in range(F):
+            assert rel_fro(Wh[j], ref[j]) < 1e-11
