@@ -143,9 +143,10 @@ gw_status gw_minimax_inverse(int n_lt, double R, const double* alpha0,
  * With finalize != 0 the call then diagonalises K in FP64 on the device
  * (K is destroyed), keeps the eigenvectors whose eigenvalue is > eps_naf
  * (strict), at most max_keep of them when max_keep > 0, and writes
- *   U       device [n_aux][n_aux] FP64: row p holds the eigenvector of the
- *           p-th largest eigenvalue; rows 0 .. *n_naf-1 are the NAF basis
- *           (U^T of Eq. 13),
+ *   U       device [n_aux][n_aux] FP64: row p < *n_naf holds the
+ *           eigenvector of the p-th largest eigenvalue, so rows
+ *           0 .. *n_naf-1 are the NAF basis (U^T of Eq. 13); later rows are
+ *           unspecified,
  *   *n_naf  host, number of kept functions (>= 1 unless all eigenvalues are
  *           <= eps_naf, then 0),
  *   eigvals host [n_aux] or NULL: eigenvalues in descending order.

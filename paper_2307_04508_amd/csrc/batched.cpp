@@ -293,7 +293,7 @@ extern "C" gw_status gw_g0w0_batched(gw_ctx ctx, gw_precision prec, const gw_bat
     key.push_back(h);
     const void* bufs[] = {Rov, Rqp, Mm, What, sig, ctx->ws[WS_SYRK_PART], ctx->ws[WS_SYRK_SCALE],
                           ctx->ws[WS_SCREEN_A], ctx->ws[WS_SCREEN_PANEL], ctx->ws[WS_SIGMA_PART],
-                          ctx->ws[WS_SIGMA_W]};
+                          ctx->ws[WS_SIGMA_W], ctx->ws[WS_SIGMA_RT]};
     for (const void* p : bufs)
       key_add(key, reinterpret_cast<uintptr_t>(p));
     return key;

@@ -24,6 +24,7 @@ enum WsSlot {
   WS_SCREEN_PANEL,  // pivot column panels, scaled panels, pivot inverses
   WS_SIGMA_PART,    // per-column-block row-dot partials of W_nm
   WS_SIGMA_W,       // W_nm [F][Q*M] FP64
+  WS_SIGMA_RT,      // FP32 k-major copy of the QP rows of R~ for the contraction
   WS_EIG,           // eigensolver scratch (eigenvalues, off-diagonal, info)
   WS_QP,            // Pade / QP outputs
   WS_G_RT_OV,       // whole-step driver: NAF-transformed ov tensor
@@ -41,6 +42,9 @@ enum WsSlot {
   WS_B_WHAT,        // batched driver: screened interactions
   WS_B_SIGMA,       // batched driver: Sigma(i w) and QP outputs
   WS_B_EIG,         // batched driver: eigenvalues, off-diagonals, info
+  WS_TRI,           // tridiagonalisation exchange buffers and barrier counters
+  WS_EIG_Y,         // eigenvectors of the tridiagonal matrix
+  WS_NAF_T,         // k-major FP32 copies of the NAF transform's operands
   WS_COUNT
 };
 
@@ -191,6 +195,28 @@ struct NafEigJob {
   double* eig;          // host [A]: eigenvalues, descending
 };
 gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs);
+// FP32 transposes dst[c][r] = src[r][c] (c < cols, r < rows; rows up to
+// ld_dst - 1 are zero-filled), all jobs in one launch.
+struct TransposeJob {
+  const float* src;     // [rows][ld_src]
+  int64_t rows, ld_src;
+  int cols;
+  float* dst;           // [cols][ld_dst]
+  int64_t ld_dst;
+};
+gw_status transpose_f32(gw_ctx ctx, const std::vector<TransposeJob>& jobs);
+// Householder tridiagonalisation (LAPACK dsytrd form, lower) of symmetric
+// matrices held whole on chip by a cooperative launch; see tridiag.hip.
+struct TriIn {
+  double* K;            // device [n][n] symmetric; out: reflectors (column-major)
+  int n;
+  double* d;            // device [n]
+  double* e;            // device [n - 1]
+  double* tau;          // device [n - 1]
+};
+// Largest order the on-chip reduction takes on this context's device.
+int tridiag_max_order(gw_ctx ctx);
+gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& jobs);
 struct NafGemmJob {
   const void* A;        // [rows][K]
   const double* U;      // [>= ncols][K]
@@ -203,7 +229,8 @@ gw_status naf_gemm_batched(gw_ctx ctx, gw_precision prec, const std::vector<NafG
 // Workspace each call needs at given sizes (gw_reserve).
 size_t syrk_part_bytes(gw_precision prec, int64_t k_rows, int N, int L);
 void screen_ws_bytes(gw_precision prec, int N, int F, size_t* a_bytes, size_t* panel_bytes);
-void sigma_ws_bytes(int N, int64_t rows, int F, size_t* part_bytes, size_t* w_bytes);
+void sigma_ws_bytes(int N, int64_t rows, int F, size_t* part_bytes, size_t* w_bytes,
+                    size_t* rt_bytes);
 // Zero n doubles with a kernel (capturable, unlike hipMemsetAsync).
 gw_status fill_zero(gw_ctx ctx, double* p, int64_t n);
 gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L,

@@ -269,10 +269,11 @@ gw_status gw_reserve(gw_ctx ctx, gw_precision prec, const gw_dims* d) {
     part = std::max(part, gw::syrk_part_bytes(mp, k_chi, d->n_aux, 1));
     part = std::max(part, gw::syrk_part_bytes(mp, k_oo, d->n_aux, 1));
   }
-  size_t sa = 0, sp = 0, gp = 0, gwb = 0;
+  size_t sa = 0, sp = 0, gp = 0, gwb = 0, grt = 0;
   if (d->n_naf > 0 && d->n_w > 0) {
     gw::screen_ws_bytes(prec, d->n_naf, d->n_w, &sa, &sp);
-    gw::sigma_ws_bytes(d->n_naf, (int64_t)d->n_qp * d->n_mo, d->n_w, &gp, &gwb);
+    gw::sigma_ws_bytes(d->n_naf, (int64_t)d->n_qp * d->n_mo, d->n_w, &gp, &gwb, &grt);
+    if (prec != GW_FP32) grt = 0;
   }
   const struct { WsSlot slot; size_t bytes; } want[] = {
       {WS_SYRK_PART, part},
@@ -281,7 +282,8 @@ gw_status gw_reserve(gw_ctx ctx, gw_precision prec, const gw_dims* d) {
       {WS_SCREEN_PANEL, sp},
       {WS_SIGMA_PART, gp},
       {WS_SIGMA_W, gwb},
-      {WS_EIG, (2 * (size_t)d->n_aux + 8) * sizeof(double)},
+      {WS_SIGMA_RT, grt},
+      {WS_EIG, (3 * (size_t)d->n_aux + 8) * sizeof(double)},
       {WS_QP, 3 * (size_t)d->n_qp * sizeof(double)},
   };
   for (const auto& w : want)

@@ -3,9 +3,11 @@
 //  * Metric: K = s (R_oo^T R_oo + 2 R_ov^T R_ov), s = 2, with the virtual-
 //    virtual block omitted (Sec. 2), on the scaled-SYRK kernels with a
 //    constant scale.
-//  * Eigendecomposition of K in FP64 on the device (rocSOLVER syevd), then
-//    the kept eigenvectors (eigenvalue > eps_NAF, at most max_keep) are
-//    copied in descending order into U (row p = p-th eigenvector).
+//  * Eigendecomposition of K in FP64 on the device: Householder reduction to
+//    tridiagonal form held on chip (tridiag.hip), then rocSOLVER's orgtr and
+//    divide-and-conquer stedc; past the on-chip limit, rocSOLVER syevd.  The
+//    kept eigenvectors (eigenvalue > eps_NAF, at most max_keep) are copied in
+//    descending order into U (row p = p-th eigenvector).
 //  * Transform R~ = R U (Eq. 13): a GEMM with both operands contiguous along
 //    the auxiliary index; FP32 MFMA with FP64 partial sums every 256 terms,
 //    or FP64 MFMA.
@@ -17,6 +19,22 @@
 #include <vector>
 
 #include "common.hpp"
+
+namespace gw {
+// Eigenvalues (ascending, d_eval) of the symmetric matrix K (full storage;
+// destroyed: it receives the Householder reflectors, tau in d_tau) and the
+// eigenvectors of its tridiagonal form in the columns of Y (column-major).
+// d_e: n doubles of scratch.  Asynchronous.
+gw_status tri_eig(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_eval, double* d_e,
+                  double* d_tau, rocblas_int* d_info, double* Y);
+// Back-transformation of the last `cols` columns of Y to eigenvectors of
+// the original matrix (Y <- Q Y), from tri_eig's reflectors.
+gw_status tri_back(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_tau, double* Y,
+                   int cols);
+// Synchronises; GW_EDEVICE if a tridiagonalisation barrier timed out.
+gw_status check_tridiag(gw_ctx ctx);
+gw_status gemm_f32_direct(gw_ctx ctx, const std::vector<NafGemmJob>& jobs, const char* prof);
+}  // namespace gw
 
 namespace {
 
@@ -75,8 +93,9 @@ __global__ void unpad_batched_kernel(Batch bt) {
   for (int e = 0; e < kBatchElems; e += 256) unpad_elem(a, first + e + threadIdx.x);
 }
 
-__global__ void reorder_kernel(const double* __restrict__ V, int n, double* __restrict__ U) {
-  const int64_t total = (int64_t)n * n;
+__global__ void reorder_kernel(const double* __restrict__ V, int n, int rows,
+                               double* __restrict__ U) {
+  const int64_t total = (int64_t)rows * n;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = idx / n, c = idx % n;
@@ -227,6 +246,128 @@ __global__ __launch_bounds__(NT8, 2) void nt_gemm_f32_kernel(GemmArgs g0, Batch 
     }
 }
 
+// FP32 transform with both operands k-major: A^T = R^T ([K][ldat], a copy
+// of the rows made by gw::transpose_f32) and B^T = U^T in FP32 ([K][ldbt],
+// made by ut_kernel), so each 32 x 128 stage of either operand is 32 rows of
+// memory copied global -> LDS by global_load_lds_dwordx4 (lane l of a wave
+// fills bytes 16 l .. 16 l + 15: two 128-float rows per wave and
+// instruction).  8 waves of 32 x 64 on v_mfma_f32_32x32x2f32, four waves
+// per SIMD, FP64 running sums every 256 k; a per-k factor (1, or 0 past K)
+// masks the clamped tail rows.
+struct GemmDArgs {
+  const float* AT;      // [K][ldat]
+  int64_t ldat;         // multiple of 4, >= rows
+  const float* BT;      // [K][ldbt]
+  int ldbt;             // multiple of 4, >= ncols
+  float* C;             // [rows][ldc]; columns ncols .. ldc-1 are zeroed
+  int64_t rows;
+  int K, ncols;
+  int64_t ldc;
+  int row_tiles, col_tiles;
+};
+
+constexpr int BKD = 32;
+
+__global__ __launch_bounds__(NT8, 4) void nt_gemm_f32_direct_kernel(GemmDArgs g0, Batch bt) {
+  __shared__ __attribute__((aligned(16))) float As[2][BKD][BM];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BKD][BM];
+  __shared__ float Ss[2][BKD];
+  GemmDArgs g;
+  int64_t lid;
+  if (!unit_of(g0, bt, g, lid)) return;
+  const int ct = (int)(lid % g.col_tiles);
+  const int rt = (int)(lid / g.col_tiles);
+  const int64_t row0 = (int64_t)rt * BM;
+  const int col0 = ct * BM;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;            // rows wy*32, cols wx*64
+  const int nk = (g.K + BKD - 1) / BKD;
+  const int lrow = 2 * wave + (lane >> 5);
+  const int64_t ca = min(row0 + (int64_t)(lane & 31) * 4, g.ldat - 4);
+  const int cb = min(col0 + (lane & 31) * 4, g.ldbt - 4);
+  f32x16 acc[2];
+  double acc64[2][16];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { acc[j][r] = 0.f; acc64[j][r] = 0.0; }
+  float sreg = 0.f;
+  auto issue = [&](int kb, int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kr = min(kb + lrow + 16 * h, g.K - 1);
+      __builtin_amdgcn_global_load_lds(g.AT + (int64_t)kr * g.ldat + ca,
+                                       &As[buf][2 * wave + 16 * h][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(g.BT + (int64_t)kr * g.ldbt + cb,
+                                       &Bs[buf][2 * wave + 16 * h][0], 16, 0, 0);
+    }
+    if (tid < BKD) sreg = kb + tid < g.K ? 1.f : 0.f;
+  };
+  auto publish = [&](int buf) {
+    if (tid < BKD) Ss[buf][tid] = sreg;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+  constexpr int FLUSH_STAGES = 256 / BKD;
+  issue(0, 0);
+  publish(0);
+  const int arow = wy * 32 + (lane & 31);
+  const int bcol = wx * 64 + (lane & 31);
+  const int ksub = lane >> 5;
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) issue((it + 1) * BKD, cur ^ 1);
+#pragma unroll
+    for (int kk = 0; kk < BKD / 2; ++kk) {
+      const int kr = 2 * kk + ksub;
+      const float av = As[cur][kr][arow] * Ss[cur][kr];
+      const float b0 = Bs[cur][kr][bcol];
+      const float b1 = Bs[cur][kr][bcol + 32];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1, acc[1], 0, 0, 0);
+    }
+    if ((it + 1) % FLUSH_STAGES == 0 || it + 1 == nk) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          acc64[j][r] += (double)acc[j][r];
+          acc[j][r] = 0.f;
+        }
+    }
+    publish(cur ^ 1);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = row0 + wy * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int col = col0 + wx * 64 + j * 32 + (lane & 31);
+      if (row < g.rows && col < g.ldc)
+        g.C[row * g.ldc + col] = col < g.ncols ? (float)acc64[j][r] : 0.f;
+    }
+}
+
+// U^T in FP32: UT[k][c] = U[c][k] for c < ncols, zero for ncols <= c < ldbt.
+struct UtArgs {
+  const double* U;      // [>= ncols][K]
+  int K, ncols, ldbt;
+  float* UT;            // [K][ldbt]
+};
+
+__device__ __forceinline__ void ut_elem(const UtArgs& a, int64_t idx) {
+  if (idx >= (int64_t)a.K * a.ldbt) return;
+  const int k = (int)(idx / a.ldbt), c = (int)(idx % a.ldbt);
+  a.UT[idx] = c < a.ncols ? (float)a.U[(int64_t)c * a.K + k] : 0.f;
+}
+
+__global__ void ut_batched_kernel(Batch bt) {
+  UtArgs a;
+  int64_t first;
+  if (!block_of(bt, a, first)) return;
+  for (int e = 0; e < kBatchElems; e += 256) ut_elem(a, first + e + threadIdx.x);
+}
+
 constexpr int BK64 = 16;
 constexpr int LDK64 = BK64 + 2;
 
@@ -339,26 +480,35 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
   }
   rocblas_handle h = static_cast<rocblas_handle>(ctx->rocblas);
   rocblas_set_stream(h, ctx->stream);
-  double* ws = static_cast<double*>(gw::ws_get(ctx, WS_EIG, (2 * (size_t)n_aux + 8) * sizeof(double)));
+  double* ws = static_cast<double*>(gw::ws_get(ctx, WS_EIG, (3 * (size_t)n_aux + 8) * sizeof(double)));
   if (!ws) return GW_ENOMEM;
   double* d_eval = ws;
   double* d_e = ws + n_aux;
-  rocblas_int* d_info = reinterpret_cast<rocblas_int*>(ws + 2 * n_aux);
+  double* d_tau = ws + 2 * n_aux;
+  rocblas_int* d_info = reinterpret_cast<rocblas_int*>(ws + 3 * n_aux);
   const int pe = gw::prof_begin(ctx);
-  rocblas_status rs = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_lower, n_aux, K,
-                                       n_aux, d_eval, d_e, d_info);
-  if (rs != rocblas_status_success)
-    return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocsolver_dsyevd failed (%d)", (int)rs);
-  gw::prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
-  hipLaunchKernelGGL(reorder_kernel, dim3(grid_for((int64_t)n_aux * n_aux, 256)), dim3(256), 0,
-                     ctx->stream, K, n_aux, U);
-  GW_TRY(gw::launch_check(ctx, "reorder_kernel"));
+  // orders the on-chip reduction takes: tridiagonalisation, tridiagonal
+  // eigenvectors, then only the kept ones back-transformed; larger ones:
+  // rocSOLVER syevd
+  const bool tri = n_aux <= gw::tridiag_max_order(ctx);
+  double* V = K;
+  if (tri) {
+    V = static_cast<double*>(gw::ws_get(ctx, WS_EIG_Y, (size_t)n_aux * n_aux * sizeof(double)));
+    if (!V) return GW_ENOMEM;
+    GW_TRY(gw::tri_eig(ctx, h, K, n_aux, d_eval, d_e, d_tau, d_info, V));
+  } else {
+    const rocblas_status rs = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_lower,
+                                               n_aux, K, n_aux, d_eval, d_e, d_info);
+    if (rs != rocblas_status_success)
+      return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocsolver_dsyevd failed (%d)", (int)rs);
+  }
   std::vector<double> ev(n_aux);
   rocblas_int info = 0;
   GW_HIP(ctx, hipMemcpyAsync(ev.data(), d_eval, n_aux * sizeof(double), hipMemcpyDeviceToHost,
                              ctx->stream));
   GW_HIP(ctx, hipMemcpyAsync(&info, d_info, sizeof info, hipMemcpyDeviceToHost, ctx->stream));
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  GW_TRY(gw::check_tridiag(ctx));
   if (info != 0)
     return gw::fail(ctx, GW_ENOCONV, "gw_naf_compress: eigensolver info = %d", (int)info);
   int keep = 0;
@@ -366,6 +516,14 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
     if (ev[i] > eps_naf) ++keep; else break;
   }
   if (max_keep > 0) keep = std::min(keep, max_keep);
+  if (tri && keep > 0) GW_TRY(gw::tri_back(ctx, h, K, n_aux, d_tau, V, keep));
+  gw::prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
+  const int rows = tri ? keep : n_aux;
+  if (rows > 0) {
+    hipLaunchKernelGGL(reorder_kernel, dim3(grid_for((int64_t)rows * n_aux, 256)), dim3(256), 0,
+                       ctx->stream, V, n_aux, rows, U);
+    GW_TRY(gw::launch_check(ctx, "reorder_kernel"));
+  }
   *n_naf = keep;
   if (eigvals)
     for (int i = 0; i < n_aux; ++i) eigvals[i] = ev[n_aux - 1 - i];
@@ -386,6 +544,9 @@ extern "C" gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int 
   GW_REQUIRE(ctx, ld_out >= n_naf, "gw_naf_apply: ld_out < n_naf");
   if (n_rows == 0) return GW_OK;
   GW_HIP(ctx, hipSetDevice(ctx->device));
+  if (prec != GW_FP64)
+    return gw::gemm_f32_direct(ctx, {gw::NafGemmJob{R_in, U, R_out, n_rows, n_aux, n_naf, ld_out}},
+                               "naf_gemm_f32");
   const int rt = (int)((n_rows + BM - 1) / BM), ct = (int)((ld_out + BM - 1) / BM);
   GemmArgs g{R_in, U, R_out, n_rows, n_aux, n_naf, ld_out, rt, ct};
   const int64_t grid = (int64_t)rt * ct;
@@ -402,6 +563,45 @@ extern "C" gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int 
 }
 
 namespace gw {
+
+gw_status tri_eig(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_eval, double* d_e,
+                  double* d_tau, rocblas_int* d_info, double* Y) {
+  int pt = prof_begin(ctx);
+  GW_TRY(tridiag_jobs(ctx, {TriIn{K, n, d_eval, d_e, d_tau}}));
+  prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
+  pt = prof_begin(ctx);
+  const rocblas_status rs = rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, d_eval, d_e, Y, n,
+                                             d_info);
+  if (rs != rocblas_status_success)
+    return fail(ctx, GW_EDEVICE, "rocsolver_dstedc failed (%d)", (int)rs);
+  prof_end(ctx, pt, "naf_stedc", 0.0, 0.0);
+  return GW_OK;
+}
+
+gw_status tri_back(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_tau, double* Y,
+                   int cols) {
+  if (n < 2 || cols < 1) return GW_OK;
+  const int pt = prof_begin(ctx);
+  const rocblas_status rs =
+      rocsolver_dormtr(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n, cols,
+                       K, n, d_tau, Y + (size_t)(n - cols) * n, n);
+  if (rs != rocblas_status_success)
+    return fail(ctx, GW_EDEVICE, "rocsolver_dormtr failed (%d)", (int)rs);
+  prof_end(ctx, pt, "naf_ormtr", 0.0, 0.0);
+  return GW_OK;
+}
+
+gw_status check_tridiag(gw_ctx ctx) {
+  int f = 0;
+  GW_HIP(ctx, hipMemcpyAsync(&f, ctx->d_flags + 1, sizeof f, hipMemcpyDeviceToHost, ctx->stream));
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (f != 0) {
+    GW_HIP(ctx, hipMemsetAsync(ctx->d_flags + 1, 0, sizeof(int), ctx->stream));
+    GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return fail(ctx, GW_EDEVICE, "tridiagonalisation: a workgroup barrier timed out");
+  }
+  return GW_OK;
+}
 
 rocblas_handle naf_rocblas(gw_ctx ctx) {
   if (!ctx->rocblas) {
@@ -509,7 +709,55 @@ gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs) {
   return GW_OK;
 }
 
+// FP32 transforms C = A U^T of several jobs through k-major copies of A and
+// U (one transpose launch, one conversion launch, one GEMM launch).
+gw_status gemm_f32_direct(gw_ctx ctx, const std::vector<NafGemmJob>& jobs, const char* prof) {
+  auto r4 = [](int64_t x) { return std::max<int64_t>(4, (x + 3) / 4 * 4); };
+  size_t tot = 0;
+  for (const NafGemmJob& j : jobs)
+    if (j.rows > 0) tot += (size_t)j.K * (r4(j.rows) + r4(j.ncols));
+  if (tot == 0) return GW_OK;
+  float* ws = static_cast<float*>(ws_get(ctx, WS_NAF_T, tot * sizeof(float)));
+  if (!ws) return GW_ENOMEM;
+  std::vector<TransposeJob> tr;
+  std::vector<UtArgs> ut;
+  std::vector<int64_t> ut_n;
+  std::vector<GemmDArgs> d;
+  std::vector<int64_t> off(1, 0);
+  double flops = 0;
+  size_t o = 0;
+  for (const NafGemmJob& j : jobs) {
+    if (j.rows == 0) continue;
+    const int64_t ldat = r4(j.rows);
+    const int ldbt = (int)r4(j.ncols);
+    float* AT = ws + o;
+    o += (size_t)j.K * ldat;
+    float* BT = ws + o;
+    o += (size_t)j.K * ldbt;
+    tr.push_back(TransposeJob{static_cast<const float*>(j.A), j.rows, j.K, j.K, AT, ldat});
+    ut.push_back(UtArgs{j.U, j.K, j.ncols, ldbt, BT});
+    ut_n.push_back((int64_t)j.K * ldbt);
+    const int rt = (int)((j.rows + BM - 1) / BM), ct = (int)((j.ldc + BM - 1) / BM);
+    d.push_back(GemmDArgs{AT, ldat, BT, ldbt, static_cast<float*>(j.C), j.rows, j.K, j.ncols,
+                          j.ldc, rt, ct});
+    off.push_back(off.back() + (int64_t)rt * ct);
+    flops += 2.0 * (double)j.rows * j.K * (double)j.ncols;
+  }
+  GW_TRY(transpose_f32(ctx, tr));
+  GW_TRY(elementwise_batched(ctx, ut, ut_n, ut_batched_kernel, "ut_batched_kernel"));
+  constexpr int CHUNK = 8;
+  Batch bt;
+  GW_TRY(stage_batch(ctx, d, off, CHUNK, bt));
+  const int64_t grid = (off.back() + 8 * CHUNK - 1) / (8 * CHUNK) * (8 * CHUNK);
+  const int pi = prof_begin(ctx);
+  hipLaunchKernelGGL(nt_gemm_f32_direct_kernel, dim3((unsigned)grid), dim3(NT8), 0, ctx->stream,
+                     GemmDArgs{}, bt);
+  prof_end(ctx, pi, prof, flops, 0.0);
+  return launch_check(ctx, "naf transform");
+}
+
 gw_status naf_gemm_batched(gw_ctx ctx, gw_precision prec, const std::vector<NafGemmJob>& jobs) {
+  if (prec != GW_FP64) return gemm_f32_direct(ctx, jobs, "naf_gemm_f32");
   std::vector<GemmArgs> d;
   std::vector<int64_t> off(1, 0);
   double flops = 0;

@@ -391,6 +391,102 @@ __global__ __launch_bounds__(256) void update_batched_kernel(Batch bt) {
       }
 }
 
+// Outer level (pivot width 128 or 256, so pivot blocks are unions of whole
+// 128-tiles): A[I][J] -= sum_k P[I rows][k] C[J rows][k] for lower 128 x 128
+// tiles outside the pivot block's rows and columns.  8 waves of 32 x 64 on
+// v_mfma_f64_16x16x4f64; k in double-buffered chunks of 16, stored k-major
+// in LDS ([k][row], padded) so that the 16 rows an MFMA operand takes are
+// consecutive doubles.  Panel columns bw .. pw-1 hold zeros, so k runs over
+// whole chunks.
+constexpr int BU = 128;
+constexpr int BKU = 16;
+constexpr int LDU = BU + 8;
+
+__global__ __launch_bounds__(512, 2) void update128_batched_kernel(Batch bt) {
+  __shared__ double Ps[2][BKU][LDU];
+  __shared__ double Cs[2][BKU][LDU];
+  SwArgs sa;
+  int64_t lid;
+  if (!unit_of(SwArgs{}, bt, sa, lid)) return;
+  const int N = sa.N, pw = sa.pw, bw = sa.bw;
+  const int T = (N + BU - 1) / BU;
+  const int n_tiles = T * (T + 1) / 2;
+  const int j = (int)(lid / n_tiles);
+  int I, J;
+  lower_tile((int)(lid % n_tiles), I, J);
+  const int k_lo = sa.kb / BU, k_hi = (sa.kb + bw - 1) / BU;   // pivot block, in tiles
+  if ((I >= k_lo && I <= k_hi) || (J >= k_lo && J <= k_hi)) return;
+  const double* Pj = sa.P + (int64_t)j * N * pw;
+  const double* Cj = sa.C + (int64_t)j * N * pw;
+  double* Aj = sa.A + (int64_t)j * N * N;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;            // rows wy*32, cols wx*64
+  f64x4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // loader: rows (tid >> 3) + 64 h, k pair (tid & 7) * 2
+  const int lr = tid >> 3, lk = (tid & 7) * 2;
+  double2 rp[2], rc[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int pr = I * BU + lr + 64 * h, cr = J * BU + lr + 64 * h;
+      rp[h] = pr < N ? *reinterpret_cast<const double2*>(Pj + (int64_t)pr * pw + k0 + lk)
+                     : make_double2(0.0, 0.0);
+      rc[h] = cr < N ? *reinterpret_cast<const double2*>(Cj + (int64_t)cr * pw + k0 + lk)
+                     : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      Ps[buf][lk][lr + 64 * h] = rp[h].x;
+      Ps[buf][lk + 1][lr + 64 * h] = rp[h].y;
+      Cs[buf][lk][lr + 64 * h] = rc[h].x;
+      Cs[buf][lk + 1][lr + 64 * h] = rc[h].y;
+    }
+  };
+  const int nk = (bw + BKU - 1) / BKU;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload((it + 1) * BKU);
+#pragma unroll
+    for (int kk = 0; kk < BKU / 4; ++kk) {
+      const int kr = 4 * kk + (lane >> 4);
+      double af[2], bf[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = Ps[cur][kr][wy * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bf[b] = Cs[cur][kr][wx * 64 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = I * BU + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int col = J * BU + wx * 64 + b * 16 + (lane & 15);
+        if (row < N && col < N) {
+          double* e = Aj + (int64_t)row * N + col;
+          *e -= acc[a][b][r];
+        }
+      }
+}
+
 // Pivot rows / columns after the update: A(r, K) <- P[r] for r outside K;
 // A(K, K) <- -D^-1 (inner: from Dinv; outer: Dw already holds it), lower
 // triangle storage.
@@ -559,8 +655,18 @@ gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* s
                           },
                           8, false, panel_gemm_batched_kernel, 256, "panel_gemm"));
     }
-    GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.T * (a.T + 1) / 2; },
-                        8, false, update_batched_kernel, 256, "update_kernel"));
+    if (pw > B) {
+      GW_TRY(launch_units(ctx, dst, st,
+                          [](const SwArgs& a) {
+                            const int64_t t = (a.N + BU - 1) / BU;
+                            return (int64_t)a.F * t * (t + 1) / 2;
+                          },
+                          8, false, update128_batched_kernel, 512, "update128_kernel"));
+    } else {
+      GW_TRY(launch_units(ctx, dst, st,
+                          [](const SwArgs& a) { return (int64_t)a.F * a.T * (a.T + 1) / 2; }, 8,
+                          false, update_batched_kernel, 256, "update_kernel"));
+    }
     GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; },
                         1, true, writeback_batched_kernel, 256, "writeback"));
   }

@@ -10,7 +10,8 @@
 // tile writes one FP64 partial per row; a second kernel sums the partials
 // in a fixed order.
 //
-//  FP32:   v_mfma_f32_32x32x2f32, operands FP32, tile 128 x 128 x 32.
+//  FP32:   v_mfma_f32_32x32x2f32, operands FP32 and k-major (R~ transposed once
+//          per call), copied global -> LDS directly; tile 128 x 128 x 32.
 //  FP64:   v_mfma_f64_16x16x4f64, operands FP64, tile 128 x 128 x 16.
 #include <algorithm>
 #include <cmath>
@@ -27,6 +28,9 @@ inline int grid_for(int64_t n, int block) {
   return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
 }
 
+// Row stride of the k-major copy of the QP rows: a multiple of 4 floats.
+inline int64_t rt_ld(int64_t rows) { return std::max<int64_t>(4, (rows + 3) / 4 * 4); }
+
 struct BwbArgs {
   const void* R;      // [rows][ldr]
   const void* W;      // [F][N][N]
@@ -37,6 +41,8 @@ struct BwbArgs {
   int row_tiles;
   int col_tiles;
   double* part;       // [F][2 * col_tiles][rows]
+  const float* RT;    // FP32 k-major copy of R: [N][ldt] (bwb_f32_direct_kernel)
+  int64_t ldt;        // multiple of 4, >= rows
 };
 
 __device__ __forceinline__ void decode(const BwbArgs& a, int64_t lid, int& j, int& ct, int& rt) {
@@ -47,142 +53,120 @@ __device__ __forceinline__ void decode(const BwbArgs& a, int64_t lid, int& j, in
 
 // ------------------------------------------------------------------ FP32
 constexpr int BK32 = 32;
-constexpr int LDA32 = BK32 + 1;
 
-__global__ __launch_bounds__(NT, 1) void bwb_f32_kernel(BwbArgs a0, Batch bt) {
-  __shared__ float As[2][BM][LDA32];
-  __shared__ float Bs[2][BK32][BM];
+// FP32 with both operands k-major: A = R^T (a copy of R made by
+// transpose_kernel, [N][ldt]) and B = W^_j ([N][N], rows are k), so each
+// 32 x 128 stage of either operand is 32 rows of memory copied global -> LDS
+// by global_load_lds (lane l of a wave fills bytes 16 l .. 16 l + 15, or
+// 4 l .. 4 l + 3 when the rows of W^ are not 16-byte aligned): no loader
+// registers, no transposing LDS stores.  8 waves of 32 x 64 on
+// v_mfma_f32_32x32x2f32, four waves per SIMD.  The symmetric weighting of the
+// k blocks (1 for the diagonal block, 2 below it, 0 past N) is a per-k
+// factor on the A operand, kept in LDS next to the tiles.
+constexpr int NTD = 512;
+
+template <bool VEC>
+__global__ __launch_bounds__(NTD, 4) void bwb_f32_direct_kernel(BwbArgs a0, Batch bt) {
+  __shared__ __attribute__((aligned(16))) float As[2][BK32][BM];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK32][BM];
+  __shared__ float Ss[2][BK32];
   int j, ct, rt;
   BwbArgs a;
   int64_t lid;
   if (!unit_of(a0, bt, a, lid)) return;
   decode(a, lid, j, ct, rt);
-  const float* R = static_cast<const float*>(a.R);
-  const float* W = static_cast<const float*>(a.W) + (int64_t)j * a.N * a.N;
+  const int N = a.N;
+  const float* RT = a.RT;
+  const float* W = static_cast<const float*>(a.W) + (int64_t)j * N * N;
   const int64_t row0 = (int64_t)rt * BM;
   const int col0 = ct * BM;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wy = wave >> 1, wx = wave & 1;
-
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][jj][r] = 0.f;
-
-  // A loader: rows (tid >> 3) + 32 h, k offset (tid & 7) * 4
-  // B loader: rows (tid >> 5) + 8 h, col offset (tid & 31) * 4
-  float4 ra[4], rb[4];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int64_t row = row0 + (tid >> 3) + 32 * h;
-      const int k = k0 + (tid & 7) * 4;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row < a.rows) {
-        const int64_t off = row * a.ldr + k;
-        const float* p = R + off;
-        if (k + 3 < a.N && (off & 3) == 0) v = *reinterpret_cast<const float4*>(p);
-        else {
-          if (k + 0 < a.N) v.x = p[0];
-          if (k + 1 < a.N) v.y = p[1];
-          if (k + 2 < a.N) v.z = p[2];
-          if (k + 3 < a.N) v.w = p[3];
-        }
-      }
-      ra[h] = v;
-      const int kr = k0 + (tid >> 5) + 8 * h;
-      const int c = col0 + (tid & 31) * 4;
-      float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (kr < a.N) {
-        const int64_t off = (int64_t)kr * a.N + c;
-        const float* p = W + off;
-        if (c + 3 < a.N && (off & 3) == 0) u = *reinterpret_cast<const float4*>(p);
-        else {
-          if (c + 0 < a.N) u.x = p[0];
-          if (c + 1 < a.N) u.y = p[1];
-          if (c + 2 < a.N) u.z = p[2];
-          if (c + 3 < a.N) u.w = p[3];
-        }
-      }
-      rb[h] = u;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int r = (tid >> 3) + 32 * h, k = (tid & 7) * 4;
-      As[buf][r][k + 0] = ra[h].x;
-      As[buf][r][k + 1] = ra[h].y;
-      As[buf][r][k + 2] = ra[h].z;
-      As[buf][r][k + 3] = ra[h].w;
-      *reinterpret_cast<float4*>(&Bs[buf][(tid >> 5) + 8 * h][(tid & 31) * 4]) = rb[h];
-    }
-  };
-
-  // W^ is symmetric: only rows P >= col0 of W^ are needed.  The diagonal
-  // block (P in this tile's columns) counts once, every block below it twice
-  // (it stands for its mirror image too): the accumulator is halved after the
-  // diagonal block and doubled at the end (exact scalings).
+  const int wy = wave >> 1, wx = wave & 1;            // rows wy*32, cols wx*64
   const int kstart = col0;
-  const int nk = (a.N - kstart + BK32 - 1) / BK32;
-  constexpr int DIAG_STAGES = BM / BK32;
-  gload(kstart);
-  sstore(0);
-  __syncthreads();
+  const int nk = (N - kstart + BK32 - 1) / BK32;
+  const int kdiag = col0 + BM;                        // first k of the doubled blocks
+  // loader: wave w fills stage rows 2w + (lane >> 5) and 16 + 2w + (lane >> 5)
+  const int lrow = 2 * wave + (lane >> 5);
+  const int64_t ca = min(row0 + (int64_t)(lane & 31) * 4, a.ldt - 4);
+  const int cb = min(col0 + (lane & 31) * 4, N - 4);  // VEC: N >= 4
+
+  f32x16 acc[2];
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[jj][r] = 0.f;
+
+  float sreg = 0.f;
+  auto issue = [&](int kb, int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kr = min(kb + lrow + 16 * h, N - 1);
+      __builtin_amdgcn_global_load_lds(RT + (int64_t)kr * a.ldt + ca,
+                                       &As[buf][2 * wave + 16 * h][0], 16, 0, 0);
+      if (VEC) {
+        __builtin_amdgcn_global_load_lds(W + (int64_t)kr * N + cb, &Bs[buf][2 * wave + 16 * h][0],
+                                         16, 0, 0);
+      }
+    }
+    if (!VEC) {
+      // 4-byte copies: one instruction fills 64 consecutive floats (half a row)
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int q = wave + 8 * h;                   // 64 halves of 32 rows x 128 columns
+        const int kr = min(kb + (q >> 1), N - 1);
+        const int c = min(col0 + (q & 1) * 64 + lane, N - 1);
+        __builtin_amdgcn_global_load_lds(W + (int64_t)kr * N + c, &Bs[buf][q >> 1][(q & 1) * 64],
+                                         4, 0, 0);
+      }
+    }
+    if (tid < BK32) {
+      const int k = kb + tid;
+      sreg = k < N ? (k < kdiag ? 1.f : 2.f) : 0.f;
+    }
+  };
+  auto publish = [&](int buf) {
+    if (tid < BK32) Ss[buf][tid] = sreg;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+
+  issue(kstart, 0);
+  publish(0);
+  const int arow = wy * 32 + (lane & 31);
+  const int bcol = wx * 64 + (lane & 31);
+  const int ksub = lane >> 5;
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
-    if (it + 1 < nk) gload(kstart + (it + 1) * BK32);
+    if (it + 1 < nk) issue(kstart + (it + 1) * BK32, cur ^ 1);
 #pragma unroll
     for (int kk = 0; kk < BK32 / 2; ++kk) {
-      const int kr = kk * 2 + (lane >> 5);
-      const float a0 = As[cur][wy * 64 + (lane & 31)][kr];
-      const float a1 = As[cur][wy * 64 + 32 + (lane & 31)][kr];
-      const float b0 = Bs[cur][kr][wx * 64 + (lane & 31)];
-      const float b1 = Bs[cur][kr][wx * 64 + 32 + (lane & 31)];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      const int kr = 2 * kk + ksub;
+      const float av = As[cur][kr][arow] * Ss[cur][kr];
+      const float b0 = Bs[cur][kr][bcol];
+      const float b1 = Bs[cur][kr][bcol + 32];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1, acc[1], 0, 0, 0);
     }
-    if (it + 1 == DIAG_STAGES && nk > DIAG_STAGES) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 0.5f;
-    }
-    if (it + 1 < nk) sstore(cur ^ 1);
-    __syncthreads();
-  }
-  if (nk > DIAG_STAGES) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 2.0f;
+    publish(cur ^ 1);
   }
 
   // epilogue: per-row dot product with R[row][col] over this wave's 64 columns
+  const float* R = static_cast<const float*>(a.R);
   double* part = a.part + ((int64_t)j * 2 * a.col_tiles + 2 * ct + wx) * a.rows;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = row0 + wy * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    double sum = 0.0;
+    if (row < a.rows) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int lrow = wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      const int64_t row = row0 + lrow;
-      double s = 0.0;
-      if (row < a.rows) {
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const int col = col0 + wx * 64 + jj * 32 + (lane & 31);
-          if (col < a.N) s += (double)acc[i][jj][r] * (double)R[row * a.ldr + col];
-        }
+      for (int jj = 0; jj < 2; ++jj) {
+        const int col = col0 + wx * 64 + jj * 32 + (lane & 31);
+        if (col < N) sum += (double)acc[jj][r] * (double)R[row * a.ldr + col];
       }
-#pragma unroll
-      for (int off = 16; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-      if ((lane & 31) == 0 && row < a.rows) part[row] = s;
     }
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if ((lane & 31) == 0 && row < a.rows) part[row] = sum;
   }
 }
 
@@ -573,14 +557,28 @@ __global__ __launch_bounds__(256) void sigma_quad_batched_kernel(Batch bt) {
   sigma_quad_unit(a, (int)(blockIdx.x - bt.off[d]));
 }
 
+// FP32: rows of W^_j 16-byte aligned (N % 4 == 0, aligned base) take the
+// vector copies of bwb_f32_direct_kernel, other N its 4-byte copies.
+bool w_rows_aligned(const void* W, int N) {
+  return N >= 4 && N % 4 == 0 && reinterpret_cast<uintptr_t>(W) % 16 == 0;
+}
+
 void launch_bwb(gw_ctx ctx, gw_precision prec, const BwbArgs& a, const Batch& bt,
-                int64_t grid) {
+                int64_t grid, bool vec) {
   if (prec == GW_FP64)
     hipLaunchKernelGGL(bwb_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a, bt);
   else if (prec == GW_BF16X3)
     hipLaunchKernelGGL(bwb_bf16x3_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a, bt);
+  else if (vec)
+    hipLaunchKernelGGL(bwb_f32_direct_kernel<true>, dim3((unsigned)grid), dim3(NTD), 0,
+                       ctx->stream, a, bt);
   else
-    hipLaunchKernelGGL(bwb_f32_kernel, dim3((unsigned)grid), dim3(NT), 0, ctx->stream, a, bt);
+    hipLaunchKernelGGL(bwb_f32_direct_kernel<false>, dim3((unsigned)grid), dim3(NTD), 0,
+                       ctx->stream, a, bt);
+}
+
+gw::TransposeJob tr_job(const void* R, int64_t rows, int64_t ldr, int N, float* RT) {
+  return gw::TransposeJob{static_cast<const float*>(R), rows, ldr, N, RT, rt_ld(rows)};
 }
 
 }  // namespace
@@ -617,10 +615,19 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
       gw::ws_get(ctx, WS_SIGMA_PART, (size_t)F * n_part * rows * sizeof(double)));
   double* W = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_W, (size_t)F * rows * sizeof(double)));
   if (!part || !W) return GW_ENOMEM;
-  BwbArgs a{R_qp, W_hat, rows, N, ld_R, F, row_tiles, col_tiles, part};
+  BwbArgs a{R_qp, W_hat, rows, N, ld_R, F, row_tiles, col_tiles, part, nullptr, 0};
+  if (prec == GW_FP32) {
+    float* RT = static_cast<float*>(
+        gw::ws_get(ctx, WS_SIGMA_RT, (size_t)N * rt_ld(rows) * sizeof(float)));
+    if (!RT) return GW_ENOMEM;
+    const gw::TransposeJob t = tr_job(R_qp, rows, ld_R, N, RT);
+    GW_TRY(gw::transpose_f32(ctx, {t}));
+    a.RT = RT;
+    a.ldt = t.ld_dst;
+  }
   const int64_t grid = (int64_t)F * row_tiles * col_tiles;
   const int pi = gw::prof_begin(ctx);
-  launch_bwb(ctx, prec, a, Batch{}, grid);
+  launch_bwb(ctx, prec, a, Batch{}, grid, w_rows_aligned(W_hat, N));
   {
     const double esz = prec == GW_FP64 ? 8.0 : 4.0;
     // algorithmic work of the symmetric form: rows * N (N + 1) per frequency
@@ -666,6 +673,17 @@ extern "C" gw_status gw_sigma_diag_batched(gw_ctx ctx, gw_precision prec, int n_
   double* part = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_PART, part_tot * sizeof(double)));
   double* W = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_W, w_tot * sizeof(double)));
   if (!part || !W) return GW_ENOMEM;
+  float* RT = nullptr;
+  bool vec = true;
+  if (prec == GW_FP32) {
+    size_t rt_tot = 0;
+    for (int d = 0; d < n_jobs; ++d)
+      rt_tot += (size_t)jobs[d].n_naf * rt_ld((int64_t)jobs[d].n_qp * jobs[d].n_mo);
+    RT = static_cast<float*>(gw::ws_get(ctx, WS_SIGMA_RT, rt_tot * sizeof(float)));
+    if (!RT) return GW_ENOMEM;
+  }
+  std::vector<gw::TransposeJob> trs;
+  size_t rto = 0;
   std::vector<BwbArgs> bw;
   std::vector<WRedArgs> red;
   std::vector<QuadArgs> quad;
@@ -685,8 +703,17 @@ extern "C" gw_status gw_sigma_diag_batched(gw_ctx ctx, gw_precision prec, int n_
     const int row_tiles = (int)((rows + BM - 1) / BM);
     const int col_tiles = (N + BM - 1) / BM;
     const int n_part = 2 * col_tiles;
-    bw.push_back(BwbArgs{j.R_qp, j.W_hat, rows, N, j.ld_R ? j.ld_R : N, F, row_tiles, col_tiles,
-                         part + po});
+    BwbArgs b{j.R_qp, j.W_hat, rows, N, j.ld_R ? j.ld_R : N, F, row_tiles, col_tiles,
+              part + po, nullptr, 0};
+    if (prec == GW_FP32) {
+      const gw::TransposeJob t = tr_job(j.R_qp, rows, b.ldr, N, RT + rto);
+      trs.push_back(t);
+      b.RT = t.dst;
+      b.ldt = t.ld_dst;
+      rto += (size_t)N * t.ld_dst;
+      vec = vec && w_rows_aligned(j.W_hat, N);
+    }
+    bw.push_back(b);
     red.push_back(WRedArgs{part + po, n_part, rows, F, W + wo, j.W_nm});
     n_red.push_back((int64_t)F * rows);
     quad.push_back(QuadArgs{W + wo, F, j.n_qp, j.n_mo, d_eps, j.eps_F, d_om, d_wt, d_op,
@@ -706,8 +733,9 @@ extern "C" gw_status gw_sigma_diag_batched(gw_ctx ctx, gw_precision prec, int n_
   Batch bt;
   GW_TRY(gw::stage_batch(ctx, order, off, CHUNK, bt));
   const int64_t grid = (off.back() + 8 * CHUNK - 1) / (8 * CHUNK) * (8 * CHUNK);
+  if (prec == GW_FP32) GW_TRY(gw::transpose_f32(ctx, trs));
   const int pi = gw::prof_begin(ctx);
-  launch_bwb(ctx, prec, BwbArgs{}, bt, grid);
+  launch_bwb(ctx, prec, BwbArgs{}, bt, grid, vec);
   gw::prof_end(ctx, pi, prec == GW_FP64 ? "bwb_f64" : (prec == GW_BF16X3 ? "bwb_bf16x3" : "bwb_f32"),
                flops, bytes);
   GW_TRY(gw::launch_check(ctx, "batched bwb kernel"));
@@ -723,9 +751,59 @@ extern "C" gw_status gw_sigma_diag_batched(gw_ctx ctx, gw_precision prec, int n_
 
 namespace gw {
 
-void sigma_ws_bytes(int N, int64_t rows, int F, size_t* part_bytes, size_t* w_bytes) {
+void sigma_ws_bytes(int N, int64_t rows, int F, size_t* part_bytes, size_t* w_bytes,
+                    size_t* rt_bytes) {
   *part_bytes = (size_t)F * 2 * ((N + BM - 1) / BM) * rows * sizeof(double);
   *w_bytes = (size_t)F * rows * sizeof(double);
+  *rt_bytes = (size_t)N * rt_ld(rows) * sizeof(float);
+}
+
+}  // namespace gw
+
+namespace {
+
+// dst[c][r] = src[r][c] for c < cols, r < rows; rows .. ld_dst-1 zero.
+// 64 x 64 tiles through LDS, one workgroup each.
+__device__ __forceinline__ void transpose_tile(const gw::TransposeJob& t, int64_t tile) {
+  __shared__ float sh[64][65];
+  const int64_t ktiles = (t.cols + 63) / 64;
+  const int64_t r0 = (tile / ktiles) * 64;
+  const int c0 = (int)(tile % ktiles) * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;      // 256 threads: 4 rows a pass
+  for (int y = ty; y < 64; y += 4) {
+    const int64_t r = r0 + y;
+    const int c = c0 + tx;
+    sh[y][tx] = (r < t.rows && c < t.cols) ? t.src[r * t.ld_src + c] : 0.f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 64; y += 4) {
+    const int c = c0 + y;
+    const int64_t r = r0 + tx;
+    if (c < t.cols && r < t.ld_dst) t.dst[(int64_t)c * t.ld_dst + r] = sh[tx][y];
+  }
+}
+
+__global__ __launch_bounds__(256) void transpose_batched_kernel(Batch bt) {
+  const int64_t u = blockIdx.x;
+  if (u >= bt.units) return;
+  const int d = find_problem(bt.off, bt.n, u);
+  transpose_tile(static_cast<const gw::TransposeJob*>(bt.descs)[d], u - bt.off[d]);
+}
+
+}  // namespace
+
+namespace gw {
+
+gw_status transpose_f32(gw_ctx ctx, const std::vector<TransposeJob>& jobs) {
+  std::vector<int64_t> off(1, 0);
+  for (const TransposeJob& t : jobs)
+    off.push_back(off.back() + ((t.ld_dst + 63) / 64) * (int64_t)((t.cols + 63) / 64));
+  if (off.back() == 0) return GW_OK;
+  Batch bt;
+  GW_TRY(stage_batch(ctx, jobs, off, 1, bt));
+  hipLaunchKernelGGL(transpose_batched_kernel, dim3((unsigned)off.back()), dim3(256), 0,
+                     ctx->stream, bt);
+  return launch_check(ctx, "transpose_batched_kernel");
 }
 
 }  // namespace gw

@@ -10,7 +10,9 @@
 // bitwise reproducible.
 //
 //  FP32 / BF16x3: v_mfma_f32_32x32x2f32 / v_mfma_f32_32x32x16_bf16, FP32
-//                 accumulators added into FP64 registers every 256 rows.
+//                 accumulators added into FP64 registers every 256 rows
+//                 (FP32: per-lane FP64 sums; BF16x3: per split-K slice).
+//                 Aligned FP32 rows are copied global -> LDS directly.
 //  FP64:          v_mfma_f64_16x16x4f64.
 #include <algorithm>
 #include <cmath>
@@ -48,17 +50,15 @@ __device__ __forceinline__ void tile_coords(int t, int& ti, int& tj) {
 }
 
 // ------------------------------------------------------------------ FP32 MFMA
-// 8 waves (4 x 2), each owning a 32 x 64 slice of the 128 x 128 tile, so the
-// FP32 accumulators (32 AGPRs) and their FP64 running sums (64 VGPRs) leave
-// room for two waves per SIMD.  FAST: rows 16-byte aligned (row stride a
-// multiple of 4).  Tile loads then need no column guards: a float4 start
-// past the row end is clamped back inside the row, and lanes past column N
-// only feed outputs that are discarded.  Rows past the end are clamped and
-// zeroed with a select, keeping the loads branch-free.
+// 8 waves (4 x 2), each owning a 32 x 64 slice of the 128 x 128 tile: 32
+// FP32 accumulators and their 32 FP64 running sums per lane.  This kernel
+// takes rows of any stride and alignment (element loads with column
+// guards); rows whose stride is a multiple of 4 floats at a 16-byte aligned
+// base go to syrk_f32_direct_kernel below.
 constexpr int NT32 = 512;
 constexpr int BK32 = 32;
 
-template <bool FAST, bool SCALED>
+template <bool SCALED>
 __global__ __launch_bounds__(NT32, 2) void syrk_f32_kernel(SyrkArgs a0, Batch bt) {
   __shared__ float As[2][BK32][BM];
   __shared__ float Bs[2][BK32][BM];
@@ -99,35 +99,25 @@ __global__ __launch_bounds__(NT32, 2) void syrk_f32_kernel(SyrkArgs a0, Batch bt
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int64_t r = kb + lrow + 16 * h;
-      if (FAST) {
-        const bool ok = r < r1;
-        const int64_t rr = ok ? r : r1 - 1;
-        if (SCALED) rs[h] = scale[rr]; else rs[h] = csc;
-        rm[h] = ok ? 1.f : 0.f;
-        const float* row = X + rr * a.ld;
-        ra[h] = *reinterpret_cast<const float4*>(row + min(p0 + lcol, (int)a.ld - 4));
-        rb[h] = *reinterpret_cast<const float4*>(row + min(q0 + lcol, (int)a.ld - 4));
-      } else {
-        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
-        rs[h] = 0.f;
-        rm[h] = 0.f;
-        if (r < r1) {
-          if (SCALED) rs[h] = scale[r]; else rs[h] = csc;
-          rm[h] = 1.f;
-          const float* row = X + r * a.ld;
-          const int pa = p0 + lcol, pb = q0 + lcol;
-          if (pa + 0 < a.N) va.x = row[pa + 0];
-          if (pa + 1 < a.N) va.y = row[pa + 1];
-          if (pa + 2 < a.N) va.z = row[pa + 2];
-          if (pa + 3 < a.N) va.w = row[pa + 3];
-          if (pb + 0 < a.N) vb.x = row[pb + 0];
-          if (pb + 1 < a.N) vb.y = row[pb + 1];
-          if (pb + 2 < a.N) vb.z = row[pb + 2];
-          if (pb + 3 < a.N) vb.w = row[pb + 3];
-        }
-        ra[h] = va;
-        rb[h] = vb;
+      float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+      rs[h] = 0.f;
+      rm[h] = 0.f;
+      if (r < r1) {
+        if (SCALED) rs[h] = scale[r]; else rs[h] = csc;
+        rm[h] = 1.f;
+        const float* row = X + r * a.ld;
+        const int pa = p0 + lcol, pb = q0 + lcol;
+        if (pa + 0 < a.N) va.x = row[pa + 0];
+        if (pa + 1 < a.N) va.y = row[pa + 1];
+        if (pa + 2 < a.N) va.z = row[pa + 2];
+        if (pa + 3 < a.N) va.w = row[pa + 3];
+        if (pb + 0 < a.N) vb.x = row[pb + 0];
+        if (pb + 1 < a.N) vb.y = row[pb + 1];
+        if (pb + 2 < a.N) vb.z = row[pb + 2];
+        if (pb + 3 < a.N) vb.w = row[pb + 3];
       }
+      ra[h] = va;
+      rb[h] = vb;
     }
   };
   auto sstore = [&](int buf) {
@@ -183,6 +173,120 @@ __global__ __launch_bounds__(NT32, 2) void syrk_f32_kernel(SyrkArgs a0, Batch bt
         }
     }
     __syncthreads();
+  }
+
+  double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = wy * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int col = wx * 64 + j * 32 + (lane & 31);
+      out[row * BM + col] = acc64[j][r];
+    }
+}
+
+// FP32, rows 16-byte aligned: the same 128 x 128 tile and wave layout, with
+// the X tiles copied global -> LDS by global_load_lds_dwordx4 (lane l of a
+// wave writes bytes 16 l .. 16 l + 15 after the wave's LDS base, i.e. two
+// 128-float rows per wave and instruction), so no loader registers are held
+// across the MFMA block.  The per-row scale (zero for rows past the slice,
+// whose loads are clamped to the last row) goes to a small LDS vector and
+// multiplies the A operand as it is read.  About 120 VGPRs: four waves per
+// SIMD, two workgroups per CU.
+template <bool SCALED>
+__global__ __launch_bounds__(NT32, 4) void syrk_f32_direct_kernel(SyrkArgs a0, Batch bt) {
+  __shared__ __attribute__((aligned(16))) float As[2][BK32][BM];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK32][BM];
+  __shared__ float Ss[2][BK32];
+
+  SyrkArgs a;
+  int64_t lid;
+  if (!unit_of(a0, bt, a, lid)) return;
+  const int m = (int)(lid % a.L);
+  const int t = (int)((lid / a.L) % a.n_tiles);
+  const int s = (int)(lid / ((int64_t)a.L * a.n_tiles));
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int p0 = ti * BM, q0 = tj * BM;
+  const int64_t r0 = (int64_t)s * a.rows_per_split;
+  const int64_t r1 = min(r0 + a.rows_per_split, a.k_rows);
+  const int nk = r1 > r0 ? (int)((r1 - r0 + BK32 - 1) / BK32) : 0;
+
+  const float* X = static_cast<const float*>(a.X);
+  const float* scale = SCALED ? static_cast<const float*>(a.scale) + (int64_t)m * a.k_rows : nullptr;
+  const float csc = (float)a.cscale;
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;            // rows wy*32, cols wx*64
+  // loader: wave w fills tile rows 2w + (lane >> 5) and 16 + 2w + (lane >> 5),
+  // columns 4 (lane & 31) .. + 3 (clamped inside the row)
+  const int lrow = 2 * wave + (lane >> 5);
+  const int64_t ca = min(p0 + (lane & 31) * 4, (int)a.ld - 4);
+  const int64_t cb = min(q0 + (lane & 31) * 4, (int)a.ld - 4);
+
+  f32x16 acc[2];
+  double acc64[2][16];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { acc[j][r] = 0.f; acc64[j][r] = 0.0; }
+
+  // Issue the copies of stage kb into buffer buf; threads 0..31 also fetch
+  // the row scales into sreg (written to LDS before the next barrier).
+  float sreg = 0.f;
+  auto issue = [&](int64_t kb, int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t rr = min(kb + lrow + 16 * h, r1 - 1);
+      const float* row = X + rr * a.ld;
+      __builtin_amdgcn_global_load_lds(row + ca, &As[buf][2 * wave + 16 * h][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(row + cb, &Bs[buf][2 * wave + 16 * h][0], 16, 0, 0);
+    }
+    if (tid < BK32) {
+      // a global (not flat) load, so it need not wait for the LDS copies
+      const int64_t r = kb + tid;
+      sreg = r < r1 ? (SCALED ? ((const __attribute__((address_space(1))) float*)scale)[r]
+                              : csc)
+                    : 0.f;
+    }
+  };
+  auto publish = [&](int buf) {
+    if (tid < BK32) Ss[buf][tid] = sreg;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+
+  constexpr int FLUSH_STAGES = FLUSH_ROWS / BK32;
+  if (nk > 0) {
+    issue(r0, 0);
+    publish(0);
+  }
+  const int arow = wy * 32 + (lane & 31);
+  const int bcol = wx * 64 + (lane & 31);
+  const int ksub = lane >> 5;
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) issue(r0 + (int64_t)(it + 1) * BK32, cur ^ 1);
+#pragma unroll
+    for (int kk = 0; kk < BK32 / 2; ++kk) {
+      const int kr = 2 * kk + ksub;
+      const float av = As[cur][kr][arow] * Ss[cur][kr];
+      const float b0 = Bs[cur][kr][bcol];
+      const float b1 = Bs[cur][kr][bcol + 32];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1, acc[1], 0, 0, 0);
+    }
+    if ((it + 1) % FLUSH_STAGES == 0 || it + 1 == nk) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          acc64[j][r] += (double)acc[j][r];
+          acc[j][r] = 0.f;
+        }
+    }
+    publish(cur ^ 1);
   }
 
   double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
@@ -625,8 +729,8 @@ static void launch_syrk_kernel(gw_ctx ctx, gw_precision prec, bool fast, bool sc
                      : (scaled ? syrk_bf16x3_kernel<false, true> : syrk_bf16x3_kernel<false, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NTB), 0, ctx->stream, a, bt);
   } else {
-    auto kern = fast ? (scaled ? syrk_f32_kernel<true, true> : syrk_f32_kernel<true, false>)
-                     : (scaled ? syrk_f32_kernel<false, true> : syrk_f32_kernel<false, false>);
+    auto kern = fast ? (scaled ? syrk_f32_direct_kernel<true> : syrk_f32_direct_kernel<false>)
+                     : (scaled ? syrk_f32_kernel<true> : syrk_f32_kernel<false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT32), 0, ctx->stream, a, bt);
   }
 }

@@ -1,0 +1,357 @@
+// Householder reduction of a symmetric matrix to tridiagonal form, the first
+// stage of the NAF eigendecomposition (Eq. 12).  Output in the LAPACK
+// dsytrd form (lower): diagonal d, sub-diagonal e, reflector scalars tau,
+// and the reflectors v_k (v_k(k+1) = 1 implied) stored below the
+// sub-diagonal of column k, column-major.
+//
+// The reduction is one column per step, with the whole matrix held on chip:
+// a persistent cooperative launch of G workgroups, workgroup g keeping rows
+// g, g + G, g + 2G, ... (at most 13) in registers (and, past 3072 columns, one
+// column slot per row in LDS), thread t of it columns t, t + 512, ....  Step
+// k of the unblocked algorithm needs
+//   the Householder vector v_k of column k of A^(k-1),
+//   p = tau A^(k-1) v_k (rows > k),   w = p - (tau/2)(p.v_k) v_k,
+//   A^(k) = A^(k-1) - v_k w^T - w v_k^T.
+// The rank-2 update of step k-1 and the product with v_k touch the same
+// registers, so they run as one pass; column k of A^(k-1) is formed by every
+// workgroup from the pre-update column (published by its owners in the
+// previous pass) and the previous step's v and w.  A step then exchanges
+// two vectors through HBM (p, and the next pre-update column) and needs a
+// single barrier across the G workgroups.  Every workgroup computes v_k,
+// tau and the reductions redundantly, in the same order, so all hold the
+// same bits.  The barrier spins a bounded number of times; a timeout sets
+// the error flag and every workgroup leaves.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int TNT = 512;          // threads per workgroup
+constexpr int TNW = TNT / 64;     // waves per workgroup
+constexpr int TR = 13;            // matrix rows held per workgroup (max)
+constexpr int TC_MAX = 7;         // column slots per thread (max): n <= 3584
+constexpr int TC_REG = 6;         // column slots per thread held in registers
+
+struct TriJob {
+  double* K;          // [n][n] symmetric (full); out: reflectors (column-major, below sub-diag)
+  double* d;          // [n]
+  double* e;          // [n - 1]
+  double* tau;        // [n - 1]
+  double* pbuf;       // [2][n] exchange buffers (by step parity)
+  double* colbuf;     // [2][n]
+  unsigned* count;    // barrier counter, zero on entry
+  int n, G, wg0;      // order, workgroups, first workgroup of the job in the grid
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Exchange-buffer accesses are device-coherent (other workgroups, other XCDs).
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier across the G workgroups of one job (the counter only grows, so
+// pass number q waits for q * G arrivals).  Every wave first waits for its
+// own exchange-buffer stores; the arrival is a release and the exit an
+// acquire at device scope, so the stores of every workgroup are ordered
+// before the loads that follow the barrier.  Returns false after spin_limit
+// polls or when another workgroup raised the error flag.
+__device__ bool group_barrier(unsigned* count, unsigned target, int* err, int spin_limit,
+                              int* s_ok) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    for (int it = 0;; ++it) {
+      if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (it >= spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+template <int C>
+__global__ __launch_bounds__(TNT, 1) void tridiag_kernel(const TriJob* __restrict__ jobs,
+                                                         int n_jobs, int* err, int spin_limit) {
+  constexpr int NV = TNT * C;                       // vector length per workgroup (>= n)
+  constexpr int CR = C < TC_REG ? C : TC_REG;       // slots in registers
+  constexpr int CL = C - CR;                        // slots in LDS
+  __shared__ double vsh[2][NV];                     // v of the last two steps (by parity)
+  __shared__ double wsh[NV];                        // w of the previous step
+  __shared__ double red[TNW][TR + 2];               // per-wave partial sums
+  __shared__ double alds[CL > 0 ? CL * TR * TNT : 1];
+  __shared__ double bc[2];
+  __shared__ int s_ok;
+
+  int jb = 0;
+  while (jb + 1 < n_jobs && jobs[jb + 1].wg0 <= (int)blockIdx.x) ++jb;
+  const TriJob J = jobs[jb];
+  const int g = (int)blockIdx.x - J.wg0;
+  if (g < 0 || g >= J.G) return;
+  const int n = J.n, G = J.G;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R = (n - g + G - 1) / G;                // rows of this workgroup (<= TR)
+
+  // load the rows; publish column 0 (pre-update) for step 0
+  double a[TR][CR > 0 ? CR : 1];
+#pragma unroll
+  for (int r = 0; r < TR; ++r) {
+    const int i = g + G * r;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = tid + TNT * c;
+      const double v = (r < R && j < n) ? J.K[(size_t)i * n + j] : 0.0;
+      if (c < CR) a[r][c < CR ? c : 0] = v;
+      else alds[((c - CR) * TR + r) * TNT + tid] = v;
+    }
+    if (tid == 0 && r < R) st_dev(&J.colbuf[i], a[r][0]);
+  }
+  for (int x = tid; x < NV; x += TNT) {
+    vsh[0][x] = 0.0;
+    vsh[1][x] = 0.0;
+    wsh[x] = 0.0;
+  }
+  double vp[C], w[C], vn[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) vp[c] = w[c] = vn[c] = 0.0;
+  double tau_prev = 0.0;
+  // every workgroup has read K before any reflector is written into it
+  if (!group_barrier(J.count, (unsigned)G, err, spin_limit, &s_ok)) return;
+
+  for (int k = 0; k + 1 < n; ++k) {
+    const int pc = k & 1, pp = pc ^ 1;
+    // ---- column k of A^(k-1) and the previous step's w, on own indices
+    double pv[C], cv[C];
+    double sp = 0.0;
+    const double pk = k > 0 ? ld_dev(&J.pbuf[pp * n + k]) : 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = tid + TNT * c;
+      const bool on = j >= k && j < n;
+      pv[c] = (on && k > 0) ? ld_dev(&J.pbuf[pp * n + j]) : 0.0;
+      cv[c] = on ? ld_dev(&J.colbuf[pc * n + j]) : 0.0;
+      sp += pv[c] * vp[c];
+    }
+    sp = wave_sum(sp);
+    if (lane == 0) red[wave][TR] = sp;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < TNW; ++q) s += red[q][TR];
+    const double h = 0.5 * tau_prev * s;
+    const double vpk = vsh[pp][k];
+    const double wk = pk - h * vpk;
+    double xp = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = tid + TNT * c;
+      w[c] = pv[c] - h * vp[c];
+      wsh[j] = w[c];
+      cv[c] -= vp[c] * wk + w[c] * vpk;
+      if (j >= k + 2 && j < n) xp += cv[c] * cv[c];
+      if (j == k) bc[0] = cv[c];
+      if (j == k + 1) bc[1] = cv[c];
+    }
+    xp = wave_sum(xp);
+    if (lane == 0) red[wave][TR + 1] = xp;
+    __syncthreads();
+    double xn2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < TNW; ++q) xn2 += red[q][TR + 1];
+    const double dk = bc[0], alpha = bc[1];
+    // ---- Householder vector of column k (LAPACK dlarfg convention)
+    double beta = alpha, t = 0.0, scal = 0.0;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      t = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = tid + TNT * c;
+      vn[c] = j == k + 1 ? 1.0 : ((j >= k + 2 && j < n) ? cv[c] * scal : 0.0);
+      vsh[pc][j] = vn[c];
+    }
+    if (g == 0 && tid == 0) {
+      J.d[k] = dk;
+      J.e[k] = beta;
+      J.tau[k] = t;
+    }
+    __syncthreads();
+    if (tid < R) {
+      const int i = g + G * tid;
+      if (i >= k + 2) J.K[(size_t)k * n + i] = vsh[pc][i];
+    }
+    // ---- rank-2 update of step k-1 fused with p = tau A^(k-1) v_k
+    const int tnext = (k + 1) % TNT, cnext = (k + 1) / TNT;
+#pragma unroll
+    for (int r = 0; r < TR; ++r) {
+      if (r < R) {
+        const int i = g + G * r;
+        const double vpi = vsh[pp][i], wi = wsh[i];
+        double acc = 0.0, cn = 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          double x;
+          if (c < CR) {
+            x = a[r][c < CR ? c : 0] - (vpi * w[c] + wi * vp[c]);
+            a[r][c < CR ? c : 0] = x;
+          } else {
+            double& ref = alds[((c - CR) * TR + r) * TNT + tid];
+            x = ref - (vpi * w[c] + wi * vp[c]);
+            ref = x;
+          }
+          acc += x * vn[c];
+          if (c == cnext) cn = x;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) red[wave][r] = acc;
+        if (tid == tnext && i >= k + 1) st_dev(&J.colbuf[pp * n + i], cn);
+      }
+    }
+    __syncthreads();
+    if (tid < R) {
+      const int i = g + G * tid;
+      if (i > k) {
+        double p = 0.0;
+#pragma unroll
+        for (int q = 0; q < TNW; ++q) p += red[q][tid];
+        st_dev(&J.pbuf[pc * n + i], t * p);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) vp[c] = vn[c];
+    tau_prev = t;
+    if (!group_barrier(J.count, (unsigned)(k + 2) * G, err, spin_limit, &s_ok)) return;
+  }
+  // last diagonal entry: column n-1 of A^(n-2)
+  if (g == 0 && tid == 0) {
+    if (n == 1) {
+      J.d[0] = a[0][0];
+    } else {
+      const int k = n - 1, pp = (k - 1) & 1;
+      const double p = ld_dev(&J.pbuf[pp * n + k]);
+      const double vv = vsh[pp][k];
+      const double wl = p - 0.5 * tau_prev * (p * vv) * vv;
+      J.d[k] = ld_dev(&J.colbuf[(k & 1) * n + k]) - 2.0 * vv * wl;
+    }
+  }
+}
+
+template <int C>
+void* tridiag_fn() {
+  return reinterpret_cast<void*>(&tridiag_kernel<C>);
+}
+
+void* tridiag_fn_for(int C) {
+  switch (C) {
+    case 1: return tridiag_fn<1>();
+    case 2: return tridiag_fn<2>();
+    case 3: return tridiag_fn<3>();
+    case 4: return tridiag_fn<4>();
+    case 5: return tridiag_fn<5>();
+    case 6: return tridiag_fn<6>();
+    default: return tridiag_fn<7>();
+  }
+}
+
+}  // namespace
+
+namespace gw {
+
+int tridiag_max_order(gw_ctx ctx) {
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+      hipSuccess)
+    return 0;
+  return std::min(TR * n_cu, TNT * TC_MAX);
+}
+
+// Reduce every job's matrix to tridiagonal form.  Jobs are packed, largest
+// first, into cooperative launches whose workgroups are all resident; each
+// launch uses the column-slot count of its largest job.  Asynchronous on the
+// context's stream; a barrier timeout raises ctx->d_flags[1].
+gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in) {
+  const int n_jobs = (int)in.size();
+  if (n_jobs == 0) return GW_OK;
+  int n_cu = 0;
+  GW_HIP(ctx, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  // scratch: per job 4 n doubles of exchange buffers + one counter slot
+  size_t sc = 0;
+  for (const TriIn& j : in) sc += 4 * (size_t)j.n + 1;
+  double* ws = static_cast<double*>(ws_get(ctx, WS_TRI, sc * sizeof(double)));
+  if (!ws) return GW_ENOMEM;
+  GW_TRY(fill_zero(ctx, ws, (int64_t)sc));
+  std::vector<TriJob> all(n_jobs);
+  size_t o = 0;
+  for (int d = 0; d < n_jobs; ++d) {
+    const TriIn& j = in[d];
+    if (j.n < 1 || j.n > std::min(TR * n_cu, TNT * TC_MAX))
+      return fail(ctx, GW_EINVAL, "tridiagonalisation: order %d outside [1, %d]", j.n,
+                  std::min(TR * n_cu, TNT * TC_MAX));
+    TriJob t{};
+    t.K = j.K;
+    t.d = j.d;
+    t.e = j.e;
+    t.tau = j.tau;
+    t.pbuf = ws + o;
+    t.colbuf = ws + o + 2 * (size_t)j.n;
+    t.count = reinterpret_cast<unsigned*>(ws + o + 4 * (size_t)j.n);
+    t.n = j.n;
+    t.G = std::min(n_cu, (j.n + TR - 1) / TR);
+    t.wg0 = 0;
+    all[d] = t;
+    o += 4 * (size_t)j.n + 1;
+  }
+  std::vector<int> order(n_jobs);
+  for (int d = 0; d < n_jobs; ++d) order[d] = d;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return all[x].n > all[y].n; });
+  size_t pos = 0;
+  while (pos < order.size()) {
+    const int C = (all[order[pos]].n + TNT - 1) / TNT;
+    void* fn = tridiag_fn_for(C);
+    int per_cu = 0;
+    GW_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TNT, 0));
+    const int cap = per_cu * n_cu;
+    if (cap < all[order[pos]].G)
+      return fail(ctx, GW_EDEVICE, "tridiagonalisation: %d resident workgroups, %d needed", cap,
+                  all[order[pos]].G);
+    std::vector<TriJob> grp;
+    int wg = 0;
+    while (pos < order.size() && wg + all[order[pos]].G <= cap) {
+      TriJob t = all[order[pos]];
+      t.wg0 = wg;
+      wg += t.G;
+      grp.push_back(t);
+      ++pos;
+    }
+    const TriJob* dj = static_cast<const TriJob*>(stage(ctx, grp.data(), grp.size() * sizeof(TriJob)));
+    if (!dj) return GW_EINVAL;
+    int nj = (int)grp.size();
+    int* err = ctx->d_flags + 1;
+    int spin = 1 << 21;
+    void* args[] = {&dj, &nj, &err, &spin};
+    GW_HIP(ctx, hipLaunchCooperativeKernel(fn, dim3(wg), dim3(TNT), args, 0, ctx->stream));
+  }
+  return GW_OK;
+}
+
+}  // namespace gw

@@ -354,6 +354,48 @@ def test_naf_matches_oracle(gw, ctx, tiny_problem, prec):
     assert n2 == 37
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 200, 513, 1030, 3100])
+def test_naf_eigensolver_orders(gw, ctx, n):
+    """Eigendecomposition of the NAF metric across orders that exercise every
+    column-slot count of the on-chip tridiagonalisation (512 columns per slot,
+    the seventh slot in LDS) and the 1 x 1 and 2 x 2 cases: eigenvalues
+    against LAPACK, orthonormal eigenvectors, small residual K u = lambda u."""
+    _say(f"naf eigensolver n={n}")
+    rng = np.random.default_rng(100 + n)
+    m = n + 7
+    X = rng.standard_normal((m, n)) / np.sqrt(m)
+    K_ref = 4.0 * X.T @ X                        # the metric of R_ov = X (s = 2, factor 2)
+    lam_ref = np.sort(np.linalg.eigvalsh(K_ref))[::-1]
+    K = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    U = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    k, ev = gw.gw_naf_compress(ctx, "fp64", n, None, dev(X, "fp64"), K, 0, 1, -1.0, 0, U)
+    gw.gw_sync(ctx)
+    assert k == n
+    scale = lam_ref[0]
+    assert np.max(np.abs(ev - lam_ref)) <= 1e-12 * scale * max(1.0, np.sqrt(n) / 8)
+    Uh = U.cpu().numpy()                         # rows: eigenvectors, descending
+    assert np.abs(Uh @ Uh.T - np.eye(n)).max() < 1e-12 * max(1.0, np.sqrt(n) / 8)
+    res = K_ref @ Uh.T - Uh.T * ev[None, :]
+    assert np.abs(res).max() < 1e-12 * scale * max(1.0, np.sqrt(n) / 8)
+
+
+def test_naf_eigensolver_degenerate_spectrum(gw, ctx):
+    """A metric with one eigenvalue of multiplicity n (columns of R already
+    orthogonal): every reflector is the identity (tau = 0) and any orthonormal
+    basis is an answer."""
+    n = 300
+    X = np.zeros((n + 5, n))
+    X[:n, :n] = np.eye(n) * 0.5
+    K = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    U = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    k, ev = gw.gw_naf_compress(ctx, "fp64", n, None, dev(X, "fp64"), K, 0, 1, 0.5, 0, U)
+    gw.gw_sync(ctx)
+    assert k == n
+    assert np.abs(ev - 1.0).max() < 1e-14
+    Uh = U.cpu().numpy()
+    assert np.abs(Uh @ Uh.T - np.eye(n)).max() < 1e-13
+
+
 # ------------------------------------------------------------------ whole step
 
 def _lt_grid_for(prob, omega0):
