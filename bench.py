@@ -250,6 +250,51 @@ def run_streamed(args, cfg, gw, torch):
     ctx.close()
 
 
+def run_grid_sweep(args, cfg, gw, torch):
+    """Fig. 4 on the synthetic workload: G0W0 wall time and the largest QP
+    error over the QP states for Laplace grids of L points x modified-GL
+    grids of F frequencies, against the sum-over-states (no Laplace) result
+    on the largest F; plus the smallest L whose normalised minimax error is
+    below eps_LT = 1e-7 (Sec. 3) on the workload's bounds."""
+    import dataclasses
+    from gwsynth import make_problem
+    prob = make_problem(cfg, dtype=np.float32)
+    R = [torch.as_tensor(a).to(device="cuda", dtype=torch.float32).contiguous()
+         for a in (prob.R_oo, prob.R_ov, prob.R_qp)]
+    ctx = gw.Context(0)
+    F_list, L_list = (32, 64, 128), (8, 9, 10, 12, 14, 16, 18)
+
+    def timed(params, reps=2):
+        gw.gw_g0w0(ctx, args.prec, params, prob.eps, prob.qp, None, *R)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E, _, S, _, st = gw.gw_g0w0(ctx, args.prec, params, prob.eps, prob.qp, None, *R)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, E, S, st
+
+    ref_cfg = dataclasses.replace(cfg, n_freq=F_list[-1])
+    t_ref, E_ref, S_ref, _ = timed(gw.params_for(ref_cfg, no_lt=True))
+    log(f"reference (no Laplace, F={F_list[-1]}): {t_ref * 1e3:.1f} ms")
+    rows = []
+    for F in F_list:
+        t_sos, E_sos, _, _ = timed(gw.params_for(dataclasses.replace(cfg, n_freq=F), no_lt=True))
+        rows.append({"F": F, "L": None, "ms": round(t_sos * 1e3, 2),
+                     "speedup": round(t_ref / t_sos, 2),
+                     "qp_err_meV": float(np.max(np.abs(E_sos - E_ref)) * HARTREE_MEV)})
+        for L in L_list:
+            c2 = dataclasses.replace(cfg, n_freq=F, n_lt=L)
+            t, E, S, st = timed(gw.params_for(c2))
+            rows.append({"F": F, "L": L, "ms": round(t * 1e3, 2), "speedup": round(t_ref / t, 2),
+                         "qp_err_meV": float(np.max(np.abs(E - E_ref)) * HARTREE_MEV),
+                         "lt_err_norm": st.lt_err_norm, "status_ok": bool(np.all(S == 0))})
+            log(f"F={F} L={L}: {t * 1e3:.1f} ms, QP error {rows[-1]['qp_err_meV']:.3f} meV")
+    auto = gw.lt_points_for(prob.eps, cfg, 1e-7)
+    print(json.dumps({"grid_sweep": cfg.name, "prec": args.prec, "reference_ms": t_ref * 1e3,
+                      "rows": rows, "auto_L_eps_lt_1e-7": auto}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,12 +306,22 @@ def main():
                     help="steps of the FP64 path timed for comparison (0 = skip)")
     ap.add_argument("--bf16x3-steps", type=int, default=3,
                     help="steps of the BF16x3 path timed for comparison (0 = skip)")
+    ap.add_argument("--evgw-runs", type=int, default=1,
+                    help="timed five-cycle evGW runs (Sec. 3, Table 3) after the G0W0 steps "
+                         "(0 = skip)")
+    ap.add_argument("--no-lt-steps", type=int, default=1,
+                    help="steps of the same G0W0 without the Laplace transform (sum over "
+                         "states at every frequency, the paper's baseline; 0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--streamed", action="store_true",
                     help="stream the raw tensors in occupied chunks (the paper-scale workload; "
                          "prints its own JSON line)")
+    ap.add_argument("--grid-sweep", action="store_true",
+                    help="sweep Laplace points x integration frequencies on the workload "
+                         "(Fig. 4): time and QP error against the sum-over-states result "
+                         "on the largest frequency grid (prints its own JSON line)")
     ap.add_argument("--precs", default="fp64,fp32,bf16x3")
     ap.add_argument("--chunk-i", type=int, default=0)
     ap.add_argument("--chunk-gb", type=float, default=12.0)
@@ -285,6 +340,9 @@ def main():
     cfg = get_config(args.config)
     if args.streamed:
         run_streamed(args, cfg, gw, torch)
+        return
+    if args.grid_sweep:
+        run_grid_sweep(args, cfg, gw, torch)
         return
     t0 = time.perf_counter()
     prob = make_problem(cfg, dtype=np.float32)
@@ -357,6 +415,44 @@ def main():
                              "frac_of_fp32_peak": round(kr["tflops"] / 157.3, 4)}
         log(f"bf16x3 path: {wb * 1e3:.1f} ms/step")
 
+    evgw = None
+    if args.evgw_runs > 0:
+        gw.gw_evgw(ctx, args.prec, params, 5, prob.eps, prob.qp, None, *R)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.evgw_runs):
+            Ee, _, Se, _, ste = gw.gw_evgw(ctx, args.prec, params, 5, prob.eps, prob.qp, None, *R)
+        torch.cuda.synchronize()
+        evgw = {"cycles": 5, "wall_s": (time.perf_counter() - t0) / args.evgw_runs,
+                "naf_ms": round(ste.t_naf_ms, 3), "chi_ms": round(ste.t_chi_ms, 3),
+                "screen_ms": round(ste.t_screen_ms, 3), "sigma_ms": round(ste.t_sigma_ms, 3),
+                "qp_shift_vs_g0w0_meV": [round(float(x), 3)
+                                         for x in (Ee[-1] - Ee[0]) * HARTREE_MEV],
+                "last_step_meV": float(np.max(np.abs(Ee[-1] - Ee[-2])) * HARTREE_MEV),
+                "status": Se[-1].tolist()}
+        log(f"evGW (5 cycles): {evgw['wall_s'] * 1e3:.1f} ms")
+
+    no_lt = None
+    if args.no_lt_steps > 0:
+        p_sos = gw.params_for(cfg, no_lt=True)
+        gw.gw_g0w0(ctx, args.prec, p_sos, prob.eps, prob.qp, None, *R)
+        gw.gw_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.no_lt_steps):
+            Es, _, Ss, _, sts = gw.gw_g0w0(ctx, args.prec, p_sos, prob.eps, prob.qp, None, *R)
+        torch.cuda.synchronize()
+        ws = (time.perf_counter() - t0) / args.no_lt_steps
+        chis = kernel_rate(gw, ctx, "chi_sos_f32" if args.prec == "fp32" else "chi_sos_f64")
+        gw.gw_profile_enable(ctx, False)
+        no_lt = {"wall_s": ws, "lt_speedup": ws / wall,
+                 "chi_ms": round(sts.t_chi_ms, 3), "chi_speedup_lt": round(sts.t_chi_ms /
+                                                                         stage_ms["chi"], 3),
+                 "chi_tflops": None if not chis else round(chis["tflops"], 3),
+                 "qp_diff_vs_lt_meV": float(np.max(np.abs(Es - E)) * HARTREE_MEV),
+                 "status": Ss.tolist()}
+        log(f"without the Laplace transform: {ws * 1e3:.1f} ms/step")
+
     fp64 = None
     if args.fp64_steps > 0 and args.prec != "fp64":
         del R
@@ -425,6 +521,8 @@ def main():
         "lt_err_norm": st.lt_err_norm,
         "fp64": fp64,
         "bf16x3": bf16,
+        "evgw": evgw,
+        "no_laplace": no_lt,
         "qp_err": qp_err,
         "cpu_baseline": cpu,
     }

@@ -116,10 +116,17 @@ gw_status gw_freq_grid_mgl(int n, double x0, double* omega, double* weight);
  * w[n_lt] (host, x ascending) minimising max |1/y - sum_m w_m exp(-x_m y)|
  * on [y_min, y_max].  err_norm (may be NULL) receives the equioscillation
  * level of the normalised problem on t = y / y_min in [1, y_max / y_min].
- * 1 <= n_lt <= 16, 0 < y_min < y_max.  GW_ENOCONV if the Remez exchange
+ * 1 <= n_lt <= 20, 0 < y_min < y_max.  GW_ENOCONV if the Remez exchange
  * fails. */
 gw_status gw_lt_grid_minimax(int n_lt, double y_min, double y_max,
                              double* x, double* w, double* err_norm);
+
+/* Accuracy-driven Laplace grid (Sec. 3): the smallest n_lt <= max_lt
+ * (<= 20) whose normalised minimax error (err_norm of gw_lt_grid_minimax)
+ * is at most eps_lt, with its points and weights (x, w host [max_lt]).
+ * GW_ENOCONV (with *err_norm the error reached at max_lt) if none is. */
+gw_status gw_lt_grid_auto(double eps_lt, int max_lt, double y_min, double y_max, int* n_lt,
+                          double* x, double* w, double* err_norm);
 
 /* Minimax of 1/t on [1, R] by n_lt exponentials (the normalised problem
  * behind gw_lt_grid_minimax): alpha (ascending), omega host [n_lt], err the
@@ -189,6 +196,19 @@ gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_naf,
                                const void* R_chunk, int64_t ld_R,
                                int accumulate, int finalize, double* M);
 
+/* The polarizability without the Laplace transform (Eq. 3, the baseline the
+ * paper's speed-ups are measured against): for each frequency j (omega
+ * host [n_w]) the sum over states
+ *   P_j = sum_ia R_ia D_ia / (omega_j^2 + D_ia^2) R_ia^T,
+ * so that Pi_j = -2 s P_j.  The same scaled SYRK as gw_polarizability_lt
+ * with one "point" per frequency.  Arguments as there; P device
+ * [n_w][n_naf][n_naf] FP64. */
+gw_status gw_polarizability_sos(gw_ctx ctx, gw_precision prec, int n_naf, int n_w,
+                                const double* omega, int n_i, int n_virt,
+                                const double* eps_i, const double* eps_a,
+                                const void* R_chunk, int64_t ld_R, int accumulate,
+                                int finalize, double* P);
+
 /* ------------------------------------------------ a5 + a6: screening */
 
 /* Eqs. 2 and 10: for each frequency j (omega host [n_w]),
@@ -199,10 +219,18 @@ gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_naf,
  * W_hat device [n_w][n_naf][n_naf], FP64 for GW_FP64, FP32 otherwise
  * (rounded from the FP64 result); both triangles are written.
  * A non-positive pivot (1 - Pi not positive definite) is reported as
- * GW_ENOTSPD by the next synchronising call. */
+ * GW_ENOTSPD by the next synchronising call.  omega_j = 0 gives the static
+ * screened interaction W_hat(0) that a Bethe-Salpeter step built on the
+ * quasiparticle energies takes (Sec. 3, static screening). */
 gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_lt,
                     const double* x_lt, const double* M, int n_w,
                     const double* omega, void* W_hat);
+
+/* Eq. 2 from sum-over-states polarizabilities (gw_polarizability_sos):
+ * W_hat_j = (1 + 2 s P_j)^-1 - 1 for P device [n_w][n_naf][n_naf] FP64;
+ * otherwise as gw_screen. */
+gw_status gw_screen_sos(gw_ctx ctx, gw_precision prec, int n_naf, int n_w, const double* P,
+                        void* W_hat);
 
 /* ------------------------------------- a7 + a8: diagonal self-energy */
 
@@ -256,6 +284,10 @@ typedef struct {
   int max_iter;                     /* QP iterations                      */
   int freq_batch;                   /* frequencies per screening batch,
                                        0 = all at once                    */
+  int no_lt;                        /* 1: polarizability as the sum over
+                                       states at every frequency (Eq. 3,
+                                       the AC baseline without the Laplace
+                                       transform); 0: Laplace form        */
 } gw_params;
 
 typedef struct {
@@ -278,6 +310,28 @@ gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* params,
                   const void* R_oo, const void* R_ov, const void* R_qp,
                   double* eps_qp, double* z_factor, int* status,
                   double* sigma_iw, gw_stats* stats);
+
+/* Eigenvalue-self-consistent GW (Sec. 3, Table 3): n_cycles G0W0
+ * evaluations sharing one NAF basis (it depends only on the tensors).  Cycle
+ * 0 uses eps; cycle c > 0 uses the orbital energies made from cycle c-1's
+ * quasiparticle energies: QP states take them, other active occupied
+ * orbitals are shifted by the correction of the lowest QP state, other
+ * active virtual orbitals by that of the highest (frozen core unchanged).
+ * Each cycle rebuilds everything that depends on the energies: the Laplace
+ * grid bounds and points, the Laplace matrices M^m, the screening, the
+ * self-energy with its Fermi level.  The QP equation keeps the starting
+ * point as its base, E_n = eps_n + static_n + Re Sigma^c_n(E_n), with
+ * Sigma^c built from the cycle's energies.  Arguments as for gw_g0w0;
+ * outputs host: eps_qp [n_cycles][n_qp] (row c = cycle c), status
+ * [n_cycles][n_qp], z_factor [n_qp] of the last cycle (or NULL), eps_last
+ * [n_occ + n_virt] the energies the next cycle would use (or NULL).  stats
+ * (or NULL): NAF time, chi/screen/sigma/QP times summed over the cycles,
+ * total.  Synchronises. */
+gw_status gw_evgw(gw_ctx ctx, gw_precision prec, const gw_params* params, int n_cycles,
+                  const double* eps, const int* qp, const double* static_n,
+                  const void* R_oo, const void* R_ov, const void* R_qp,
+                  double* eps_qp, double* z_factor, int* status, double* eps_last,
+                  gw_stats* stats);
 
 /* ------------------------------------------------------------ autotuner */
 

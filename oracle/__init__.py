@@ -20,6 +20,7 @@ Transformation and Natural Auxiliary Functions", that it follows):
 * ``casida``  brute-force real-axis G0W0 from RPA excitations (the
               "analytic RI" reference of Sec. 4), tiny systems only.
 * ``g0w0``    the whole chain.
+* ``evgw``    eigenvalue-self-consistent GW on top of it (Sec. 3, Table 3).
 
 Every function is pinned by tests against closed forms, invariants and brute
 force; none is marked "parity unpinned".

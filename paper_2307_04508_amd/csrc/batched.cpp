@@ -93,7 +93,7 @@ extern "C" gw_status gw_g0w0_batched(gw_ctx ctx, gw_precision prec, const gw_bat
   GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
              "gw_g0w0_batched: unknown precision %d", (int)prec);
   GW_REQUIRE(ctx, P && mols && n_mol >= 1, "gw_g0w0_batched: NULL argument or no molecules");
-  GW_REQUIRE(ctx, P->n_lt >= 1 && P->n_lt <= 16 && P->n_freq >= 1 && P->n_pade >= 1 &&
+  GW_REQUIRE(ctx, P->n_lt >= 1 && P->n_lt <= 20 && P->n_freq >= 1 && P->n_pade >= 1 &&
                       P->n_pade <= 256 && P->n_freq * P->n_lt <= 4096 && P->max_iter >= 1 &&
                       P->tol > 0 && P->x0 > 0,
              "gw_g0w0_batched: bad grid or QP parameters");

@@ -45,6 +45,7 @@ enum WsSlot {
   WS_TRI,           // tridiagonalisation exchange buffers and barrier counters
   WS_EIG_Y,         // eigenvectors of the tridiagonal matrix
   WS_NAF_T,         // k-major FP32 copies of the NAF transform's operands
+  WS_EIG_BACK,      // block-reflector factors and products of the back-transformation
   WS_COUNT
 };
 
@@ -216,6 +217,8 @@ struct TriIn {
 };
 // Largest order the on-chip reduction takes on this context's device.
 int tridiag_max_order(gw_ctx ctx);
+// Workspace of the NAF back-transformation (WS_EIG_BACK) at order n.
+size_t back_ws_bytes(int n);
 gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& jobs);
 struct NafGemmJob {
   const void* A;        // [rows][K]
@@ -236,7 +239,8 @@ gw_status fill_zero(gw_ctx ctx, double* p, int64_t n);
 gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L,
                           const double* d_x, const double* d_w, int n_i,
                           int n_virt, const double* d_eps_i,
-                          const double* d_eps_a, void* scale);
+                          const double* d_eps_a, void* scale,
+                          int sos);
 
 }  // namespace gw
 

@@ -16,7 +16,7 @@
 
 namespace {
 
-constexpr int kMaxLt = 16;
+constexpr int kMaxLt = 20;
 
 struct ExpSum {
   int k = 0;
@@ -162,16 +162,16 @@ ExpSum from_theta(int k, const double* th) {
   return s;
 }
 
-// Levenberg-Marquardt on sum_i |e_i / scale|^p, p = 2 .. 128.  Keeps the last
-// iterate whose error still alternates 2k+1 times.
-bool lp_refine(int k, double R, const std::vector<double>& xs, ExpSum& s) {
+// Levenberg-Marquardt on sum_i |e_i / scale|^p, p = p0 .. 128 (doubling).
+// Keeps the last iterate whose error still alternates 2k+1 times.
+bool lp_refine(int k, double R, const std::vector<double>& xs, ExpSum& s, int p0 = 2) {
   const int n = 2 * k, m = (int)xs.size();
   std::vector<double> th(n), J((size_t)m * n), r(m), JtJ(n * n), g(n);
   for (int i = 0; i < k; ++i) { th[i] = std::log(s.om[i]); th[k + i] = std::log(s.al[i]); }
   bool have = false;
   ExpSum best = s;
   std::vector<double> pts, vals;
-  for (int p = 2; p <= 128; p *= 2) {
+  for (int p = p0; p <= 128; p *= 2) {
     const double scale = max_err(from_theta(k, th.data()), xs);
     auto cost = [&](const std::vector<double>& t) {
       ExpSum q = from_theta(k, t.data());
@@ -204,7 +204,14 @@ bool lp_refine(int k, double R, const std::vector<double>& xs, ExpSum& s) {
       bool improved = false;
       for (int tries = 0; tries < 30; ++tries) {
         std::vector<double> A(JtJ), d(n);
-        for (int a = 0; a < n; ++a) { A[a * n + a] *= (1.0 + lam); d[a] = -g[a]; }
+        // Marquardt scaling plus a small ridge: a term whose exponential has
+        // underflowed on [1, R] leaves a zero column that would stop the solve.
+        double dmax = 0;
+        for (int a = 0; a < n; ++a) dmax = std::max(dmax, JtJ[a * n + a]);
+        for (int a = 0; a < n; ++a) {
+          A[a * n + a] = A[a * n + a] * (1.0 + lam) + lam * 1e-14 * dmax;
+          d[a] = -g[a];
+        }
         if (!solve_dense(n, A, d)) { lam *= 10; continue; }
         std::vector<double> tn(th);
         for (int a = 0; a < n; ++a) tn[a] += d[a];
@@ -230,17 +237,39 @@ bool lp_refine(int k, double R, const std::vector<double>& xs, ExpSum& s) {
   return have;
 }
 
+// Absolute rounding noise of err_at near t = 1, where 1/t and the exponential
+// sum are both of order one: the equioscillation test cannot be sharper.
+constexpr double kErrNoise = 1e-14;
+
 // Remez exchange: solve e(x_i) = sgn_i E at the alternation points by damped
 // Newton in (log omega, log alpha, E), then move the points to the extrema.
+// Converged once the extremal errors agree to 1e-9 relative or to the noise.
 bool remez(int k, double R, ExpSum& s, double& E_out) {
   const int n = 2 * k + 1;
   std::vector<double> pts, vals;
+  double prev_spread = 1e300;
   for (int outer = 0; outer < 100; ++outer) {
     extrema(s, R, pts, vals);
+    // A start continued from a longer interval has lost the alternation at
+    // t = R (the end value has the sign of the last interior extremum): R
+    // joins the reference with the alternating sign, as in the classic
+    // exchange, and the next iterate alternates there again.
+    if ((int)pts.size() == n - 1 && pts.back() < R) {
+      pts.push_back(R);
+      vals.push_back(err_at(s, R));
+    }
     if ((int)pts.size() != n) return false;
     double emax = 0, emin = 1e300;
     for (double v : vals) { emax = std::max(emax, std::fabs(v)); emin = std::min(emin, std::fabs(v)); }
-    if (emax - emin <= 1e-12 * emax) { E_out = vals[0]; return true; }
+    const double spread = emax - emin;
+    if (spread <= std::max(1e-12 * emax, kErrNoise)) { E_out = vals[0]; return true; }
+    // no longer improving at a level the final test accepts: rounding in
+    // the extrema limits any further progress
+    if (spread <= std::max(1e-9 * emax, kErrNoise) && spread > 0.5 * prev_spread) {
+      E_out = vals[0];
+      return true;
+    }
+    prev_spread = spread;
     std::vector<double> sg(n);
     for (int i = 0; i < n; ++i) sg[i] = ((vals[0] < 0) ? -1.0 : 1.0) * ((i & 1) ? -1.0 : 1.0);
     std::vector<double> th(n);
@@ -289,7 +318,7 @@ bool remez(int k, double R, ExpSum& s, double& E_out) {
   double emax = 0, emin = 1e300;
   for (double v : vals) { emax = std::max(emax, std::fabs(v)); emin = std::min(emin, std::fabs(v)); }
   E_out = vals[0];
-  return emax - emin <= 1e-9 * emax;
+  return emax - emin <= std::max(1e-9 * emax, kErrNoise);
 }
 
 // Converged minimax solutions of 1/t on [1, R] for a grid of (k, log10 R),
@@ -317,6 +346,42 @@ bool remez_continue(int k, double lr0, const ExpSum& s0, double lr1, ExpSum& out
   return remez_continue(k, mid, half, lr1, out, E, depth + 1);
 }
 
+// k-term start from a (k-1)-term solution: log(alpha) and the density
+// log(omega / (alpha dlog(alpha)/di)) interpolated linearly in the index and
+// resampled on k points over the same range.
+ExpSum stretch(const ExpSum& p, int k) {
+  const int m = p.k;
+  std::vector<int> ord(m);
+  for (int i = 0; i < m; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return p.al[a] < p.al[b]; });
+  std::vector<double> la(m), lq(m);
+  for (int i = 0; i < m; ++i) la[i] = std::log(p.al[ord[i]]);
+  for (int i = 0; i < m; ++i) {
+    const double d = i == 0 ? la[1] - la[0]
+                   : i == m - 1 ? la[m - 1] - la[m - 2] : 0.5 * (la[i + 1] - la[i - 1]);
+    lq[i] = std::log(p.om[ord[i]]) - la[i] - std::log(d);
+  }
+  ExpSum s;
+  s.k = k;
+  for (int j = 0; j < k; ++j) {
+    const double ip = double(j) * (m - 1) / (k - 1);
+    const int i0 = std::min(int(ip), m - 2);
+    const double f = ip - i0;
+    const double lA = la[i0] * (1 - f) + la[i0 + 1] * f;
+    const double lQ = lq[i0] * (1 - f) + lq[i0 + 1] * f;
+    const double d = (la[i0 + 1] - la[i0]) * double(m - 1) / (k - 1);
+    s.al[j] = std::exp(lA);
+    s.om[j] = std::exp(lQ + lA) * d;
+  }
+  return s;
+}
+
+std::vector<double> sample_points(double R) {
+  std::vector<double> xs(3000);
+  for (int i = 0; i < 3000; ++i) xs[i] = std::exp(std::log(R) * i / 2999.0);
+  return xs;
+}
+
 bool table_solve(int k, double R, ExpSum& s, double& E) {
   const double lr = std::log10(R);
   const MinimaxEntry* best = nullptr;
@@ -332,6 +397,22 @@ bool table_solve(int k, double R, ExpSum& s, double& E) {
     s0.om[i] = std::exp(best->log_omega[i]);
   }
   return remez_continue(k, best->log10R, s0, lr, s, E, 0);
+}
+
+// Unseeded solve: the table; else the (k-1)-term solution stretched to k
+// terms, refined in L_p and finished by the Remez exchange; else from a
+// trapezoid start.
+bool unseeded_solve(int k, double R, ExpSum& s, double& E) {
+  if (table_solve(k, R, s, E)) return true;
+  const std::vector<double> xs = sample_points(R);
+  ExpSum prev;
+  double Ep = 0;
+  if (k >= 3 && unseeded_solve(k - 1, R, prev, Ep)) {
+    s = stretch(prev, k);
+    if (lp_refine(k, R, xs, s) && remez(k, R, s, E)) return true;
+  }
+  s = initial_guess(k, R, xs);
+  return lp_refine(k, R, xs, s) && remez(k, R, s, E);
 }
 
 }  // namespace
@@ -397,9 +478,11 @@ gw_status gw_freq_grid_mgl(int n, double x0, double* omega, double* weight) {
   return GW_OK;
 }
 
-// Minimax of 1/t on [1, R]: seeded Remez when a start is given; otherwise a
-// start interpolated (in log R) from the table of converged solutions, then
-// the from-scratch route (trapezoid start, L_p refinement, Remez).
+// Minimax of 1/t on [1, R]: seeded Remez when a start is given (L_p
+// refinement first if the start does not alternate yet); otherwise a start
+// continued in log R from the table of converged solutions, then the
+// (k-1)-term solution stretched to k terms, then the from-scratch route
+// (trapezoid start, L_p refinement, Remez).
 gw_status gw_minimax_inverse(int n_lt, double R, const double* alpha0,
                              const double* omega0, double* alpha, double* omega,
                              double* err) {
@@ -413,14 +496,16 @@ gw_status gw_minimax_inverse(int n_lt, double R, const double* alpha0,
     s.k = n_lt;
     for (int i = 0; i < n_lt; ++i) { s.al[i] = alpha0[i]; s.om[i] = omega0[i]; }
     ok = remez(n_lt, R, s, E);
-  } else {
-    ok = table_solve(n_lt, R, s, E);
     if (!ok) {
-      std::vector<double> xs(3000);
-      for (int i = 0; i < 3000; ++i) xs[i] = std::exp(std::log(R) * i / 2999.0);
-      s = initial_guess(n_lt, R, xs);
-      ok = lp_refine(n_lt, R, xs, s) && remez(n_lt, R, s, E);
+      // the start does not alternate 2k+1 times on this interval: refine it
+      // in L_p first (from p = 32: it is a near-minimax start already)
+      s.k = n_lt;
+      for (int i = 0; i < n_lt; ++i) { s.al[i] = alpha0[i]; s.om[i] = omega0[i]; }
+      const std::vector<double> xs = sample_points(R);
+      ok = lp_refine(n_lt, R, xs, s, 32) && remez(n_lt, R, s, E);
     }
+  } else {
+    ok = unseeded_solve(n_lt, R, s, E);
   }
   if (!ok) return gw::fail(nullptr, GW_ENOCONV, "gw_minimax_inverse: Remez exchange failed");
   std::vector<int> ord(n_lt);
@@ -448,6 +533,28 @@ gw_status gw_lt_grid_minimax(int n_lt, double y_min, double y_max, double* x,
     w[i] = om[i] / y_min;
   }
   return GW_OK;
+}
+
+gw_status gw_lt_grid_auto(double eps_lt, int max_lt, double y_min, double y_max, int* n_lt,
+                          double* x, double* w, double* err_norm) {
+  gw::clear_error(nullptr);
+  if (!(eps_lt > 0) || max_lt < 1 || max_lt > kMaxLt || !n_lt || !x || !w)
+    return gw::fail(nullptr, GW_EINVAL, "gw_lt_grid_auto: need eps_lt > 0, 1 <= max_lt <= %d",
+                    kMaxLt);
+  double err = 0;
+  for (int k = 1; k <= max_lt; ++k) {
+    const gw_status st = gw_lt_grid_minimax(k, y_min, y_max, x, w, &err);
+    if (st != GW_OK) return st;
+    if (err <= eps_lt) {
+      *n_lt = k;
+      if (err_norm) *err_norm = err;
+      return GW_OK;
+    }
+  }
+  if (err_norm) *err_norm = err;
+  return gw::fail(nullptr, GW_ENOCONV,
+                  "gw_lt_grid_auto: %d points leave a minimax error of %.3g > %.3g", max_lt, err,
+                  eps_lt);
 }
 
 }  // extern "C"

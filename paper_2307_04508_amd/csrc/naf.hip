@@ -4,9 +4,11 @@
 //    virtual block omitted (Sec. 2), on the scaled-SYRK kernels with a
 //    constant scale.
 //  * Eigendecomposition of K in FP64 on the device: Householder reduction to
-//    tridiagonal form held on chip (tridiag.hip), then rocSOLVER's orgtr and
-//    divide-and-conquer stedc; past the on-chip limit, rocSOLVER syevd.  The
-//    kept eigenvectors (eigenvalue > eps_NAF, at most max_keep) are copied in
+//    tridiagonal form held on chip (tridiag.hip), rocSOLVER's divide-and-
+//    conquer stedc on the tridiagonal matrix, then the kept eigenvectors
+//    back-transformed in blocks of reflectors (compact WY form, GEMMs and a
+//    triangular solve); past the on-chip limit, rocSOLVER syevd.  The kept
+//    eigenvectors (eigenvalue > eps_NAF, at most max_keep) are copied in
 //    descending order into U (row p = p-th eigenvector).
 //  * Transform R~ = R U (Eq. 13): a GEMM with both operands contiguous along
 //    the auxiliary index; FP32 MFMA with FP64 partial sums every 256 terms,
@@ -100,6 +102,48 @@ __global__ void reorder_kernel(const double* __restrict__ V, int n, int rows,
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = idx / n, c = idx % n;
     U[idx] = V[(int64_t)(n - 1 - p) * n + c];
+  }
+}
+
+// Back-transformation of the tridiagonal eigenvectors (Y <- Q Y with
+// Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^T) in blocks of kBackNb
+// reflectors, each block in the compact form I - V T V^T.  T comes from the
+// identity T^{-1} = diag(1 / tau) + (strictly upper part of V^T V), which
+// follows from appending one reflector at a time to the product (the larft
+// recurrence): the Gram matrices of all blocks are one batched GEMM, and T is
+// applied by a triangular solve with T^{-1} instead of being formed.
+constexpr int kBackNb = 128;
+
+// Reflector storage (column-major, ld n; v_k below row k + 1 of column k)
+// made explicit in place: zeros above row k + 1 and a one at row k + 1.  A
+// reflector with tau = 0 (H_k = I) becomes the zero vector.
+__global__ void explicit_reflectors_kernel(double* __restrict__ V, int n,
+                                           const double* __restrict__ tau) {
+  const int k = blockIdx.x;                        // column, 0 .. n - 2
+  const bool zero = tau[k] == 0.0;
+  double* col = V + (int64_t)k * n;
+  const int top = zero ? n : k + 2;                // rows rewritten
+  for (int i = threadIdx.x; i < top; i += blockDim.x)
+    col[i] = (i == k + 1 && !zero) ? 1.0 : 0.0;
+}
+
+// S (Gram matrices of the blocks, column-major nb x nb each, ld kBackNb)
+// becomes T^{-1} in place: strictly upper part kept, 1 / tau on the
+// diagonal (1 for tau = 0, whose zero reflector contributes nothing), zeros
+// below.
+__global__ void tinv_kernel(double* __restrict__ S, int n_blocks, int n_refl,
+                            const double* __restrict__ tau) {
+  const int b = blockIdx.x;
+  double* T = S + (int64_t)b * kBackNb * kBackNb;
+  for (int e = threadIdx.x; e < kBackNb * kBackNb; e += blockDim.x) {
+    const int i = e % kBackNb, j = e / kBackNb;
+    if (i > j) {
+      T[e] = 0.0;
+    } else if (i == j) {
+      const int k = b * kBackNb + i;
+      const double t = k < n_refl ? tau[k] : 0.0;
+      T[e] = t != 0.0 ? 1.0 / t : 1.0;
+    }
   }
 }
 
@@ -578,16 +622,64 @@ gw_status tri_eig(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_eval
   return GW_OK;
 }
 
+size_t back_ws_bytes(int n) {
+  const size_t blocks = n > 1 ? (size_t)(n - 1 + kBackNb - 1) / kBackNb : 0;
+  return (blocks * kBackNb * kBackNb + (size_t)kBackNb * n) * sizeof(double);
+}
+
 gw_status tri_back(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_tau, double* Y,
                    int cols) {
   if (n < 2 || cols < 1) return GW_OK;
   const int pt = prof_begin(ctx);
-  const rocblas_status rs =
-      rocsolver_dormtr(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n, cols,
-                       K, n, d_tau, Y + (size_t)(n - cols) * n, n);
-  if (rs != rocblas_status_success)
-    return fail(ctx, GW_EDEVICE, "rocsolver_dormtr failed (%d)", (int)rs);
-  prof_end(ctx, pt, "naf_ormtr", 0.0, 0.0);
+  const int n_refl = n - 1, nb = kBackNb;
+  const int n_blocks = (n_refl + nb - 1) / nb, n_full = n_refl / nb;
+  double* ws = static_cast<double*>(ws_get(ctx, WS_EIG_BACK, back_ws_bytes(n)));
+  if (!ws) return GW_ENOMEM;
+  double* S = ws;                                        // [n_blocks][nb][nb]
+  double* W = ws + (size_t)n_blocks * nb * nb;           // [cols][nb]
+  double* Yk = Y + (size_t)(n - cols) * n;               // kept columns, ld n
+  hipLaunchKernelGGL(explicit_reflectors_kernel, dim3(n_refl), dim3(256), 0, ctx->stream, K, n,
+                     d_tau);
+  GW_TRY(launch_check(ctx, "explicit_reflectors_kernel"));
+  const double one = 1.0, zero = 0.0, minus_one = -1.0;
+  auto ok = [&](rocblas_status rs, const char* what) {
+    return rs == rocblas_status_success
+               ? GW_OK
+               : fail(ctx, GW_EDEVICE, "naf back-transformation: %s failed (%d)", what, (int)rs);
+  };
+  // Gram matrices V_b^T V_b over the full height (rows above the block are zeros)
+  if (n_full > 0)
+    GW_TRY(ok(rocblas_dgemm_strided_batched(h, rocblas_operation_transpose,
+                                            rocblas_operation_none, nb, nb, n, &one, K, n,
+                                            (rocblas_stride)nb * n, K, n, (rocblas_stride)nb * n,
+                                            &zero, S, nb, (rocblas_stride)nb * nb, n_full),
+              "Gram GEMM"));
+  if (n_full < n_blocks) {
+    const int w = n_refl - n_full * nb;
+    const double* Vb = K + (size_t)n_full * nb * n;
+    GW_TRY(ok(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, w, w, n, &one,
+                            Vb, n, Vb, n, &zero, S + (size_t)n_full * nb * nb, nb),
+              "Gram GEMM"));
+  }
+  hipLaunchKernelGGL(tinv_kernel, dim3(n_blocks), dim3(256), 0, ctx->stream, S, n_blocks, n_refl,
+                     d_tau);
+  GW_TRY(launch_check(ctx, "tinv_kernel"));
+  // Y <- Q_0 (Q_1 (... Q_last Y)): the last block first
+  for (int b = n_blocks - 1; b >= 0; --b) {
+    const int k0 = b * nb, w = std::min(nb, n_refl - k0), r0 = k0 + 1, m = n - r0;
+    const double* Vb = K + (size_t)k0 * n + r0;          // rows r0.., ld n
+    GW_TRY(ok(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, w, cols, m,
+                            &one, Vb, n, Yk + r0, n, &zero, W, nb),
+              "V^T Y"));
+    GW_TRY(ok(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                            rocblas_diagonal_non_unit, w, cols, &one, S + (size_t)b * nb * nb, nb,
+                            W, nb),
+              "T solve"));
+    GW_TRY(ok(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, cols, w,
+                            &minus_one, Vb, n, W, nb, &one, Yk + r0, n),
+              "Y - V W"));
+  }
+  prof_end(ctx, pt, "naf_ormtr", 4.0 * (double)n * n * cols, 0.0);
   return GW_OK;
 }
 

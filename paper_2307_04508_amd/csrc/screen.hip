@@ -32,15 +32,17 @@ inline int grid_for(int64_t n, int block) {
 
 // A_j[p][q] = delta_pq + 2 s sum_m exp(-w_j^2 x_m) M^m[p][q], lower triangle.
 struct AsmArgs {
-  const double* M;      // [L][N][N]
+  const double* M;      // [L][N][N]; sum-over-states: [F][N][N] sums P_j
   int L, N;
   const double* x;      // [L]
   const double* omega;  // [F]
   int F;
   double* A;            // [F][N][N]
+  int sos;              // 1: A_j = 1 + 2 s P_j (Eq. 3 without the Laplace transform)
 };
 
 __device__ __forceinline__ void load_coef(const AsmArgs& a, double* coef) {
+  if (a.sos) return;
   for (int i = threadIdx.x; i < a.F * a.L; i += blockDim.x) {
     const int j = i / a.L, m = i % a.L;
     coef[i] = 4.0 * exp(-a.omega[j] * a.omega[j] * a.x[m]);   // 2 s, s = 2
@@ -53,9 +55,13 @@ __device__ __forceinline__ void assemble_elem(const AsmArgs& a, const double* co
   if (idx >= NN) return;
   const int p = (int)(idx / a.N), q = (int)(idx % a.N);
   if (q > p) return;
+  const double d = (p == q) ? 1.0 : 0.0;
+  if (a.sos) {
+    for (int j = 0; j < a.F; ++j) a.A[j * NN + idx] = d + 4.0 * a.M[j * NN + idx];   // 2 s, s = 2
+    return;
+  }
   double mv[32];
   for (int m = 0; m < a.L; ++m) mv[m] = a.M[m * NN + idx];
-  const double d = (p == q) ? 1.0 : 0.0;
   for (int j = 0; j < a.F; ++j) {
     double v = d;
     for (int m = 0; m < a.L; ++m) v += coef[j * a.L + m] * mv[m];
@@ -676,21 +682,22 @@ gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* s
 // Assemble, sweep and finish the given screening jobs (device pointers,
 // staged x and omega).
 struct ScreenJob {
-  const double* M;      // device [L][N][N]
+  const double* M;      // device [L][N][N] (sum-over-states: [F][N][N] sums P_j)
   const double* x;      // device [L]
   const double* omega;  // device [F]
   int N, F;
   void* W_hat;
 };
 
-gw_status screen_jobs(gw_ctx ctx, gw_precision prec, int L, const std::vector<ScreenJob>& jobs) {
+gw_status screen_jobs(gw_ctx ctx, gw_precision prec, int L, const std::vector<ScreenJob>& jobs,
+                      int sos = 0) {
   size_t a_tot = 0;
   std::vector<SweepSet> sets;
   int flag_base = 0, smem = 0;
   double flops = 0, bytes = 0;
   for (const ScreenJob& j : jobs) {
     if (prec != GW_FP64) a_tot += (size_t)j.F * j.N * j.N;
-    smem = std::max(smem, j.F * L);
+    if (!sos) smem = std::max(smem, j.F * L);
   }
   double* Aws = nullptr;
   if (a_tot) {
@@ -706,7 +713,7 @@ gw_status screen_jobs(gw_ctx ctx, gw_precision prec, int L, const std::vector<Sc
     if (prec != GW_FP64) ao += (size_t)j.F * j.N * j.N;
     sets.push_back(SweepSet{A, j.N, j.F, flag_base});
     flag_base += j.F;
-    asm_d.push_back(AsmArgs{j.M, L, j.N, j.x, j.omega, j.F, A});
+    asm_d.push_back(AsmArgs{j.M, L, j.N, j.x, j.omega, j.F, A, sos});
     n_asm.push_back((int64_t)j.N * j.N);
     fin_d.push_back(FinArgs{A, j.N, j.F, j.W_hat});
     n_fin.push_back((int64_t)j.F * j.N * j.N);
@@ -734,7 +741,7 @@ gw_status screen_jobs(gw_ctx ctx, gw_precision prec, int L, const std::vector<Sc
                                    "finish_batched_kernel");
   };
   // outer pivot width: the rank of the trailing update (autotuned per shape)
-  std::string key = "screen";
+  std::string key = sos ? "screen_sos" : "screen";
   for (const ScreenJob& j : jobs) key += ":" + std::to_string(j.N) + "x" + std::to_string(j.F);
   const int pw = gw::tune(ctx, key, {BO, 128, B}, [&](int c) { return run(c, false); });
   return run(pw, true);
@@ -757,6 +764,19 @@ extern "C" gw_status gw_screen(gw_ctx ctx, gw_precision prec, int n_naf, int n_l
   const double* dw = gw::stage_t(ctx, omega, n_w);
   if (!dx || !dw) return GW_EINVAL;
   return screen_jobs(ctx, prec, n_lt, {ScreenJob{M, dx, dw, n_naf, n_w, W_hat}});
+}
+
+extern "C" gw_status gw_screen_sos(gw_ctx ctx, gw_precision prec, int n_naf, int n_w,
+                                   const double* P, void* W_hat) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_screen_sos: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_screen_sos: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_naf >= 1 && n_w >= 1, "gw_screen_sos: bad sizes (n_naf=%d n_w=%d)", n_naf,
+             n_w);
+  GW_REQUIRE(ctx, P && W_hat, "gw_screen_sos: NULL argument");
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  return screen_jobs(ctx, prec, 1, {ScreenJob{P, nullptr, nullptr, n_naf, n_w, W_hat}}, 1);
 }
 
 extern "C" gw_status gw_screen_batched(gw_ctx ctx, gw_precision prec, int n_lt, int n_jobs,

@@ -311,7 +311,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 constexpr int NTB = 256;
 constexpr int BKB = 32;
-constexpr int LDB = BKB + 8;        // padded k stride (bf16) of an LDS row
+constexpr int LDB = BKB;            // k stride (bf16) of an LDS row; 16-byte chunks XOR-swizzled
+__device__ __forceinline__ int swz(int col, int k) { return (((k >> 3) ^ ((col >> 2) & 3)) << 3) | (k & 7); }
 
 __device__ __forceinline__ void split4(const float4 v, float s, bf16x4& hi, bf16x4& lo) {
   const float x[4] = {v.x * s, v.y * s, v.z * s, v.w * s};
@@ -407,13 +408,14 @@ __global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a0, Batch 
     for (int c = 0; c < 4; ++c) {
       bf16x4 v;
       v = bf16x4{ah[0][c], ah[1][c], ah[2][c], ah[3][c]};
-      *reinterpret_cast<bf16x4*>(&Ah[buf][lcol + c][krow]) = v;
+      const int ks = swz(lcol + c, krow);
+      *reinterpret_cast<bf16x4*>(&Ah[buf][lcol + c][ks]) = v;
       v = bf16x4{al[0][c], al[1][c], al[2][c], al[3][c]};
-      *reinterpret_cast<bf16x4*>(&Al[buf][lcol + c][krow]) = v;
+      *reinterpret_cast<bf16x4*>(&Al[buf][lcol + c][ks]) = v;
       v = bf16x4{bh[0][c], bh[1][c], bh[2][c], bh[3][c]};
-      *reinterpret_cast<bf16x4*>(&Bh[buf][lcol + c][krow]) = v;
+      *reinterpret_cast<bf16x4*>(&Bh[buf][lcol + c][ks]) = v;
       v = bf16x4{bl[0][c], bl[1][c], bl[2][c], bl[3][c]};
-      *reinterpret_cast<bf16x4*>(&Bl[buf][lcol + c][krow]) = v;
+      *reinterpret_cast<bf16x4*>(&Bl[buf][lcol + c][ks]) = v;
     }
   };
 
@@ -434,10 +436,11 @@ __global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a0, Batch 
       for (int i = 0; i < 2; ++i) {
         const int pr = wy * 64 + i * 32 + (lane & 31);
         const int qc = wx * 64 + i * 32 + (lane & 31);
-        ahf[i] = *reinterpret_cast<const bf16x8*>(&Ah[cur][pr][ks + kl]);
-        alf[i] = *reinterpret_cast<const bf16x8*>(&Al[cur][pr][ks + kl]);
-        bhf[i] = *reinterpret_cast<const bf16x8*>(&Bh[cur][qc][ks + kl]);
-        blf[i] = *reinterpret_cast<const bf16x8*>(&Bl[cur][qc][ks + kl]);
+        const int ka = swz(pr, ks + kl), kb2 = swz(qc, ks + kl);
+        ahf[i] = *reinterpret_cast<const bf16x8*>(&Ah[cur][pr][ka]);
+        alf[i] = *reinterpret_cast<const bf16x8*>(&Al[cur][pr][ka]);
+        bhf[i] = *reinterpret_cast<const bf16x8*>(&Bh[cur][qc][kb2]);
+        blf[i] = *reinterpret_cast<const bf16x8*>(&Bl[cur][qc][kb2]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -651,6 +654,7 @@ struct ScaleArgs {
   const double* eps_i;
   const double* eps_a;
   void* out;            // [L][n_i * n_virt], FP64 or FP32
+  int sos;              // 0: Laplace factors (x, w); 1: D / (x^2 + D^2), x = frequencies
 };
 
 template <typename T>
@@ -661,7 +665,8 @@ __device__ __forceinline__ void scale_elem(const ScaleArgs& s, int64_t idx) {
   const int m = (int)(idx / k);
   const int i = (int)(r / s.n_virt), aa = (int)(r % s.n_virt);
   const double d = s.eps_a[aa] - s.eps_i[i];
-  static_cast<T*>(s.out)[idx] = (T)(s.w[m] * d * exp(-d * d * s.x[m]));
+  const double v = s.sos ? d / (s.x[m] * s.x[m] + d * d) : s.w[m] * d * exp(-d * d * s.x[m]);
+  static_cast<T*>(s.out)[idx] = (T)v;
 }
 
 template <typename T>
@@ -691,9 +696,10 @@ namespace gw {
 
 gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L, const double* d_x,
                           const double* d_w, int n_i, int n_virt,
-                          const double* d_eps_i, const double* d_eps_a, void* scale) {
+                          const double* d_eps_i, const double* d_eps_a, void* scale,
+                          int sos) {
   const int64_t n = (int64_t)L * n_i * n_virt;
-  const ScaleArgs sa{L, d_x, d_w, n_i, n_virt, d_eps_i, d_eps_a, scale};
+  const ScaleArgs sa{L, d_x, d_w, n_i, n_virt, d_eps_i, d_eps_a, scale, sos};
   if (prec == GW_FP64)
     hipLaunchKernelGGL(lt_scale_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0,
                        ctx->stream, sa);
@@ -799,7 +805,7 @@ gw_status lt_scale_batched(gw_ctx ctx, gw_precision prec, const std::vector<Scal
   std::vector<ScaleArgs> d;
   std::vector<int64_t> n;
   for (const ScaleJob& j : jobs) {
-    d.push_back(ScaleArgs{j.L, j.x, j.w, j.n_i, j.n_virt, j.eps_i, j.eps_a, j.out});
+    d.push_back(ScaleArgs{j.L, j.x, j.w, j.n_i, j.n_virt, j.eps_i, j.eps_a, j.out, 0});
     n.push_back((int64_t)j.L * j.n_i * j.n_virt);
   }
   return elementwise_batched(ctx, d, n, prec == GW_FP64 ? lt_scale_batched_kernel<double>
@@ -923,12 +929,48 @@ extern "C" gw_status gw_polarizability_lt(gw_ctx ctx, gw_precision prec, int n_n
     const size_t esz = prec == GW_FP64 ? 8 : 4;
     scale = gw::ws_get(ctx, WS_SYRK_SCALE, (size_t)n_lt * k * esz);
     if (!scale) return GW_ENOMEM;
-    GW_TRY(gw::lt_scale_launch(ctx, prec, n_lt, dx, dw, n_i, n_virt, dei, dea, scale));
+    GW_TRY(gw::lt_scale_launch(ctx, prec, n_lt, dx, dw, n_i, n_virt, dei, dea, scale, 0));
   }
   GW_TRY(gw::syrk_launch(ctx, prec, R_chunk, k, n_naf, ld_R, n_lt, scale, 1.0, M, accumulate,
                          prec == GW_FP64 ? "chi_syrk_f64"
                                          : (prec == GW_BF16X3 ? "chi_syrk_bf16x3" : "chi_syrk_f32")));
   if (finalize) GW_TRY(gw::mirror_lower(ctx, M, n_lt, n_naf));
+  return GW_OK;
+}
+
+extern "C" gw_status gw_polarizability_sos(gw_ctx ctx, gw_precision prec, int n_naf, int n_w,
+                                           const double* omega, int n_i, int n_virt,
+                                           const double* eps_i, const double* eps_a,
+                                           const void* R_chunk, int64_t ld_R, int accumulate,
+                                           int finalize, double* P) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_polarizability_sos: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
+             "gw_polarizability_sos: unknown precision %d", (int)prec);
+  GW_REQUIRE(ctx, n_naf >= 1 && n_w >= 1 && n_i >= 0 && n_virt >= 1,
+             "gw_polarizability_sos: bad sizes (n_naf=%d n_w=%d n_i=%d n_virt=%d)", n_naf, n_w,
+             n_i, n_virt);
+  GW_REQUIRE(ctx, omega && P && eps_a && (n_i == 0 || (eps_i && R_chunk)),
+             "gw_polarizability_sos: NULL argument");
+  if (ld_R == 0) ld_R = n_naf;
+  GW_REQUIRE(ctx, ld_R >= n_naf, "gw_polarizability_sos: ld_R < n_naf");
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  const int64_t k = (int64_t)n_i * n_virt;
+  const double* dom = gw::stage_t(ctx, omega, n_w);
+  const double* dei = n_i ? gw::stage_t(ctx, eps_i, n_i) : nullptr;
+  const double* dea = gw::stage_t(ctx, eps_a, n_virt);
+  if (!dom || !dea || (n_i && !dei)) return GW_EINVAL;
+  void* scale = nullptr;
+  if (k > 0) {
+    const size_t esz = prec == GW_FP64 ? 8 : 4;
+    scale = gw::ws_get(ctx, WS_SYRK_SCALE, (size_t)n_w * k * esz);
+    if (!scale) return GW_ENOMEM;
+    GW_TRY(gw::lt_scale_launch(ctx, prec, n_w, dom, dom, n_i, n_virt, dei, dea, scale, 1));
+  }
+  GW_TRY(gw::syrk_launch(ctx, prec, R_chunk, k, n_naf, ld_R, n_w, scale, 1.0, P, accumulate,
+                         prec == GW_FP64 ? "chi_sos_f64"
+                                         : (prec == GW_BF16X3 ? "chi_sos_bf16x3" : "chi_sos_f32")));
+  if (finalize) GW_TRY(gw::mirror_lower(ctx, P, n_w, n_naf));
   return GW_OK;
 }
 

@@ -38,7 +38,8 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_set_stream", "gw_sync", "gw_last_error
            "gw_graph_begin", "gw_graph_end", "gw_graph_launch", "gw_graph_destroy",
            "gw_polarizability_lt_batched", "gw_screen_batched", "gw_sigma_diag_batched",
            "gw_qp_solve_batched", "gw_g0w0_batched", "gw_reserve", "gw_naf_compress_batched",
-           "gw_naf_apply_batched", "gw_autotune"]
+           "gw_naf_apply_batched", "gw_autotune", "gw_evgw", "gw_polarizability_sos",
+           "gw_screen_sos", "gw_lt_grid_auto"]
 
 c_int, c_i64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_DBL = ctypes.POINTER(ctypes.c_double)
@@ -49,7 +50,7 @@ class GwParams(ctypes.Structure):
     _fields_ = [("n_occ", c_int), ("n_fc", c_int), ("n_virt", c_int), ("n_aux", c_int),
                 ("n_lt", c_int), ("n_freq", c_int), ("n_pade", c_int), ("n_qp", c_int),
                 ("eps_naf", c_dbl), ("max_keep", c_int), ("x0", c_dbl), ("eta", c_dbl),
-                ("tol", c_dbl), ("max_iter", c_int), ("freq_batch", c_int)]
+                ("tol", c_dbl), ("max_iter", c_int), ("freq_batch", c_int), ("no_lt", c_int)]
 
 
 class GwStats(ctypes.Structure):
@@ -143,6 +144,12 @@ _sig = {
     "gw_g0w0": [c_vp, c_int, ctypes.POINTER(GwParams), P_DBL, P_INT, P_DBL, c_vp, c_vp, c_vp,
                 P_DBL, P_DBL, P_INT, P_DBL, ctypes.POINTER(GwStats)],
     "gw_reserve": [c_vp, c_int, ctypes.POINTER(Dims)],
+    "gw_polarizability_sos": [c_vp, c_int, c_int, c_int, P_DBL, c_int, c_int, P_DBL, P_DBL,
+                              c_vp, c_i64, c_int, c_int, c_vp],
+    "gw_screen_sos": [c_vp, c_int, c_int, c_int, c_vp, c_vp],
+    "gw_lt_grid_auto": [c_dbl, c_int, c_dbl, c_dbl, P_INT, P_DBL, P_DBL, P_DBL],
+    "gw_evgw": [c_vp, c_int, ctypes.POINTER(GwParams), c_int, P_DBL, P_INT, P_DBL, c_vp, c_vp,
+                c_vp, P_DBL, P_DBL, P_INT, P_DBL, ctypes.POINTER(GwStats)],
     "gw_autotune": [c_vp, c_int, P_INT],
     "gw_naf_compress_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafJob)],
     "gw_naf_apply_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafApplyJob)],
@@ -282,6 +289,24 @@ def gw_lt_grid_minimax(n_lt: int, y_min: float, y_max: float):
     return x, w, err.value
 
 
+def gw_lt_grid_auto(eps_lt: float, y_min: float, y_max: float, max_lt: int = 20):
+    """Smallest Laplace grid meeting eps_lt: (n_lt, x, w, err)."""
+    n = ctypes.c_int(0)
+    x, w, err = np.empty(max_lt), np.empty(max_lt), c_dbl()
+    _check(_lib.gw_lt_grid_auto(float(eps_lt), int(max_lt), float(y_min), float(y_max),
+                                ctypes.byref(n), _dp(x), _dp(w), ctypes.byref(err)))
+    return n.value, x[:n.value].copy(), w[:n.value].copy(), err.value
+
+
+def lt_points_for(eps, cfg, eps_lt: float):
+    """The accuracy-driven Laplace grid for a workload's energies (its bounds
+    as gw_g0w0 takes them): {"L": n_lt, "err_norm": ...}."""
+    om, _ = gw_freq_grid_mgl(cfg.n_freq, cfg.x0)
+    _, y_min, y_max = gw_prepare(cfg.n_occ, cfg.n_fc, cfg.n_virt, eps, om[0])
+    n, _, _, err = gw_lt_grid_auto(eps_lt, y_min, y_max)
+    return {"L": n, "err_norm": err, "y_min": y_min, "y_max": y_max}
+
+
 def gw_minimax_inverse(n_lt: int, R: float, alpha0=None, omega0=None):
     a0 = None if alpha0 is None else _host(alpha0)
     o0 = None if omega0 is None else _host(omega0)
@@ -319,6 +344,21 @@ def gw_polarizability_lt(ctx, prec, n_naf, x_lt, w_lt, n_i, n_virt, eps_i, eps_a
                                      n_i, n_virt, _dp(ei), _dp(ea), _dev(R_chunk, True),
                                      _ld(R_chunk, n_naf), int(accumulate), int(finalize),
                                      _dev(M)), ctx)
+
+
+def gw_polarizability_sos(ctx, prec, n_naf, omega, n_i, n_virt, eps_i, eps_a, R_chunk,
+                          accumulate, finalize, P):
+    om = _host(omega)
+    ei, ea = _host(eps_i), _host(eps_a)
+    _check(_lib.gw_polarizability_sos(ctx.handle, _prec(prec), n_naf, len(om), _dp(om), n_i,
+                                      n_virt, _dp(ei), _dp(ea), _dev(R_chunk, True),
+                                      _ld(R_chunk, n_naf), int(accumulate), int(finalize),
+                                      _dev(P)), ctx)
+
+
+def gw_screen_sos(ctx, prec, n_naf, P, W_hat):
+    _check(_lib.gw_screen_sos(ctx.handle, _prec(prec), n_naf, P.shape[0], _dev(P),
+                              _dev(W_hat)), ctx)
 
 
 def gw_screen(ctx, prec, n_naf, x_lt, M, omega, W_hat):
@@ -365,12 +405,31 @@ def gw_g0w0(ctx, prec, params: GwParams, eps, qp, static_n, R_oo, R_ov, R_qp,
     return E, Z, S, sigma, stats
 
 
-def params_for(cfg, freq_batch: int = 0, tol: float = 1e-6, max_iter: int = 100) -> GwParams:
+def gw_evgw(ctx, prec, params: GwParams, n_cycles, eps, qp, static_n, R_oo, R_ov, R_qp):
+    """Returns (eps_qp [n_cycles][n_qp], z [n_qp] of the last cycle, status
+    [n_cycles][n_qp], energies of the next cycle, stats)."""
+    e = _host(eps)
+    q = _host(qp, np.int32)
+    st = None if static_n is None else _host(static_n)
+    n = params.n_qp
+    E = np.empty((n_cycles, n))
+    Z = np.empty(n)
+    S = np.empty((n_cycles, n), dtype=np.int32)
+    last = np.empty(len(e))
+    stats = GwStats()
+    _check(_lib.gw_evgw(ctx.handle, _prec(prec), ctypes.byref(params), int(n_cycles), _dp(e),
+                        _ip(q), _dp(st), _dev(R_oo), _dev(R_ov), _dev(R_qp), _dp(E), _dp(Z),
+                        _ip(S), _dp(last), ctypes.byref(stats)), ctx)
+    return E, Z, S, last, stats
+
+
+def params_for(cfg, freq_batch: int = 0, tol: float = 1e-6, max_iter: int = 100,
+               no_lt: bool = False) -> GwParams:
     """gw_params from a workload description with the fields of gwsynth.Config."""
     return GwParams(n_occ=cfg.n_occ, n_fc=cfg.n_fc, n_virt=cfg.n_virt, n_aux=cfg.n_aux,
                     n_lt=cfg.n_lt, n_freq=cfg.n_freq, n_pade=cfg.n_pade, n_qp=cfg.n_qp,
                     eps_naf=cfg.eps_naf, max_keep=cfg.max_keep, x0=cfg.x0, eta=cfg.eta,
-                    tol=tol, max_iter=max_iter, freq_batch=freq_batch)
+                    tol=tol, max_iter=max_iter, freq_batch=freq_batch, no_lt=int(no_lt))
 
 
 # ------------------------------------------------------------------ graphs

@@ -56,6 +56,42 @@ def test_minimax_grid_equioscillates_large_k(k):
     assert np.max(np.abs(vals)) - np.min(np.abs(vals)) < 1e-8 * e
 
 
+def test_minimax_grid_matches_oracle_beyond_16_points():
+    # k = 17 at R = 1e6: the level sits near 2e-7, where rounding in the error
+    # curve (about 1e-15 near t = 1) limits how sharply equioscillation shows
+    al, om, e = gwlt.gw_minimax_inverse(17, 1e6)
+    ao, oo, eo = grids.minimax_inverse(17, 1e6)
+    assert np.allclose(al, ao, rtol=1e-7)
+    assert np.allclose(om, oo, rtol=1e-7)
+    assert abs(e - abs(eo)) < 1e-7 * e
+
+
+@pytest.mark.parametrize("k,R", [(18, 1e6), (20, 1e8)])
+def test_minimax_grid_equioscillates_beyond_16_points(k, R):
+    al, om, e = gwlt.gw_minimax_inverse(k, R)
+    pts, vals = grids._extrema(R, al, om, k, n_grid=40000)
+    assert pts.size == 2 * k + 1
+    assert np.all(np.sign(vals[1:]) == -np.sign(vals[:-1]))
+    assert np.max(np.abs(vals)) - np.min(np.abs(vals)) < 1e-14 + 1e-8 * e
+
+
+@pytest.mark.parametrize("eps_lt", [1e-4, 1e-6, 1e-7])
+def test_lt_grid_auto_takes_the_smallest_grid(eps_lt):
+    lo, hi = 0.0904, 1.2e4
+    n, x, w, e = gwlt.gw_lt_grid_auto(eps_lt, lo, hi)
+    assert e <= eps_lt
+    x2, w2, e2 = gwlt.gw_lt_grid_minimax(n, lo, hi)
+    assert np.array_equal(x, x2) and np.array_equal(w, w2) and e == e2
+    if n > 1:
+        assert gwlt.gw_lt_grid_minimax(n - 1, lo, hi)[2] > eps_lt
+
+
+def test_lt_grid_auto_reports_an_unreachable_target():
+    with pytest.raises(gwlt.GwError) as ei:
+        gwlt.gw_lt_grid_auto(1e-9, 0.0904, 1.2e4, max_lt=6)
+    assert ei.value.status == gwlt.GW_ENOCONV
+
+
 def test_prepare_matches_oracle(tiny_problem):
     p = tiny_problem
     c = p.cfg
@@ -70,7 +106,7 @@ def test_argument_errors_are_status_codes():
         gwlt.gw_freq_grid_mgl(0, 0.5)
     assert ei.value.status == gwlt.GW_EINVAL
     with pytest.raises(gwlt.GwError) as ei:
-        gwlt.gw_lt_grid_minimax(17, 1.0, 10.0)
+        gwlt.gw_lt_grid_minimax(21, 1.0, 10.0)
     assert ei.value.status == gwlt.GW_EINVAL
     with pytest.raises(gwlt.GwError):
         gwlt.gw_prepare(3, 3, 5, np.zeros(8), 0.0)        # n_fc == n_occ

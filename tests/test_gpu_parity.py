@@ -136,6 +136,42 @@ def test_polarizability_rejects_bad_arguments(gw, ctx):
     assert ei.value.status == gw.GW_EINVAL
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("shape", [(8, 40, 150), (3, 7, 129)])
+def test_polarizability_sos_matches_oracle(gw, ctx, prec, tol, shape):
+    """The baseline without the Laplace transform: P_j = sum_ia R D/(w^2+D^2) R^T
+    per frequency, against the oracle's Eq. 3 (Pi_j = -2 s P_j)."""
+    o, v, N = shape
+    _say(f"polarizability sos {prec} o={o} v={v} N={N}")
+    eps_i, eps_a, R, _, _ = _lt_case(12, o, v, N, 4)
+    d = (eps_a[None, :] - eps_i[:, None]).ravel()
+    om, _ = grids.modified_gauss_legendre(7, 0.5)
+    ref = -rpa.pi_sos(R, d, om) / 4.0
+    P = torch.zeros((len(om), N, N), dtype=torch.float64, device="cuda")
+    gw.gw_polarizability_sos(ctx, prec, N, om, o, v, eps_i, eps_a, dev(R, prec), 0, 1, P)
+    gw.gw_sync(ctx)
+    Ph = P.cpu().numpy()
+    for j in range(len(om)):
+        assert rel_fro(Ph[j], ref[j]) < tol, (j, rel_fro(Ph[j], ref[j]))
+        assert np.array_equal(Ph[j], Ph[j].T)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-7)])
+def test_screen_sos_matches_oracle(gw, ctx, prec, tol):
+    N, F = 333, 3
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((N + 40, N)) / np.sqrt(N)
+    P = np.stack([X.T @ (np.diag(rng.uniform(0.1, 1.0, N + 40)) @ X) for _ in range(F)])
+    ref = rpa.screen(-4.0 * P)
+    W = torch.zeros((F, N, N), dtype=torch.float64 if prec == "fp64" else torch.float32,
+                    device="cuda")
+    gw.gw_screen_sos(ctx, prec, N, dev(P, "fp64"), W)
+    gw.gw_sync(ctx)
+    Wh = W.double().cpu().numpy()
+    for j in range(F):
+        assert rel_fro(Wh[j], ref[j]) < tol
+
+
 # ------------------------------------------------------------------ a5 + a6
 
 def _spd_m(seed, L, N):
@@ -165,6 +201,25 @@ def test_screen_matches_oracle(gw, ctx, prec, tol, N, F):
     for j in range(F):
         assert rel_fro(Wh[j], ref[j]) < tol, (j, rel_fro(Wh[j], ref[j]))
         assert np.array_equal(Wh[j], Wh[j].T)
+
+
+def test_static_screening_for_bse(gw, ctx, tiny_problem, tiny_lt_grid):
+    """W_hat at omega = 0 (the static screening a BSE step takes) from the
+    Laplace matrices of the tiny molecule, against the oracle; at omega = 0
+    every Laplace point enters with weight 1, so Pi(0) = -2s sum_m M^m."""
+    p = tiny_problem
+    c = p.cfg
+    x, w, _, _, _ = tiny_lt_grid
+    d = rpa.delta_ov(p.eps, c.n_fc, c.n_occ)
+    M = rpa.m_lt(p.R_ov, d, x, w)
+    ref = rpa.screen(rpa.pi_lt(M, x, np.array([0.0])))[0]
+    assert np.allclose(rpa.pi_lt(M, x, np.array([0.0]))[0], -4.0 * M.sum(axis=0))
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-7)):
+        W = torch.zeros((1, c.n_aux, c.n_aux),
+                        dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
+        gw.gw_screen(ctx, prec, c.n_aux, x, dev(M, "fp64"), np.array([0.0]), W)
+        gw.gw_sync(ctx)
+        assert rel_fro(W[0].double().cpu().numpy(), ref) < tol
 
 
 def test_screen_reports_non_spd(gw, ctx):
@@ -421,6 +476,58 @@ def test_g0w0_tiny(gw, ctx, tiny_problem, tiny_sos, prec, tol_mev):
     assert np.all(err_prec < tol_mev)
     stol = 1e-5 if prec != "bf16x3" else 1e-3
     assert np.max(np.abs(sig - lt.sigma)) < stol * np.max(np.abs(lt.sigma))
+
+
+@pytest.mark.parametrize("prec,tol_mev", [("fp64", 1e-4), ("fp32", 0.1), ("bf16x3", 1.0)])
+def test_evgw_tiny(gw, ctx, tiny_problem, prec, tol_mev):
+    """Eigenvalue-self-consistent GW, five cycles (Sec. 3, Table 3): every
+    cycle's QP energies against the oracle's evGW with its own Laplace grid
+    on each cycle's bounds; cycle 0 is the G0W0 result."""
+    from oracle.evgw import evgw_problem
+    p = tiny_problem
+    c = p.cfg
+    _say(f"evgw tiny {prec}")
+    ref = evgw_problem(p, n_cycles=5, lt_points=c.n_lt, tol=1e-10, max_iter=200)
+    params = gw.params_for(c, tol=1e-10, max_iter=200)
+    E, Z, S, last, st = gw.gw_evgw(ctx, prec, params, 5, p.eps, p.qp, None, dev(p.R_oo, prec),
+                                   dev(p.R_ov, prec), dev(p.R_qp, prec))
+    assert np.all(S == 0) and st.n_naf == c.n_aux
+    err = np.abs(E - ref.eps_qp) * HARTREE_MEV
+    _say(f"  per-cycle max error {err.max(axis=1)} meV; shift over the cycles "
+         f"{(ref.eps_qp[-1] - ref.eps_qp[0]) * HARTREE_MEV} meV")
+    assert np.all(err < tol_mev)
+    assert np.allclose(last, ref.eps[-1], atol=tol_mev / HARTREE_MEV)
+    E0, _, _, _, _ = gw.gw_g0w0(ctx, prec, params, p.eps, p.qp, None, dev(p.R_oo, prec),
+                                dev(p.R_ov, prec), dev(p.R_qp, prec))
+    assert np.allclose(E[0], E0, atol=1e-12)
+
+
+def test_evgw_rejects_bad_arguments(gw, ctx, tiny_problem):
+    p = tiny_problem
+    params = gw.params_for(p.cfg)
+    with pytest.raises(gw.GwError) as ei:
+        gw.gw_evgw(ctx, "fp64", params, 0, p.eps, p.qp, None, dev(p.R_oo, "fp64"),
+                   dev(p.R_ov, "fp64"), dev(p.R_qp, "fp64"))
+    assert ei.value.status == gw.GW_EINVAL
+
+
+@pytest.mark.parametrize("prec,tol_mev", [("fp64", 1e-4), ("fp32", 0.1), ("bf16x3", 1.0)])
+def test_g0w0_tiny_without_laplace(gw, ctx, tiny_problem, tiny_sos, prec, tol_mev):
+    """The whole step with the sum-over-states polarizability at every
+    frequency (no Laplace transform): the GPU path against the oracle's
+    sum-over-states chain, which carries no Laplace error at all."""
+    p = tiny_problem
+    c = p.cfg
+    _say(f"g0w0 tiny without Laplace {prec}")
+    params = gw.params_for(c, tol=1e-10, max_iter=200, no_lt=True)
+    E, Z, S, sig, st = gw.gw_g0w0(ctx, prec, params, p.eps, p.qp, None, dev(p.R_oo, prec),
+                                  dev(p.R_ov, prec), dev(p.R_qp, prec))
+    assert np.all(S == 0)
+    err = np.abs(E - tiny_sos.eps_qp) * HARTREE_MEV
+    _say(f"  error vs the sum-over-states oracle {err} meV")
+    assert np.all(err < tol_mev)
+    stol = 1e-5 if prec != "bf16x3" else 1e-3
+    assert np.max(np.abs(sig - tiny_sos.sigma)) < stol * np.max(np.abs(tiny_sos.sigma))
 
 
 def _golden(name):
