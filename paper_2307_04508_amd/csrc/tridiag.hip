@@ -41,9 +41,16 @@ struct TriJob {
   double* tau;        // [n - 1]
   double* pbuf;       // [2][n] exchange buffers (by step parity)
   double* colbuf;     // [2][n]
-  unsigned* count;    // barrier counter, zero on entry
+  unsigned* count;    // barrier: top counter, then group counters kCtrStride apart; zero on entry
   int n, G, wg0;      // order, workgroups, first workgroup of the job in the grid
 };
+
+// The barrier is two-level: workgroups arrive on the counter of their group
+// of kBarGroup, and the last arrival of a group arrives on the top counter,
+// which everyone polls.  One counter under all ~230 arrivals serialises
+// them (3.4 us per barrier at 231 workgroups, 1.8 us with groups of 32).
+constexpr int kBarGroup = 32;
+constexpr int kCtrStride = 32;    // unsigneds: one 128-byte line per counter
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -59,23 +66,32 @@ __device__ __forceinline__ void st_dev(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Barrier across the G workgroups of one job (the counter only grows, so
-// pass number q waits for q * G arrivals).  Every wave first waits for its
-// own memory operations to complete; only then does thread 0 arrive.  All
-// data that crosses workgroups inside the kernel (pbuf, colbuf) is written
-// and read with device-scope atomic accesses, which are performed at the
-// device's coherence point, so completed stores are visible to the loads
-// that follow the barrier without a release / acquire pair: those would
-// add an L2 write-back and an L2 invalidate per step (~2 us of a ~17 us
-// step at order 3000) for plain data that no other workgroup reads before
-// the kernel ends.  Returns false after spin_limit polls or when another
-// workgroup raised the error flag.
-__device__ bool group_barrier(unsigned* count, unsigned target, int* err, int spin_limit,
-                              int* s_ok) {
+// Barrier across the G workgroups of one job (the counters only grow, so
+// pass number q waits for q arrivals of each group on the top counter).
+// Every wave first waits for its own memory operations to complete; only
+// then does thread 0 arrive.  All data that crosses workgroups inside the
+// kernel (pbuf, colbuf) is written and read with device-scope atomic
+// accesses, which are performed at the device's coherence point, so
+// completed stores are visible to the loads that follow the barrier without
+// a release / acquire pair: those would add an L2 write-back and an L2
+// invalidate per step (~2 us of a ~17 us step at order 3000) for plain data
+// that no other workgroup reads before the kernel ends.  The group's last
+// arrival sees the group count in the value its own increment returns, and
+// only then increments the top counter, so every arrival of the group has
+// been performed before the top counter moves.  Returns false after
+// spin_limit polls or when another workgroup raised the error flag.
+__device__ bool group_barrier(unsigned* count, int g, int G, unsigned pass, int* err,
+                              int spin_limit, int* s_ok) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int gi = g / kBarGroup, n_grp = (G + kBarGroup - 1) / kBarGroup;
+    const unsigned gsize = (unsigned)min(kBarGroup, G - gi * kBarGroup);
+    const unsigned prev = __hip_atomic_fetch_add(count + (1 + gi) * kCtrStride, 1u,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev + 1 == pass * gsize)
+      __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = pass * (unsigned)n_grp;
     int ok = 1;
     for (int it = 0;; ++it) {
       if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
@@ -139,7 +155,7 @@ __global__ __launch_bounds__(TNT, 1) void tridiag_kernel(const TriJob* __restric
   for (int c = 0; c < C; ++c) vp[c] = w[c] = vn[c] = 0.0;
   double tau_prev = 0.0;
   // every workgroup has read K before any reflector is written into it
-  if (!group_barrier(J.count, (unsigned)G, err, spin_limit, &s_ok)) return;
+  if (!group_barrier(J.count, g, G, 1u, err, spin_limit, &s_ok)) return;
 
   for (int k = 0; k + 1 < n; ++k) {
     const int pc = k & 1, pp = pc ^ 1;
@@ -245,7 +261,7 @@ __global__ __launch_bounds__(TNT, 1) void tridiag_kernel(const TriJob* __restric
 #pragma unroll
     for (int c = 0; c < C; ++c) vp[c] = vn[c];
     tau_prev = t;
-    if (!group_barrier(J.count, (unsigned)(k + 2) * G, err, spin_limit, &s_ok)) return;
+    if (!group_barrier(J.count, g, G, (unsigned)(k + 2), err, spin_limit, &s_ok)) return;
   }
   // last diagonal entry: column n-1 of A^(n-2)
   if (g == 0 && tid == 0) {
@@ -299,9 +315,14 @@ gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in) {
   if (n_jobs == 0) return GW_OK;
   int n_cu = 0;
   GW_HIP(ctx, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
-  // scratch: per job 4 n doubles of exchange buffers + one counter slot
+  // scratch: per job 4 n doubles of exchange buffers + the barrier counters
+  // (top + one per group of kBarGroup workgroups, a 128-byte line each)
+  auto workgroups = [&](int n) { return std::min(n_cu, (n + TR - 1) / TR); };
+  auto ctr_doubles = [&](int n) {
+    return (size_t)(1 + (workgroups(n) + kBarGroup - 1) / kBarGroup) * kCtrStride / 2;
+  };
   size_t sc = 0;
-  for (const TriIn& j : in) sc += 4 * (size_t)j.n + 1;
+  for (const TriIn& j : in) sc += 4 * (size_t)std::max(j.n, 1) + ctr_doubles(j.n);
   double* ws = static_cast<double*>(ws_get(ctx, WS_TRI, sc * sizeof(double)));
   if (!ws) return GW_ENOMEM;
   GW_TRY(fill_zero(ctx, ws, (int64_t)sc));
@@ -321,10 +342,10 @@ gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in) {
     t.colbuf = ws + o + 2 * (size_t)j.n;
     t.count = reinterpret_cast<unsigned*>(ws + o + 4 * (size_t)j.n);
     t.n = j.n;
-    t.G = std::min(n_cu, (j.n + TR - 1) / TR);
+    t.G = workgroups(j.n);
     t.wg0 = 0;
     all[d] = t;
-    o += 4 * (size_t)j.n + 1;
+    o += 4 * (size_t)j.n + ctr_doubles(j.n);
   }
   std::vector<int> order(n_jobs);
   for (int d = 0; d < n_jobs; ++d) order[d] = d;
