@@ -361,14 +361,23 @@ __global__ __launch_bounds__(NT8, 4) void nt_gemm_f32_direct_kernel(GemmDArgs g0
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
     if (it + 1 < nk) issue((it + 1) * BKD, cur ^ 1);
+    // operands of step kk + 1 read during the MFMAs of step kk (see the
+    // chi SYRK for the scheduling hint)
+    float na = As[cur][ksub][arow], ns = Ss[cur][ksub];
+    float nb0 = Bs[cur][ksub][bcol], nb1 = Bs[cur][ksub][bcol + 32];
 #pragma unroll
     for (int kk = 0; kk < BKD / 2; ++kk) {
-      const int kr = 2 * kk + ksub;
-      const float av = As[cur][kr][arow] * Ss[cur][kr];
-      const float b0 = Bs[cur][kr][bcol];
-      const float b1 = Bs[cur][kr][bcol + 32];
+      const float av = na * ns, b0 = nb0, b1 = nb1;
+      if (kk + 1 < BKD / 2) {
+        const int kr = 2 * (kk + 1) + ksub;
+        na = As[cur][kr][arow];
+        ns = Ss[cur][kr];
+        nb0 = Bs[cur][kr][bcol];
+        nb1 = Bs[cur][kr][bcol + 32];
+      }
       acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0, acc[0], 0, 0, 0);
       acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1, acc[1], 0, 0, 0);
+      __builtin_amdgcn_iglp_opt(0);
     }
     if ((it + 1) % FLUSH_STAGES == 0 || it + 1 == nk) {
 #pragma unroll
