@@ -52,9 +52,23 @@ struct TriJob {
 constexpr int kBarGroup = 32;
 constexpr int kCtrStride = 32;    // unsigneds: one 128-byte line per counter
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Sum over the 64 lanes of a wave, complete in lane 63 only (other lanes
+// hold partial sums).  DPP moves within rows of 16 lanes, then the row
+// broadcasts of lanes 15 and 31: VALU only, no LDS round trip per step.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kLastLane = 63;
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_move<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]: quad sums
+  v += dpp_move<0x141, 0xF>(v);    // row_half_mirror: sums of 8
+  v += dpp_move<0x140, 0xF>(v);    // row_mirror: row sums of 16
+  v += dpp_move<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -171,8 +185,8 @@ __global__ __launch_bounds__(TNT, 1) void tridiag_kernel(const TriJob* __restric
       cv[c] = on ? ld_dev(&J.colbuf[pc * n + j]) : 0.0;
       sp += pv[c] * vp[c];
     }
-    sp = wave_sum(sp);
-    if (lane == 0) red[wave][TR] = sp;
+    sp = wave_total(sp);
+    if (lane == kLastLane) red[wave][TR] = sp;
     __syncthreads();
     double s = 0.0;
 #pragma unroll
@@ -191,8 +205,8 @@ __global__ __launch_bounds__(TNT, 1) void tridiag_kernel(const TriJob* __restric
       if (j == k) bc[0] = cv[c];
       if (j == k + 1) bc[1] = cv[c];
     }
-    xp = wave_sum(xp);
-    if (lane == 0) red[wave][TR + 1] = xp;
+    xp = wave_total(xp);
+    if (lane == kLastLane) red[wave][TR + 1] = xp;
     __syncthreads();
     double xn2 = 0.0;
 #pragma unroll
@@ -243,8 +257,8 @@ __global__ __launch_bounds__(TNT, 1) void tridiag_kernel(const TriJob* __restric
           acc += x * vn[c];
           if (c == cnext) cn = x;
         }
-        acc = wave_sum(acc);
-        if (lane == 0) red[wave][r] = acc;
+        acc = wave_total(acc);
+        if (lane == kLastLane) red[wave][r] = acc;
         if (tid == tnext && i >= k + 1) st_dev(&J.colbuf[pp * n + i], cn);
       }
     }
