@@ -72,12 +72,16 @@ __device__ __forceinline__ double wave_total(double v) {
   return v;
 }
 
-// Exchange-buffer accesses are device-coherent (other workgroups, other XCDs).
+// Exchange-buffer accesses are device-coherent (other workgroups, other
+// XCDs), issued as global (not flat) memory operations.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) unsigned guint;
+typedef __attribute__((address_space(1))) int gint;
 __device__ __forceinline__ double ld_dev(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const gdouble*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_dev(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gdouble*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Barrier across the G workgroups of one job (the counters only grow, so
@@ -94,8 +98,10 @@ __device__ __forceinline__ void st_dev(double* p, double v) {
 // only then increments the top counter, so every arrival of the group has
 // been performed before the top counter moves.  Returns false after
 // spin_limit polls or when another workgroup raised the error flag.
-__device__ bool group_barrier(unsigned* count, int g, int G, unsigned pass, int* err,
+__device__ bool group_barrier(unsigned* count_ptr, int g, int G, unsigned pass, int* err_ptr,
                               int spin_limit, int* s_ok) {
+  guint* count = (guint*)count_ptr;
+  gint* err = (gint*)err_ptr;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
