@@ -243,14 +243,18 @@ __global__ __launch_bounds__(TNT, 1) void tridiag_kernel(const TriJob* __restric
     }
     // ---- rank-2 update of step k-1 fused with p = tau A^(k-1) v_k
     const int tnext = (k + 1) % TNT, cnext = (k + 1) / TNT;
+    // Rows i <= k and column slots wholly left of column k + 1 are finished:
+    // nothing later reads them, so they are skipped (both tests are uniform
+    // across the workgroup); the work per step shrinks with (n - k)^2.
 #pragma unroll
     for (int r = 0; r < TR; ++r) {
-      if (r < R) {
+      if (r < R && g + G * r > k) {
         const int i = g + G * r;
         const double vpi = vsh[pp][i], wi = wsh[i];
         double acc = 0.0, cn = 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
+          if (TNT * (c + 1) <= k + 1) continue;
           double x;
           if (c < CR) {
             x = a[r][c < CR ? c : 0] - (vpi * w[c] + wi * vp[c]);
