@@ -288,12 +288,18 @@ typedef struct {
                                        states at every frequency (Eq. 3,
                                        the AC baseline without the Laplace
                                        transform); 0: Laplace form        */
+  double eps_lt;                    /* > 0: accuracy-driven Laplace grid,
+                                       the smallest one whose normalised
+                                       minimax level is <= eps_lt (Sec. 3),
+                                       with n_lt as its upper bound (0 or
+                                       past 20: 20); 0: n_lt points      */
 } gw_params;
 
 typedef struct {
   int n_naf;                        /* kept natural auxiliary functions   */
   double lt_err_norm;               /* minimax level of the Laplace grid  */
   double t_naf_ms, t_chi_ms, t_screen_ms, t_sigma_ms, t_qp_ms, t_total_ms;
+  int n_lt;                         /* Laplace points taken (last cycle)  */
 } gw_stats;
 
 /* One LT-AC G0W0 evaluation (a1-a9 in order): NAF compression of the raw

@@ -113,13 +113,36 @@ gw_status check_args(gw_ctx ctx, const char* who, const gw_params* P, const doub
   GW_REQUIRE(ctx, P && eps && qp && R_oo && R_ov && R_qp && out && status,
              "%s: NULL argument", who);
   const int o = P->n_occ - P->n_fc;
-  GW_REQUIRE(ctx, o >= 1 && P->n_virt >= 1 && P->n_aux >= 1 && P->n_qp >= 1 && P->n_lt >= 1 &&
-                      P->n_freq >= 1 && P->n_pade >= 1,
+  GW_REQUIRE(ctx, o >= 1 && P->n_virt >= 1 && P->n_aux >= 1 && P->n_qp >= 1 &&
+                      (P->n_lt >= 1 || P->eps_lt > 0) && P->n_freq >= 1 && P->n_pade >= 1,
              "%s: bad sizes", who);
+  GW_REQUIRE(ctx, P->eps_lt >= 0, "%s: eps_lt = %g < 0", who, P->eps_lt);
   for (int q = 0; q < P->n_qp; ++q)
     GW_REQUIRE(ctx, qp[q] >= P->n_fc && qp[q] < P->n_occ + P->n_virt,
                "%s: QP state %d (orbital %d) is not active", who, q, qp[q]);
   return GW_OK;
+}
+
+// a3, Laplace grid on [ymin, ymax]: n_lt points, or with eps_lt > 0 the
+// smallest grid meeting it (n_lt, at most 20, as the bound); P->n_lt of the
+// copy Pg becomes the size taken.
+gw_status laplace_grid(const gw_params* P, double ymin, double ymax, gw_params* Pg,
+                       std::vector<double>& xl, std::vector<double>& wl, double* err) {
+  *Pg = *P;
+  if (P->eps_lt > 0) {
+    const int max_lt = P->n_lt >= 1 && P->n_lt <= 20 ? P->n_lt : 20;
+    xl.assign(max_lt, 0.0);
+    wl.assign(max_lt, 0.0);
+    int n = 0;
+    GW_TRY(gw_lt_grid_auto(P->eps_lt, max_lt, ymin, ymax, &n, xl.data(), wl.data(), err));
+    xl.resize(n);
+    wl.resize(n);
+    Pg->n_lt = n;
+    return GW_OK;
+  }
+  xl.assign(P->n_lt, 0.0);
+  wl.assign(P->n_lt, 0.0);
+  return gw_lt_grid_minimax(P->n_lt, ymin, ymax, xl.data(), wl.data(), err);
 }
 
 // a2: NAF compression and transformation of the ov and QP rows.
@@ -170,12 +193,13 @@ extern "C" gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* P,
   if (st != GW_OK) return gw::fail(ctx, st, "gw_g0w0: %s", gw_last_error(nullptr));
 
   // a3 (Laplace grid): host work, overlapped with the NAF stage on the device
-  std::vector<double> xl(P->n_lt), wl(P->n_lt);
+  std::vector<double> xl, wl;
   double lt_err = 0;
   std::string lt_msg;
+  gw_params Pg = *P;
   auto lt_job = std::async(std::launch::async, [&]() {
     if (P->no_lt) return GW_OK;
-    gw_status s = gw_lt_grid_minimax(P->n_lt, ymin, ymax, xl.data(), wl.data(), &lt_err);
+    gw_status s = laplace_grid(P, ymin, ymax, &Pg, xl, wl, &lt_err);
     if (s != GW_OK) lt_msg = gw_last_error(nullptr);
     return s;
   });
@@ -192,10 +216,11 @@ extern "C" gw_status gw_g0w0(gw_ctx ctx, gw_precision prec, const gw_params* P,
   if (st != GW_OK) return gw::fail(ctx, st, "gw_g0w0: %s", lt_msg.c_str());
 
   double t[4] = {0, 0, 0, 0};
-  GW_TRY(post_naf(ctx, prec, P, eps, qp, static_n, xl, wl, om, wom, omp, eF, N, ldN, Rt_ov,
+  GW_TRY(post_naf(ctx, prec, &Pg, eps, qp, static_n, xl, wl, om, wom, omp, eF, N, ldN, Rt_ov,
                   Rt_qp, eps_qp, z_factor, status, sigma_iw, ev, t));
   if (stats) {
     stats->n_naf = N;
+    stats->n_lt = P->no_lt ? 0 : Pg.n_lt;
     stats->lt_err_norm = lt_err;
     stats->t_naf_ms = ev.ms(0, 1);
     stats->t_chi_ms = t[0];
@@ -246,20 +271,22 @@ extern "C" gw_status gw_evgw(gw_ctx ctx, gw_precision prec, const gw_params* P, 
     if (qp[q] < qp[lo]) lo = q;
     if (qp[q] > qp[hi]) hi = q;
   }
-  std::vector<double> cur(eps, eps + n_orb), stat(Q), xl(P->n_lt), wl(P->n_lt);
+  std::vector<double> cur(eps, eps + n_orb), stat(Q), xl, wl;
   double t[4] = {0, 0, 0, 0}, lt_err = 0;
+  int n_lt_last = 0;
   for (int c = 0; c < n_cycles; ++c) {
     double eF = 0, ymin = 0, ymax = 0;
+    gw_params Pg = *P;
     st = gw_prepare(P->n_occ, P->n_fc, P->n_virt, cur.data(), om[0], &eF, &ymin, &ymax);
-    if (st == GW_OK && !P->no_lt)
-      st = gw_lt_grid_minimax(P->n_lt, ymin, ymax, xl.data(), wl.data(), &lt_err);
+    if (st == GW_OK && !P->no_lt) st = laplace_grid(P, ymin, ymax, &Pg, xl, wl, &lt_err);
     if (st != GW_OK) return gw::fail(ctx, st, "gw_evgw: cycle %d: %s", c, gw_last_error(nullptr));
+    n_lt_last = P->no_lt ? 0 : Pg.n_lt;
     // QP equation based on the starting energies: E = eps0 + c + Re Sigma[cur](E)
     for (int q = 0; q < Q; ++q)
       stat[q] = eps[qp[q]] + (static_n ? static_n[q] : 0.0) - cur[qp[q]];
     double* E = eps_qp + (size_t)c * Q;
     int* S = status + (size_t)c * Q;
-    GW_TRY(post_naf(ctx, prec, P, cur.data(), qp, stat.data(), xl, wl, om, wom, omp, eF, N, ldN,
+    GW_TRY(post_naf(ctx, prec, &Pg, cur.data(), qp, stat.data(), xl, wl, om, wom, omp, eF, N, ldN,
                     Rt_ov, Rt_qp, E, c + 1 == n_cycles ? z_factor : nullptr, S, nullptr, ev, t));
     // energies of the next cycle (Sec. 3): QP states take their QP energies;
     // other active occupied orbitals the shift of the lowest QP state, other
@@ -272,6 +299,7 @@ extern "C" gw_status gw_evgw(gw_ctx ctx, gw_precision prec, const gw_params* P, 
   if (eps_last) std::copy(cur.begin(), cur.end(), eps_last);
   if (stats) {
     stats->n_naf = N;
+    stats->n_lt = n_lt_last;
     stats->lt_err_norm = lt_err;
     stats->t_naf_ms = t_naf;
     stats->t_chi_ms = t[0];

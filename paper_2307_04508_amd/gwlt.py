@@ -50,13 +50,14 @@ class GwParams(ctypes.Structure):
     _fields_ = [("n_occ", c_int), ("n_fc", c_int), ("n_virt", c_int), ("n_aux", c_int),
                 ("n_lt", c_int), ("n_freq", c_int), ("n_pade", c_int), ("n_qp", c_int),
                 ("eps_naf", c_dbl), ("max_keep", c_int), ("x0", c_dbl), ("eta", c_dbl),
-                ("tol", c_dbl), ("max_iter", c_int), ("freq_batch", c_int), ("no_lt", c_int)]
+                ("tol", c_dbl), ("max_iter", c_int), ("freq_batch", c_int), ("no_lt", c_int),
+                ("eps_lt", c_dbl)]
 
 
 class GwStats(ctypes.Structure):
     _fields_ = [("n_naf", c_int), ("lt_err_norm", c_dbl), ("t_naf_ms", c_dbl),
                 ("t_chi_ms", c_dbl), ("t_screen_ms", c_dbl), ("t_sigma_ms", c_dbl),
-                ("t_qp_ms", c_dbl), ("t_total_ms", c_dbl)]
+                ("t_qp_ms", c_dbl), ("t_total_ms", c_dbl), ("n_lt", c_int)]
 
 
 class ChiJob(ctypes.Structure):
@@ -424,12 +425,14 @@ def gw_evgw(ctx, prec, params: GwParams, n_cycles, eps, qp, static_n, R_oo, R_ov
 
 
 def params_for(cfg, freq_batch: int = 0, tol: float = 1e-6, max_iter: int = 100,
-               no_lt: bool = False) -> GwParams:
-    """gw_params from a workload description with the fields of gwsynth.Config."""
+               no_lt: bool = False, eps_lt: float = 0.0) -> GwParams:
+    """gw_params from a workload description with the fields of gwsynth.Config;
+    eps_lt > 0 asks for the accuracy-driven Laplace grid (n_lt its upper bound)."""
     return GwParams(n_occ=cfg.n_occ, n_fc=cfg.n_fc, n_virt=cfg.n_virt, n_aux=cfg.n_aux,
                     n_lt=cfg.n_lt, n_freq=cfg.n_freq, n_pade=cfg.n_pade, n_qp=cfg.n_qp,
                     eps_naf=cfg.eps_naf, max_keep=cfg.max_keep, x0=cfg.x0, eta=cfg.eta,
-                    tol=tol, max_iter=max_iter, freq_batch=freq_batch, no_lt=int(no_lt))
+                    tol=tol, max_iter=max_iter, freq_batch=freq_batch, no_lt=int(no_lt),
+                    eps_lt=float(eps_lt))
 
 
 # ------------------------------------------------------------------ graphs

@@ -530,6 +530,45 @@ def test_g0w0_tiny_without_laplace(gw, ctx, tiny_problem, tiny_sos, prec, tol_me
     assert np.max(np.abs(sig - tiny_sos.sigma)) < stol * np.max(np.abs(tiny_sos.sigma))
 
 
+def test_g0w0_accuracy_driven_laplace_grid(gw, ctx, tiny_problem, tiny_sos):
+    """gw_params.eps_lt > 0 (Sec. 3, a threshold on the Laplace error instead
+    of a point count): the step takes the smallest grid whose minimax level
+    meets eps_lt, reports its size, and reproduces the fixed-size step with
+    that many points bitwise; a tighter eps_lt does not move the QP energies
+    away from the sum-over-states result."""
+    import dataclasses
+    p = tiny_problem
+    c = p.cfg
+    R = [dev(a, "fp64") for a in (p.R_oo, p.R_ov, p.R_qp)]
+    om, _ = gw.gw_freq_grid_mgl(c.n_freq, c.x0)
+    _, ymin, ymax = gw.gw_prepare(c.n_occ, c.n_fc, c.n_virt, p.eps, om[0])
+    errs = []
+    for eps_lt in (1e-3, 1e-5, 1e-7):
+        # n_lt = 0: no bound below the library's 20 points
+        params = gw.params_for(dataclasses.replace(c, n_lt=0), tol=1e-10, max_iter=200,
+                               eps_lt=eps_lt)
+        E, _, S, _, st = gw.gw_g0w0(ctx, "fp64", params, p.eps, p.qp, None, *R)
+        assert np.all(S == 0) and 1 <= st.n_lt <= 20 and st.lt_err_norm <= eps_lt
+        if st.n_lt > 1:
+            assert gw.gw_lt_grid_minimax(st.n_lt - 1, ymin, ymax)[2] > eps_lt
+        fixed = gw.params_for(dataclasses.replace(c, n_lt=st.n_lt), tol=1e-10, max_iter=200)
+        E2, _, S2, _, st2 = gw.gw_g0w0(ctx, "fp64", fixed, p.eps, p.qp, None, *R)
+        assert st2.n_lt == st.n_lt and np.array_equal(E, E2)
+        errs.append(float(np.max(np.abs(E - tiny_sos.eps_qp)) * HARTREE_MEV))
+        _say(f"  eps_lt {eps_lt:g}: L = {st.n_lt}, level {st.lt_err_norm:.2e}, "
+             f"QP vs sum over states {errs[-1]:.2e} meV")
+    assert errs[2] <= errs[0]
+    # the bound binds: 8 points cannot reach 1e-7 here
+    capped = gw.params_for(c, tol=1e-10, max_iter=200, eps_lt=1e-7)
+    with pytest.raises(gw.GwError) as ei:
+        gw.gw_g0w0(ctx, "fp64", capped, p.eps, p.qp, None, *R)
+    assert ei.value.status == gw.GW_ENOCONV
+    bad = gw.params_for(c, eps_lt=-1.0)
+    with pytest.raises(gw.GwError) as ei:
+        gw.gw_g0w0(ctx, "fp64", bad, p.eps, p.qp, None, *R)
+    assert ei.value.status == gw.GW_EINVAL
+
+
 def _golden(name):
     path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")
     if not os.path.exists(path):
