@@ -60,22 +60,18 @@ __device__ __forceinline__ void assemble_elem(const AsmArgs& a, const double* co
     for (int j = 0; j < a.F; ++j) a.A[j * NN + idx] = d + 4.0 * a.M[j * NN + idx];   // 2 s, s = 2
     return;
   }
+  // fully unrolled over the at most 32 Laplace points, so mv stays in
+  // registers (a loop bounded by L alone indexes it dynamically: scratch)
   double mv[32];
-  for (int m = 0; m < a.L; ++m) mv[m] = a.M[m * NN + idx];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) mv[m] = m < a.L ? a.M[m * NN + idx] : 0.0;
   for (int j = 0; j < a.F; ++j) {
     double v = d;
-    for (int m = 0; m < a.L; ++m) v += coef[j * a.L + m] * mv[m];
+#pragma unroll
+    for (int m = 0; m < 32; ++m)
+      if (m < a.L) v += coef[j * a.L + m] * mv[m];
     a.A[j * NN + idx] = v;
   }
-}
-
-__global__ void assemble_kernel(AsmArgs a) {
-  extern __shared__ double coef[];   // [F][L]
-  load_coef(a, coef);
-  const int64_t NN = (int64_t)a.N * a.N;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < NN;
-       idx += (int64_t)gridDim.x * blockDim.x)
-    assemble_elem(a, coef, idx);
 }
 
 __global__ void assemble_batched_kernel(Batch bt) {
@@ -531,33 +527,53 @@ struct FinArgs {
   void* W;              // [F][N][N] FP64 or FP32
 };
 
-template <typename T>
-__device__ __forceinline__ void finish_elem(const FinArgs& a, int64_t idx) {
-  const int64_t NN = (int64_t)a.N * a.N;
-  if (idx >= (int64_t)a.F * NN) return;
-  const int64_t j = idx / NN, e = idx % NN;
-  const int p = (int)(e / a.N), q = (int)(e % a.N);
-  if (q > p) return;
-  const double v = -a.S[j * NN + e] - (p == q ? 1.0 : 0.0);
-  T* W = static_cast<T*>(a.W);
-  W[j * NN + (int64_t)p * a.N + q] = (T)v;
-  W[j * NN + (int64_t)q * a.N + p] = (T)v;
+// W_j = -(S_j + 1) with the lower triangle of S_j mirrored, in 32 x 32
+// tiles: block b of a job is lower tile (P, Q), P >= Q, of matrix j; both
+// W(P, Q) and its transpose W(Q, P) are written row-contiguously through an
+// LDS copy of the tile.
+constexpr int FT = 32;
+__device__ __forceinline__ int64_t finish_tiles(int N) {
+  const int64_t T = (N + FT - 1) / FT;
+  return T * (T + 1) / 2;
 }
 
 template <typename T>
-__global__ void finish_kernel(FinArgs a) {
-  const int64_t total = (int64_t)a.F * a.N * a.N;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x)
-    finish_elem<T>(a, idx);
+__device__ __forceinline__ void finish_tile(const FinArgs& a, int64_t tile, double (*sh)[FT + 1]) {
+  const int64_t NN = (int64_t)a.N * a.N, per = finish_tiles(a.N);
+  const int64_t j = tile / per;
+  int t = (int)(tile % per), P = 0;
+  while (t > P) { t -= P + 1; ++P; }                  // t-th tile of block row P
+  const int Q = t;
+  const double* S = a.S + j * NN;
+  T* W = static_cast<T*>(a.W) + j * NN;
+  const int c = threadIdx.x % FT, r0 = threadIdx.x / FT;
+#pragma unroll
+  for (int k = 0; k < FT; k += 256 / FT) {
+    const int r = r0 + k, gr = P * FT + r, gc = Q * FT + c;
+    sh[r][c] = (gr < a.N && gc < a.N && gr >= gc) ? S[(int64_t)gr * a.N + gc] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < FT; k += 256 / FT) {
+    const int r = r0 + k, gr = P * FT + r, gc = Q * FT + c;
+    // element (r, c) of tile (P, Q) of the symmetric matrix
+    const double sv = (P > Q || r >= c) ? sh[r][c] : sh[c][r];
+    if (gr < a.N && gc < a.N) W[(int64_t)gr * a.N + gc] = (T)(-sv - (gr == gc ? 1.0 : 0.0));
+    if (P > Q) {
+      const int tr = Q * FT + r, tc = P * FT + c;     // element (r, c) of tile (Q, P)
+      if (tr < a.N && tc < a.N) W[(int64_t)tr * a.N + tc] = (T)(-sh[c][r]);
+    }
+  }
+  __syncthreads();
 }
 
 template <typename T>
 __global__ void finish_batched_kernel(Batch bt) {
+  __shared__ double sh[FT][FT + 1];
   FinArgs a;
   int64_t first;
   if (!block_of(bt, a, first)) return;
-  for (int e = 0; e < kBatchElems; e += 256) finish_elem<T>(a, first + e + threadIdx.x);
+  finish_tile<T>(a, first / kBatchElems, sh);
 }
 
 // ------------------------------------------------------------------ host
@@ -716,7 +732,8 @@ gw_status screen_jobs(gw_ctx ctx, gw_precision prec, int L, const std::vector<Sc
     asm_d.push_back(AsmArgs{j.M, L, j.N, j.x, j.omega, j.F, A, sos});
     n_asm.push_back((int64_t)j.N * j.N);
     fin_d.push_back(FinArgs{A, j.N, j.F, j.W_hat});
-    n_fin.push_back((int64_t)j.F * j.N * j.N);
+    const int64_t T = (j.N + FT - 1) / FT;
+    n_fin.push_back((int64_t)j.F * (T * (T + 1) / 2) * kBatchElems);   // one block per tile
     flops += (double)j.F * j.N * (double)j.N * j.N;
     bytes += (double)j.F * j.N * (double)j.N * 8.0 * 2.0;
   }
