@@ -112,7 +112,7 @@ __global__ void reorder_kernel(const double* __restrict__ V, int n, int rows,
 // follows from appending one reflector at a time to the product (the larft
 // recurrence): the Gram matrices of all blocks are one batched GEMM, and T is
 // applied by a triangular solve with T^{-1} instead of being formed.
-constexpr int kBackNb = 128;
+constexpr int kBackNb = 256;
 
 // Reflector storage (column-major, ld n; v_k below row k + 1 of column k)
 // made explicit in place: zeros above row k + 1 and a one at row k + 1.  A
