@@ -15,6 +15,7 @@
 // cost, N^3 flops per matrix on the triangle) and the panel product run on
 // v_mfma_f64_16x16x4f64; the matrices are streamed once per 256 columns.
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <string>
 
@@ -598,33 +599,52 @@ size_t sweep_scratch(const std::vector<SweepSet>& sets) {
   return t;
 }
 
+// The sweep's launches are planned on the host first: every launch's
+// argument structs and work-unit offsets go into one blob, uploaded with a
+// single staging copy, and the launches then read their slices of it (one
+// copy per sweep instead of one or two per launch).
+struct SweepLaunch {
+  void (*kern)(Batch);    // nullptr: pivot_batched_kernel
+  size_t args_at, off_at; // byte offsets of the SwArgs and offsets arrays in the blob
+  int n, chunk, threads;
+  int64_t units, grid;
+  const char* what;
+};
+
+struct SweepPlan {
+  std::vector<unsigned char> blob;
+  std::vector<SweepLaunch> launches;
+  template <typename T>
+  size_t put(const T* p, size_t count) {
+    const size_t at = (blob.size() + 15) & ~size_t(15);
+    blob.resize(at + count * sizeof(T));
+    std::memcpy(blob.data() + at, p, count * sizeof(T));
+    return at;
+  }
+};
+
 template <typename F>
-gw_status launch_units(gw_ctx ctx, const SwArgs* dst, const std::vector<SwArgs>& st, F units,
-                       int chunk, bool elems, void (*kern)(Batch), int threads,
-                       const char* what) {
+void plan_units(SweepPlan& plan, size_t args_at, const std::vector<SwArgs>& st, F units,
+                int chunk, bool elems, void (*kern)(Batch), int threads, const char* what) {
   std::vector<int64_t> off(1, 0);
   for (const SwArgs& a : st) {
     const int64_t u = units(a);
     off.push_back(off.back() + (elems ? (u + kBatchElems - 1) / kBatchElems : u));
   }
-  if (off.back() == 0) return GW_OK;
-  const int64_t* doff = gw::stage_t(ctx, off.data(), off.size());
-  if (!doff) return GW_EINVAL;
-  const Batch bt{dst, doff, (int)st.size(), chunk, off.back()};
+  if (off.back() == 0) return;
   const int64_t grid = chunk > 1 ? (off.back() + 8 * chunk - 1) / (8 * chunk) * (8 * chunk)
                                  : off.back();
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), 0, ctx->stream, bt);
-  return gw::launch_check(ctx, what);
+  plan.launches.push_back(SweepLaunch{kern, args_at, plan.put(off.data(), off.size()),
+                                      (int)st.size(), chunk, threads, off.back(), grid, what});
 }
 
-// Sweep every set to -A^-1 with pivot blocks of width pw: B (one level, each
-// 64 x 64 pivot inverted in registers) or 128 / 256 (outer level, whose pivot
-// blocks are inverted by a one-level sweep of their copies).  `scr` holds
-// sweep_scratch(sets) doubles.
-gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* scr) {
+// Plan the sweep of every set to -A^-1 with pivot blocks of width pw: B (one
+// level, each 64 x 64 pivot inverted in registers) or 128 / 256 (outer
+// level, whose pivot blocks are inverted by a one-level sweep of their
+// copies).  `scr` holds sweep_scratch(sets) doubles.
+void plan_sweep(SweepPlan& plan, const std::vector<SweepSet>& sets, int pw, double* scr) {
   const int n = (int)sets.size();
   std::vector<double*> C(n), P(n), X(n);   // X: Dw (outer) or Dinv (inner)
-  std::vector<SweepSet> inner(n);
   size_t o = 0;
   for (int d = 0; d < n; ++d) {
     const SweepSet& s = sets[d];
@@ -651,46 +671,54 @@ gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* s
       st.push_back(a);
       if (pw > B) dsets.push_back(SweepSet{X[d], bw, s.F, s.flag_base});
     }
-    const SwArgs* dst = static_cast<const SwArgs*>(gw::stage(ctx, st.data(), st.size() * sizeof(SwArgs)));
-    if (!dst) return GW_EINVAL;
-    GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; },
-                        1, true, gather_panel_batched_kernel, 256, "gather_panel"));
+    const size_t at = plan.put(st.data(), st.size());
+    plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; }, 1, true,
+               gather_panel_batched_kernel, 256, "gather_panel");
     if (pw == B) {
-      std::vector<int64_t> off(1, 0);
-      for (const SwArgs& a : st) off.push_back(off.back() + a.F);
-      const int64_t* doff = gw::stage_t(ctx, off.data(), off.size());
-      if (!doff) return GW_EINVAL;
-      hipLaunchKernelGGL(pivot_batched_kernel, dim3((unsigned)off.back()), dim3(PIV_THREADS), 0,
-                         ctx->stream, Batch{dst, doff, (int)st.size(), 1, off.back()},
-                         ctx->d_flags);
-      GW_TRY(gw::launch_check(ctx, "pivot_batched_kernel"));
-      GW_TRY(launch_units(ctx, dst, st,
-                          [](const SwArgs& a) { return (int64_t)a.F * a.panel_blocks; }, 1, false,
-                          panel_batched_kernel, 256, "panel_batched_kernel"));
+      plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F; }, 1, false, nullptr,
+                 PIV_THREADS, "pivot_batched_kernel");
+      plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.panel_blocks; }, 1,
+                 false, panel_batched_kernel, 256, "panel_batched_kernel");
     } else {
-      GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.bw * a.bw; },
-                          1, true, extract_pivot_batched_kernel, 256, "extract_pivot"));
-      GW_TRY(sweep(ctx, dsets, B, inner_scr));
-      GW_TRY(launch_units(ctx, dst, st,
-                          [](const SwArgs& a) {
-                            return (int64_t)a.F * ((a.N + B - 1) / B) * (a.pw / B);
-                          },
-                          8, false, panel_gemm_batched_kernel, 256, "panel_gemm"));
+      plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.bw * a.bw; }, 1,
+                 true, extract_pivot_batched_kernel, 256, "extract_pivot");
+      plan_sweep(plan, dsets, B, inner_scr);
+      plan_units(plan, at, st,
+                 [](const SwArgs& a) { return (int64_t)a.F * ((a.N + B - 1) / B) * (a.pw / B); },
+                 8, false, panel_gemm_batched_kernel, 256, "panel_gemm");
     }
     if (pw > B) {
-      GW_TRY(launch_units(ctx, dst, st,
-                          [](const SwArgs& a) {
-                            const int64_t t = (a.N + BU - 1) / BU;
-                            return (int64_t)a.F * t * (t + 1) / 2;
-                          },
-                          8, false, update128_batched_kernel, 512, "update128_kernel"));
+      plan_units(plan, at, st,
+                 [](const SwArgs& a) {
+                   const int64_t t = (a.N + BU - 1) / BU;
+                   return (int64_t)a.F * t * (t + 1) / 2;
+                 },
+                 8, false, update128_batched_kernel, 512, "update128_kernel");
     } else {
-      GW_TRY(launch_units(ctx, dst, st,
-                          [](const SwArgs& a) { return (int64_t)a.F * a.T * (a.T + 1) / 2; }, 8,
-                          false, update_batched_kernel, 256, "update_kernel"));
+      plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.T * (a.T + 1) / 2; },
+                 8, false, update_batched_kernel, 256, "update_kernel");
     }
-    GW_TRY(launch_units(ctx, dst, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; },
-                        1, true, writeback_batched_kernel, 256, "writeback"));
+    plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; }, 1, true,
+               writeback_batched_kernel, 256, "writeback");
+  }
+}
+
+gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* scr) {
+  SweepPlan plan;
+  plan_sweep(plan, sets, pw, scr);
+  if (plan.launches.empty()) return GW_OK;
+  const unsigned char* dev =
+      static_cast<const unsigned char*>(gw::stage(ctx, plan.blob.data(), plan.blob.size()));
+  if (!dev) return GW_EINVAL;
+  for (const SweepLaunch& l : plan.launches) {
+    const Batch bt{reinterpret_cast<const SwArgs*>(dev + l.args_at),
+                   reinterpret_cast<const int64_t*>(dev + l.off_at), l.n, l.chunk, l.units};
+    if (l.kern)
+      hipLaunchKernelGGL(l.kern, dim3((unsigned)l.grid), dim3(l.threads), 0, ctx->stream, bt);
+    else
+      hipLaunchKernelGGL(pivot_batched_kernel, dim3((unsigned)l.grid), dim3(l.threads), 0,
+                         ctx->stream, bt, ctx->d_flags);
+    GW_TRY(gw::launch_check(ctx, l.what));
   }
   return GW_OK;
 }
