@@ -68,10 +68,11 @@ def measured_traffic(kernel, workload):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(prob, n_freq_sample=2):
-    """Oracle (FP64 NumPy) on a bounded sample: the NAF stage once and the
-    per-frequency work (sum-over-states Pi, dense inverse, W_nm) for
-    `n_freq_sample` of the F frequencies, extrapolated to the full step."""
+def cpu_baseline(prob, n_freq_sample=24):
+    """Oracle (FP64 NumPy) on a bounded sample (about 10 s on 16 cores): the
+    NAF stage once and the per-frequency work (sum-over-states Pi, dense
+    inverse, W_nm) for `n_freq_sample` of the F frequencies, evenly spread
+    over the grid, extrapolated to the full step."""
     from threadpoolctl import threadpool_info
     from oracle import grids, naf, rpa
     c = prob.cfg
@@ -85,7 +86,7 @@ def cpu_baseline(prob, n_freq_sample=2):
     Rt_qp = naf.naf_transform(R_qp, U)
     t_naf = time.perf_counter() - t0
     om, _ = grids.modified_gauss_legendre(c.n_freq, c.x0)
-    sel = om[[0, len(om) // 2]][:n_freq_sample]
+    sel = om[np.unique(np.linspace(0, len(om) - 1, min(n_freq_sample, len(om))).astype(int))]
     d = rpa.delta_ov(prob.eps, c.n_fc, c.n_occ)
     t0 = time.perf_counter()
     W = rpa.w_diag(Rt_qp, rpa.screen(rpa.pi_sos(Rt_ov, d, sel)))

@@ -320,7 +320,13 @@ __global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a0, Batch bt) {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 constexpr int BKB = 32;
-constexpr int LDB = BKB + 8;
+// k stride (bf16) of an LDS row: unpadded, with the 16-byte k-chunks of a row
+// XOR-swizzled by the row so the 16-byte operand reads of 32 consecutive rows
+// stay conflict-free (64 KB of tiles: two workgroups per CU)
+constexpr int LDB = BKB;
+__device__ __forceinline__ int swz(int row, int k) {
+  return (((k >> 3) ^ ((row >> 2) & 3)) << 3) | (k & 7);
+}
 
 __device__ __forceinline__ void split4(const float4 v, bf16x4& hi, bf16x4& lo) {
   const float x[4] = {v.x, v.y, v.z, v.w};
@@ -386,7 +392,7 @@ __global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a0, Batch bt)
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-      const int lr = (tid >> 3) + 32 * h, kk = (tid & 7) * 4;
+      const int lr = (tid >> 3) + 32 * h, kk = swz(lr, (tid & 7) * 4);
       bf16x4 hi, lo;
       split4(ra[h], hi, lo);
       *reinterpret_cast<bf16x4*>(&Ah[buf][lr][kk]) = hi;
@@ -415,10 +421,11 @@ __global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a0, Batch bt)
       for (int i = 0; i < 2; ++i) {
         const int pr = wy * 64 + i * 32 + (lane & 31);
         const int qc = wx * 64 + i * 32 + (lane & 31);
-        ahf[i] = *reinterpret_cast<const bf16x8*>(&Ah[cur][pr][ks + kl]);
-        alf[i] = *reinterpret_cast<const bf16x8*>(&Al[cur][pr][ks + kl]);
-        bhf[i] = *reinterpret_cast<const bf16x8*>(&Bh[cur][qc][ks + kl]);
-        blf[i] = *reinterpret_cast<const bf16x8*>(&Bl[cur][qc][ks + kl]);
+        const int kp = swz(pr, ks + kl), kq = swz(qc, ks + kl);
+        ahf[i] = *reinterpret_cast<const bf16x8*>(&Ah[cur][pr][kp]);
+        alf[i] = *reinterpret_cast<const bf16x8*>(&Al[cur][pr][kp]);
+        bhf[i] = *reinterpret_cast<const bf16x8*>(&Bh[cur][qc][kq]);
+        blf[i] = *reinterpret_cast<const bf16x8*>(&Bl[cur][qc][kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
