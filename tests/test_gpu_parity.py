@@ -558,6 +558,13 @@ def test_g0w0_accuracy_driven_laplace_grid(gw, ctx, tiny_problem, tiny_sos):
         _say(f"  eps_lt {eps_lt:g}: L = {st.n_lt}, level {st.lt_err_norm:.2e}, "
              f"QP vs sum over states {errs[-1]:.2e} meV")
     assert errs[2] <= errs[0]
+    # evGW takes the grid per cycle on that cycle's bounds; its first cycle
+    # is the G0W0 step with the same eps_lt
+    params = gw.params_for(dataclasses.replace(c, n_lt=0), tol=1e-10, max_iter=200, eps_lt=1e-5)
+    E0, _, S0, _, st0 = gw.gw_g0w0(ctx, "fp64", params, p.eps, p.qp, None, *R)
+    Ec, _, Sc, _, stc = gw.gw_evgw(ctx, "fp64", params, 2, p.eps, p.qp, None, *R)
+    assert np.all(Sc == 0) and 1 <= stc.n_lt <= 20 and stc.lt_err_norm <= 1e-5
+    assert np.max(np.abs(Ec[0] - E0)) * HARTREE_MEV < 1e-9
     # the bound binds: 8 points cannot reach 1e-7 here
     capped = gw.params_for(c, tol=1e-10, max_iter=200, eps_lt=1e-7)
     with pytest.raises(gw.GwError) as ei:
