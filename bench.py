@@ -408,8 +408,8 @@ def main():
     ap.add_argument("--screen-gb", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
-              "sharding of the path is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the path is built "
+              "for one GPU; sharding it over several is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
