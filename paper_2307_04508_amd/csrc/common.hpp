@@ -266,6 +266,32 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// DPP move of a double (both 32-bit halves) inside the wave's rows of 16
+// lanes, or a row broadcast; lanes of rows outside ROW_MASK receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// Sums over each half wave, complete in lane 31 (lanes 0-31) and lane 63
+// (lanes 32-63): quad sums, half-row and row mirrors, then the last lane of
+// rows 0 and 2 broadcast into rows 1 and 3.  VALU only (a shuffle tree
+// would take an LDS permute per step).
+// Sums over each row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xF>(v);    // row_half_mirror
+  v += dpp_move<0x140, 0xF>(v);    // row_mirror
+  return v;
+}
+__device__ __forceinline__ double half_wave_sum(double v) {
+  v = row16_sum(v);
+  v += dpp_move<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+  return v;
+}
+
 // Map a hardware workgroup index to a logical one so that workgroups placed
 // on the same XCD (dispatched round-robin over the 8 XCDs) receive
 // consecutive logical indices and share data through that XCD's L2.

@@ -173,9 +173,8 @@ __global__ __launch_bounds__(NTD, 4) void bwb_f32_direct_kernel(BwbArgs a0, Batc
         if (col < N) sum += (double)acc[jj][r] * (double)R[row * a.ldr + col];
       }
     }
-#pragma unroll
-    for (int off = 16; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
-    if ((lane & 31) == 0 && row < a.rows) part[row] = sum;
+    sum = half_wave_sum(sum);
+    if ((lane & 31) == 31 && row < a.rows) part[row] = sum;
   }
 }
 
@@ -304,8 +303,7 @@ __global__ __launch_bounds__(NT, 1) void bwb_f64_kernel(BwbArgs a0, Batch bt) {
           if (col < a.N) s += acc[i][jj][r] * R[row * a.ldr + col];
         }
       }
-#pragma unroll
-      for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+      s = row16_sum(s);
       if ((lane & 15) == 0 && row < a.rows) part[row] = s;
     }
   }
@@ -467,9 +465,8 @@ __global__ __launch_bounds__(NT, 2) void bwb_bf16x3_kernel(BwbArgs a0, Batch bt)
           if (col < a.N) sum += (double)acc[i][jj][r] * (double)R[row * a.ldr + col];
         }
       }
-#pragma unroll
-      for (int off = 16; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, 64);
-      if ((lane & 31) == 0 && row < a.rows) part[row] = sum;
+      sum = half_wave_sum(sum);
+      if ((lane & 31) == 31 && row < a.rows) part[row] = sum;
     }
   }
 }

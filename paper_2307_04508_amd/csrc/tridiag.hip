@@ -53,21 +53,11 @@ constexpr int kBarGroup = 32;
 constexpr int kCtrStride = 32;    // unsigneds: one 128-byte line per counter
 
 // Sum over the 64 lanes of a wave, complete in lane 63 only (other lanes
-// hold partial sums).  DPP moves within rows of 16 lanes, then the row
-// broadcasts of lanes 15 and 31: VALU only, no LDS round trip per step.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
+// hold partial sums): the half-wave sums (half_wave_sum), then lane 31
+// broadcast into rows 2 and 3.  VALU only, no LDS round trip per step.
 constexpr int kLastLane = 63;
 __device__ __forceinline__ double wave_total(double v) {
-  v += dpp_move<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
-  v += dpp_move<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]: quad sums
-  v += dpp_move<0x141, 0xF>(v);    // row_half_mirror: sums of 8
-  v += dpp_move<0x140, 0xF>(v);    // row_mirror: row sums of 16
-  v += dpp_move<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+  v = half_wave_sum(v);
   v += dpp_move<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
   return v;
 }
