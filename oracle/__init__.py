@@ -1,6 +1,6 @@
 """Plain FP64 CPU oracle for LT-AC G0W0 -- TEST INFRASTRUCTURE ONLY.
 
-This package is the slow, obviously-correct reference the GPU path is judged
+This package is the slow, obviously-correct reference the GPU path is checked
 against.  Only the test suite, the package smoke check and the CPU-baseline
 leg of the benchmark may import it; the product path never does.  It shares
 no code with the HIP library and does not import it.
