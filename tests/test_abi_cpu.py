@@ -125,3 +125,34 @@ def test_binding_uses_a_single_hip_runtime():
     with open("/proc/self/maps") as f:
         libs = {ln.split()[-1] for ln in f if "libamdhip64" in ln}
     assert len({os.path.realpath(p) for p in libs}) == 1, libs
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """A copy of the binding next to no libgwlt.so refuses to import: there
+    is no CPU fallback to route calls to."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "gwpkg"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text("")
+    shutil.copy(os.path.join(ROOT, "paper_2307_04508_amd", "gwlt.py"), pkg / "gwlt.py")
+    res = subprocess.run([sys.executable, "-c", "import gwpkg.gwlt"], cwd=tmp_path,
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode != 0
+    assert "ImportError" in res.stderr and "libgwlt.so not found" in res.stderr
+
+
+def test_product_code_never_reaches_the_oracle():
+    """Nothing in the package (binding, build script, HIP and C++ sources)
+    imports, loads or names the oracle package."""
+    pkg = os.path.join(ROOT, "paper_2307_04508_amd")
+    pat = re.compile(r"^\s*(?:from|import)\s+oracle\b|\boracle[./]", re.M)
+    hits = []
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h", ".inc")):
+                p = os.path.join(dirpath, f)
+                if pat.search(open(p, encoding="utf-8", errors="replace").read()):
+                    hits.append(p)
+    assert hits == []
