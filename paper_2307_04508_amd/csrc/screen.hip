@@ -424,11 +424,21 @@ __global__ __launch_bounds__(512, 2) void update128_batched_kernel(Batch bt) {
   double* Aj = sa.A + (int64_t)j * N * N;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wy = wave >> 1, wx = wave & 1;            // rows wy*32, cols wx*64
+  // The accumulators start from the tile of A and P enters LDS negated, so
+  // the MFMAs leave A - P C^T in them: the tile is read at the start, where
+  // its latency overlaps that of the first panel loads, and only stored at
+  // the end.
   f64x4 acc[2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = I * BU + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int col = J * BU + wx * 64 + b * 16 + (lane & 15);
+        acc[a][b][r] = (row < N && col < N) ? Aj[(int64_t)row * N + col] : 0.0;
+      }
   // loader: rows (tid >> 3) + 64 h, k pair (tid & 7) * 2
   const int lr = tid >> 3, lk = (tid & 7) * 2;
   double2 rp[2], rc[2];
@@ -445,8 +455,8 @@ __global__ __launch_bounds__(512, 2) void update128_batched_kernel(Batch bt) {
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      Ps[buf][lk][lr + 64 * h] = rp[h].x;
-      Ps[buf][lk + 1][lr + 64 * h] = rp[h].y;
+      Ps[buf][lk][lr + 64 * h] = -rp[h].x;
+      Ps[buf][lk + 1][lr + 64 * h] = -rp[h].y;
       Cs[buf][lk][lr + 64 * h] = rc[h].x;
       Cs[buf][lk + 1][lr + 64 * h] = rc[h].y;
     }
@@ -483,10 +493,7 @@ __global__ __launch_bounds__(512, 2) void update128_batched_kernel(Batch bt) {
       for (int r = 0; r < 4; ++r) {
         const int row = I * BU + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
         const int col = J * BU + wx * 64 + b * 16 + (lane & 15);
-        if (row < N && col < N) {
-          double* e = Aj + (int64_t)row * N + col;
-          *e -= acc[a][b][r];
-        }
+        if (row < N && col < N) Aj[(int64_t)row * N + col] = acc[a][b][r];
       }
 }
 
