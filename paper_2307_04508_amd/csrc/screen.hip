@@ -282,7 +282,7 @@ __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
 // in its lower triangle, so P = C D^-1), 64 x 64 output tiles, k in chunks
 // of 64 over the bw pivot columns; columns c >= bw are zero.
 __global__ __launch_bounds__(256) void panel_gemm_batched_kernel(Batch bt) {
-  __shared__ double Xs[B][LDP];
+  __shared__ __attribute__((aligned(16))) double Xs[B][LDP];
   __shared__ double Ys[B][LDP];
   SwArgs sa;
   int64_t lid;
@@ -302,14 +302,43 @@ __global__ __launch_bounds__(256) void panel_gemm_batched_kernel(Batch bt) {
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // loads: thread t covers row (or column) t >> 2, 16 consecutive entries
+  // from 16 (t & 3), all issued before the first LDS store
+  const int lr = tid >> 2, lc = (tid & 3) * 16;
   for (int k0 = 0; k0 < bw; k0 += B) {
-    for (int i = tid; i < B * B; i += 256) {
-      const int r = i / B, k = i % B;
-      const int gr = I * B + r, gk = k0 + k, gc = J * B + r;
-      Xs[r][k] = (gr < N && gk < bw) ? Cj[(int64_t)gr * pw + gk] : 0.0;
-      double y = 0.0;
-      if (gc < bw && gk < bw) y = gc >= gk ? Dj[(int64_t)gc * bw + gk] : Dj[(int64_t)gk * bw + gc];
-      Ys[r][k] = y;
+    // C rows I B + lr, columns k0 + lc ...: pairs (pw and k0 + lc even, so
+    // 16-byte aligned; the pair's second column is < pw), zero past bw
+    const int gr = I * B + lr;
+    double2 xv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int gk = k0 + lc + 2 * e;
+      xv[e] = make_double2(0.0, 0.0);
+      if (gr < N && gk < bw) {
+        xv[e] = *reinterpret_cast<const double2*>(Cj + (int64_t)gr * pw + gk);
+        if (gk + 1 >= bw) xv[e].y = 0.0;
+      }
+    }
+    // symmetric D (lower triangle stored): entries with column <= row are
+    // read along rows of D, the others along columns, so both are
+    // contiguous per thread; every entry is written once, zero past bw
+    double yl[16], yu[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int gc = J * B + lr, gk = k0 + lc + e;              // Ys[lr][lc + e]
+      yl[e] = (gc < bw && gk < bw && gc >= gk) ? Dj[(int64_t)gc * bw + gk] : 0.0;
+      const int hc = J * B + lc + e, hk = k0 + lr;              // Ys[lc + e][lr]
+      yu[e] = (hc < bw && hk < bw && hc < hk) ? Dj[(int64_t)hk * bw + hc] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      *reinterpret_cast<double2*>(&Xs[lr][lc + 2 * e]) = xv[e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int gc = J * B + lr, gk = k0 + lc + e;
+      if (!(gc < bw && gk < bw && gc < gk)) Ys[lr][lc + e] = yl[e];
+      const int hc = J * B + lc + e, hk = k0 + lr;
+      if (hc < bw && hk < bw && hc < hk) Ys[lc + e][lr] = yu[e];
     }
     __syncthreads();
     mfma_chunk(Xs, Ys, acc, wy, wx, lane);
