@@ -649,3 +649,29 @@ def test_autotuner_keeps_choices_and_results(gw, ctx):
         Wh = Wt.cpu().numpy()
         for j in range(F):
             assert rel_fro(Wh[j], ref[j]) < 1e-11
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N,F", [(333, 2), (257, 2), (300, 1)])
+def test_screen_outer_level_ragged_last_block(gw, ctx, N, F):
+    """With tuning off the sweep takes the 256-wide outer level; orders whose
+    last pivot block is odd (77, 1) or even (44) wide check the panel
+    product's edge handling against the oracle."""
+    _say(f"screen outer level N={N} F={F}")
+    L = 3
+    M = _spd_m(5, L, N)
+    x = np.array([0.05, 0.5, 3.0])
+    om, _ = grids.modified_gauss_legendre(F, 0.5)
+    ref = rpa.screen(rpa.pi_lt(M, x, om))
+    W = torch.zeros((F, N, N), dtype=torch.float64, device="cuda")
+    gw.gw_autotune(ctx, 2)      # forget kept choices, so tuning off means the default
+    gw.gw_autotune(ctx, 0)
+    try:
+        gw.gw_screen(ctx, "fp64", N, x, dev(M, "fp64"), om, W)
+        gw.gw_sync(ctx)
+    finally:
+        gw.gw_autotune(ctx, 1)
+    Wh = W.cpu().numpy()
+    for j in range(F):
+        assert rel_fro(Wh[j], ref[j]) < 1e-11, (j, rel_fro(Wh[j], ref[j]))
+        assert np.array_equal(Wh[j], Wh[j].T)
