@@ -73,7 +73,7 @@ class DeviceRowSource:
             host.cfg = cfg
             host.n_tot = cfg.n_occ + cfg.n_virt
             n_all = host.n_tot * (host.n_tot + 1) / 2.0
-            host.c = 1.0
+            host.c = cfg.c_scale
             tau = decay_length(cfg)
             s = np.exp(-np.arange(A) / tau)
             host.colscale = (host.c / math.sqrt(n_all)) * s * math.sqrt(3.0)

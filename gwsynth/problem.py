@@ -139,9 +139,8 @@ class _RowSource:
             self.c = 1.0
             self.all_rows = (vt * (self.c * s)[None, :]) @ self.U.T
         else:
-            o, v = cfg.n_act_occ, cfg.n_virt
             n_all = self.n_tot * (self.n_tot + 1) / 2.0
-            self.c = 1.0
+            self.c = cfg.c_scale
             self.tau = decay_length(cfg)
             s = np.exp(-np.arange(A) / self.tau)
             self.colscale = (self.c / math.sqrt(n_all)) * s * math.sqrt(3.0)
@@ -174,6 +173,55 @@ class _RowSource:
         return out
 
 
+def _qp_states(cfg: Config) -> np.ndarray:
+    nf, no, nv = cfg.n_fc, cfg.n_occ, cfg.n_virt
+    homo, lumo = no - 1, no
+    qp = np.concatenate([np.arange(homo - cfg.n_qp_occ + 1, homo + 1),
+                         np.arange(lumo, lumo + cfg.n_qp_virt)])
+    if qp.min() < nf or qp.max() >= no + nv:
+        raise ValueError("QP states must be active orbitals")
+    return qp
+
+
+class ProblemStream:
+    """The problem of ``make_problem(cfg)`` with the occupied-occupied and
+    occupied-virtual blocks produced in occupied-index chunks on the host
+    (same draws, same rows), for shapes whose whole tensor does not fit in
+    host memory.  ``R_qp`` is materialised."""
+
+    def __init__(self, cfg: Config, dtype=np.float64):
+        if cfg.exact_orthonormal:
+            raise ValueError("the exactly orthonormal (tiny) recipe is not streamed")
+        rng = np.random.default_rng(cfg.seed)
+        self.cfg = cfg
+        self.eps = _energies(cfg, rng)
+        self.src = _RowSource(cfg, rng)
+        self.qp = _qp_states(cfg)
+        self.dtype = dtype
+        nf, no, nv = cfg.n_fc, cfg.n_occ, cfg.n_virt
+        act = np.arange(nf, no + nv)
+        qn, qm = np.meshgrid(self.qp, act, indexing="ij")
+        self.R_qp = self.src.rows(qn.ravel(), qm.ravel(), dtype).reshape(
+            self.qp.size, cfg.n_act, cfg.n_aux)
+
+    def oo_chunk(self, i0: int, i1: int) -> np.ndarray:
+        """Rows (i, j), active occupied i in [i0, i1) and every active
+        occupied j: [(i1 - i0)][o][A]."""
+        c = self.cfg
+        occ = np.arange(c.n_fc, c.n_occ)
+        vi, vj = np.meshgrid(occ[i0:i1], occ, indexing="ij")
+        return self.src.rows(vi.ravel(), vj.ravel(), self.dtype).reshape(
+            i1 - i0, c.n_act_occ, c.n_aux)
+
+    def ov_chunk(self, i0: int, i1: int) -> np.ndarray:
+        """Rows i*v + a for active occupied i in [i0, i1): [(i1-i0)*v][A]."""
+        c = self.cfg
+        occ = np.arange(c.n_fc + i0, c.n_fc + i1)
+        virt = np.arange(c.n_occ, c.n_occ + c.n_virt)
+        vi, va = np.meshgrid(occ, virt, indexing="ij")
+        return self.src.rows(vi.ravel(), va.ravel(), self.dtype)
+
+
 def make_problem(cfg: Config, dtype=np.float64) -> Problem:
     """Build the synthetic problem for ``cfg`` (deterministic in cfg.seed)."""
     rng = np.random.default_rng(cfg.seed)
@@ -184,11 +232,7 @@ def make_problem(cfg: Config, dtype=np.float64) -> Problem:
     act = np.arange(nf, no + nv)
     occ = np.arange(nf, no)
     virt = np.arange(no, no + nv)
-    homo, lumo = no - 1, no
-    qp = np.concatenate([np.arange(homo - cfg.n_qp_occ + 1, homo + 1),
-                         np.arange(lumo, lumo + cfg.n_qp_virt)])
-    if qp.min() < nf or qp.max() >= no + nv:
-        raise ValueError("QP states must be active orbitals")
+    qp = _qp_states(cfg)
 
     # Unique pairs needed by the three blocks, generated once.
     pi, pj = np.meshgrid(occ, occ, indexing="ij")

@@ -40,8 +40,6 @@ class Result:
 def g0w0(eps, n_fc, n_occ, qp, R_oo, R_ov, R_qp, *, eps_naf, max_keep=0,
          n_freq=32, n_pade=16, x0=0.5, eta=1e-3, lt=None, static=None,
          tol=1e-6, max_iter=100, keep=False, U=None) -> Result:
-    eps = np.asarray(eps, dtype=np.float64)
-    qp = np.asarray(qp)
     # NAF (Eqs. 11-13); U may be supplied to pin the basis
     if U is None:
         K = naf.naf_metric(R_oo, R_ov)
@@ -50,6 +48,18 @@ def g0w0(eps, n_fc, n_occ, qp, R_oo, R_ov, R_qp, *, eps_naf, max_keep=0,
         lam = np.array([])
     Rt_ov = naf.naf_transform(R_ov, U)
     Rt_qp = naf.naf_transform(R_qp, U)
+    return g0w0_naf(eps, n_fc, n_occ, qp, Rt_ov, Rt_qp, lam=lam, U=U, n_freq=n_freq,
+                    n_pade=n_pade, x0=x0, eta=eta, lt=lt, static=static, tol=tol,
+                    max_iter=max_iter, keep=keep)
+
+
+def g0w0_naf(eps, n_fc, n_occ, qp, Rt_ov, Rt_qp, *, lam=None, U=None, n_freq=32,
+             n_pade=16, x0=0.5, eta=1e-3, lt=None, static=None, tol=1e-6,
+             max_iter=100, keep=False) -> Result:
+    """The chain after the NAF transformation (Eq. 13), from the transformed
+    tensors Rt_ov [o*v][N] and Rt_qp [Q][M][N]."""
+    eps = np.asarray(eps, dtype=np.float64)
+    qp = np.asarray(qp)
     # grids
     omega, w_omega = grids.modified_gauss_legendre(n_freq, x0)
     omega_pade, _ = grids.modified_gauss_legendre(n_pade, x0)
@@ -62,7 +72,11 @@ def g0w0(eps, n_fc, n_occ, qp, R_oo, R_ov, R_qp, *, eps_naf, max_keep=0,
         M = rpa.m_lt(Rt_ov, d, np.asarray(x), np.asarray(w))
         Pi = rpa.pi_lt(M, np.asarray(x), omega)
     What = rpa.screen(Pi)
+    if not keep:
+        del Pi
+        Pi = None
     W = rpa.w_diag(Rt_qp, What)
+    del What
     eps_f = sigma.fermi_level(eps, n_occ)
     eps_m = eps[n_fc:]
     S = sigma.sigma_iw(W, eps_m, eps_f, omega, w_omega, omega_pade)
@@ -75,9 +89,10 @@ def g0w0(eps, n_fc, n_occ, qp, R_oo, R_ov, R_qp, *, eps_naf, max_keep=0,
         a = pade.thiele_coefficients(z_nodes, S[q])
         E[q], Z[q], conv[q] = pade.qp_solve(eps[n], c[q], eps_f, z_nodes, a, eta,
                                             tol=tol, max_iter=max_iter)
-    return Result(n_naf=U.shape[1], lam=lam, U=U, Rt_ov=Rt_ov, Rt_qp=Rt_qp,
+    return Result(n_naf=Rt_ov.shape[1], lam=np.array([]) if lam is None else lam,
+                  U=U, Rt_ov=Rt_ov, Rt_qp=Rt_qp,
                   omega=omega, w_omega=w_omega, omega_pade=omega_pade,
-                  eps_f=eps_f, Pi=Pi if keep else None, M=M if keep else None,
+                  eps_f=eps_f, Pi=Pi, M=M if keep else None,
                   W=W, sigma=S, eps_qp=E, z=Z, converged=conv)
 
 

@@ -45,3 +45,23 @@ def test_haar_on_device_matches_host_qr():
     assert np.array_equal(h.eps, d.eps)
     a, b = h.R_ov, d.R_ov.numpy()
     assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_host_stream_matches_host_problem():
+    """The host stream (occupied chunks, for workloads whose whole tensor does
+    not fit in memory) draws the same rows as make_problem, bitwise; the
+    scale c enters every row linearly."""
+    from gwsynth.problem import ProblemStream
+    cfg = get_config("medium").with_(n_occ=12, n_fc=4, n_virt=30, n_aux=64, naf_target=32,
+                                     n_qp_occ=2, n_qp_virt=2)
+    h = make_problem(cfg)
+    s = ProblemStream(cfg)
+    o, v, A = cfg.n_act_occ, cfg.n_virt, cfg.n_aux
+    assert np.array_equal(h.eps, s.eps) and np.array_equal(h.qp, s.qp)
+    assert np.array_equal(h.R_qp, s.R_qp)
+    assert np.array_equal(h.R_ov[3 * v:7 * v], s.ov_chunk(3, 7))
+    assert np.array_equal(h.R_oo[2:5], s.oo_chunk(2, 5))
+    h2 = make_problem(cfg.with_(c_scale=2.5))
+    assert np.max(np.abs(h2.R_ov - 2.5 * h.R_ov)) <= 1e-14 * np.max(np.abs(h2.R_ov))
+    d2 = make_problem_device(cfg.with_(c_scale=2.5), device="cpu")
+    assert np.max(np.abs(d2.R_ov.numpy() - h2.R_ov)) <= 1e-14 * np.max(np.abs(h2.R_ov))
