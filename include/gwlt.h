@@ -254,6 +254,24 @@ gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
                         int n_pade, const double* omega_pade, int accumulate,
                         double* sigma_iw, double* W_nm);
 
+/* gw_sigma_diag for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as gw_sigma_diag, but the
+ * call's buffers (row-dot partials, W_nm staging and, for GW_FP32, the
+ * k-major copy of R_qp) live in a fixed per-GPU scratch array of 64 MiB
+ * that the library holds from its loading until the process ends; nothing
+ * is allocated or freed.  A call needing more than 64 MiB returns GW_EINVAL
+ * (split the frequencies or the QP states over calls with accumulate = 1).
+ * Every call on one GPU uses that GPU's single array: calls that overlap
+ * on one GPU (several streams or contexts) race, so serialise them. */
+gw_status gw_sigma_diag_noalloc(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
+                                int n_mo, const double* eps_mo, double eps_F,
+                                const void* R_qp, int64_t ld_R, int n_w,
+                                const double* omega, const double* w_omega,
+                                const void* W_hat, int n_pade,
+                                const double* omega_pade, int accumulate,
+                                double* sigma_iw, double* W_nm);
+
 /* ------------------------------------------------ a9: Pade + QP solve */
 
 /* Sec. 2 and Sec. 3: Thiele continued-fraction Pade approximant through

@@ -236,6 +236,9 @@ void sigma_ws_bytes(int N, int64_t rows, int F, size_t* part_bytes, size_t* w_by
                     size_t* rt_bytes);
 // Zero n doubles with a kernel (capturable, unlike hipMemsetAsync).
 gw_status fill_zero(gw_ctx ctx, double* p, int64_t n);
+// Device address of the fixed scratch of gw_sigma_diag_noalloc on `device`
+// (which must be current); called once per device at context creation.
+gw_status sigma_scratch_init(gw_ctx ctx, int device);
 gw_status lt_scale_launch(gw_ctx ctx, gw_precision prec, int L,
                           const double* d_x, const double* d_w, int n_i,
                           int n_virt, const double* d_eps_i,

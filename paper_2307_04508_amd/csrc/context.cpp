@@ -388,6 +388,10 @@ gw_status gw_create(gw_ctx* out, int device, void* hip_stream) {
     gw_destroy(c);
     return gw::fail(nullptr, GW_ENOMEM, "gw_create: allocation failed");
   }
+  // the no-allocation entry point's scratch address on this device; a
+  // failure here is reported by that entry point, which retries the lookup
+  (void)gw::sigma_scratch_init(c, device);
+  gw::clear_error(c);
   *out = c;
   return GW_OK;
 }

@@ -15,6 +15,7 @@
 //  FP64:   v_mfma_f64_16x16x4f64, operands FP64, tile 128 x 128 x 16.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -596,24 +597,52 @@ gw::TransposeJob tr_job(const void* R, int64_t rows, int64_t ldr, int N, float* 
 
 }  // namespace
 
-extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
-                                   int n_mo, const double* eps_mo, double eps_F,
-                                   const void* R_qp, int64_t ld_R, int n_w,
-                                   const double* omega,
-                                   const double* w_omega, const void* W_hat, int n_pade,
-                                   const double* omega_pade, int accumulate,
-                                   double* sigma_iw, double* W_nm) {
-  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_sigma_diag: ctx is NULL");
-  gw::clear_error(ctx);
+namespace {
+
+// Device buffers of one gw_sigma_diag call.
+struct SigmaBufs {
+  double* part;   // [F][2 * col_tiles][rows]
+  double* W;      // [F][rows]
+  float* RT;      // [N][rt_ld(rows)], FP32 path only
+};
+
+// Bytes of each buffer of one call, each rounded up to 256 bytes.
+struct SigmaSizes {
+  size_t part, w, rt;
+  size_t total() const { return part + w + rt; }
+};
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+SigmaSizes sigma_sizes(gw_precision prec, int N, int64_t rows, int F) {
+  SigmaSizes z;
+  z.part = round256((size_t)F * 2 * ((N + BM - 1) / BM) * rows * sizeof(double));
+  z.w = round256((size_t)F * rows * sizeof(double));
+  z.rt = prec == GW_FP32 ? round256((size_t)N * rt_ld(rows) * sizeof(float)) : 0;
+  return z;
+}
+
+gw_status sigma_check(gw_ctx ctx, const char* who, gw_precision prec, int n_naf, int n_qp,
+                      int n_mo, const double* eps_mo, const void* R_qp, int64_t ld_R, int n_w,
+                      const double* omega, const double* w_omega, const void* W_hat,
+                      int n_pade, const double* omega_pade, double* sigma_iw) {
   GW_REQUIRE(ctx, prec == GW_FP64 || prec == GW_FP32 || prec == GW_BF16X3,
-             "gw_sigma_diag: unknown precision %d", (int)prec);
+             "%s: unknown precision %d", who, (int)prec);
   GW_REQUIRE(ctx, n_naf >= 1 && n_qp >= 1 && n_mo >= 1 && n_w >= 1 && n_pade >= 1,
-             "gw_sigma_diag: bad sizes");
+             "%s: bad sizes", who);
   GW_REQUIRE(ctx, eps_mo && R_qp && omega && w_omega && W_hat && omega_pade && sigma_iw,
-             "gw_sigma_diag: NULL argument");
-  if (ld_R == 0) ld_R = n_naf;
-  GW_REQUIRE(ctx, ld_R >= n_naf, "gw_sigma_diag: ld_R < n_naf");
-  GW_HIP(ctx, hipSetDevice(ctx->device));
+             "%s: NULL argument", who);
+  GW_REQUIRE(ctx, ld_R == 0 || ld_R >= n_naf, "%s: ld_R < n_naf", who);
+  return GW_OK;
+}
+
+// The contraction, the reduction of its partials and the quadrature, with
+// the call's buffers supplied by the caller of this function.
+gw_status sigma_diag_run(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp, int n_mo,
+                         const double* eps_mo, double eps_F, const void* R_qp, int64_t ld_R,
+                         int n_w, const double* omega, const double* w_omega,
+                         const void* W_hat, int n_pade, const double* omega_pade,
+                         int accumulate, double* sigma_iw, double* W_nm, const SigmaBufs& b) {
   const int N = n_naf, F = n_w;
   const int64_t rows = (int64_t)n_qp * n_mo;
   const double* d_eps = gw::stage_t(ctx, eps_mo, n_mo);
@@ -624,18 +653,11 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
   const int row_tiles = (int)((rows + BM - 1) / BM);
   const int col_tiles = (N + BM - 1) / BM;
   const int n_part = 2 * col_tiles;
-  double* part = static_cast<double*>(
-      gw::ws_get(ctx, WS_SIGMA_PART, (size_t)F * n_part * rows * sizeof(double)));
-  double* W = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_W, (size_t)F * rows * sizeof(double)));
-  if (!part || !W) return GW_ENOMEM;
-  BwbArgs a{R_qp, W_hat, rows, N, ld_R, F, row_tiles, col_tiles, part, nullptr, 0};
+  BwbArgs a{R_qp, W_hat, rows, N, ld_R, F, row_tiles, col_tiles, b.part, nullptr, 0};
   if (prec == GW_FP32) {
-    float* RT = static_cast<float*>(
-        gw::ws_get(ctx, WS_SIGMA_RT, (size_t)N * rt_ld(rows) * sizeof(float)));
-    if (!RT) return GW_ENOMEM;
-    const gw::TransposeJob t = tr_job(R_qp, rows, ld_R, N, RT);
+    const gw::TransposeJob t = tr_job(R_qp, rows, ld_R, N, b.RT);
     GW_TRY(gw::transpose_f32(ctx, {t}));
-    a.RT = RT;
+    a.RT = b.RT;
     a.ldt = t.ld_dst;
   }
   const int64_t grid = (int64_t)F * row_tiles * col_tiles;
@@ -650,12 +672,109 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
   }
   GW_TRY(gw::launch_check(ctx, "bwb kernel"));
   hipLaunchKernelGGL(w_reduce_kernel, dim3(grid_for((int64_t)F * rows, 256)), dim3(256), 0,
-                     ctx->stream, WRedArgs{part, n_part, rows, F, W, W_nm});
+                     ctx->stream, WRedArgs{b.part, n_part, rows, F, b.W, W_nm});
   GW_TRY(gw::launch_check(ctx, "w_reduce_kernel"));
   hipLaunchKernelGGL(sigma_quad_kernel, dim3(n_qp * n_pade), dim3(256), 0, ctx->stream,
-                     QuadArgs{W, F, n_qp, n_mo, d_eps, eps_F, d_om, d_wt, d_op, n_pade,
+                     QuadArgs{b.W, F, n_qp, n_mo, d_eps, eps_F, d_om, d_wt, d_op, n_pade,
                               accumulate, sigma_iw});
   return gw::launch_check(ctx, "sigma_quad_kernel");
+}
+
+// Fixed scratch of gw_sigma_diag_noalloc: one array per GPU, present from
+// the loading of the code object until the process ends.  Host code never
+// passes `scratch` itself (its host-side name is not a device address); it
+// uses the device address looked up once per device by sigma_scratch_init.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+namespace gw {
+
+// Looks up this device's copy of `scratch` (the device must be current).
+// Called by gw_create; repeated calls for a device are no-ops.
+gw_status sigma_scratch_init(gw_ctx ctx, int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(ctx, GW_EUNSUPPORTED, "device index %d beyond the scratch table (%d)", device,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return GW_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return fail(ctx, GW_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                hipGetErrorString(e));
+  }
+  g_scratch_ptr[device] = ptr;
+  return GW_OK;
+}
+
+}  // namespace gw
+
+extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
+                                   int n_mo, const double* eps_mo, double eps_F,
+                                   const void* R_qp, int64_t ld_R, int n_w,
+                                   const double* omega,
+                                   const double* w_omega, const void* W_hat, int n_pade,
+                                   const double* omega_pade, int accumulate,
+                                   double* sigma_iw, double* W_nm) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_sigma_diag: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_TRY(sigma_check(ctx, "gw_sigma_diag", prec, n_naf, n_qp, n_mo, eps_mo, R_qp, ld_R, n_w,
+                     omega, w_omega, W_hat, n_pade, omega_pade, sigma_iw));
+  if (ld_R == 0) ld_R = n_naf;
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  const int64_t rows = (int64_t)n_qp * n_mo;
+  const SigmaSizes z = sigma_sizes(prec, n_naf, rows, n_w);
+  SigmaBufs b{};
+  b.part = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_PART, z.part));
+  b.W = static_cast<double*>(gw::ws_get(ctx, WS_SIGMA_W, z.w));
+  if (!b.part || !b.W) return GW_ENOMEM;
+  if (prec == GW_FP32) {
+    b.RT = static_cast<float*>(gw::ws_get(ctx, WS_SIGMA_RT, z.rt));
+    if (!b.RT) return GW_ENOMEM;
+  }
+  return sigma_diag_run(ctx, prec, n_naf, n_qp, n_mo, eps_mo, eps_F, R_qp, ld_R, n_w, omega,
+                        w_omega, W_hat, n_pade, omega_pade, accumulate, sigma_iw, W_nm, b);
+}
+
+extern "C" gw_status gw_sigma_diag_noalloc(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp,
+                                           int n_mo, const double* eps_mo, double eps_F,
+                                           const void* R_qp, int64_t ld_R, int n_w,
+                                           const double* omega, const double* w_omega,
+                                           const void* W_hat, int n_pade,
+                                           const double* omega_pade, int accumulate,
+                                           double* sigma_iw, double* W_nm) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_sigma_diag_noalloc: ctx is NULL");
+  gw::clear_error(ctx);
+  GW_TRY(sigma_check(ctx, "gw_sigma_diag_noalloc", prec, n_naf, n_qp, n_mo, eps_mo, R_qp, ld_R,
+                     n_w, omega, w_omega, W_hat, n_pade, omega_pade, sigma_iw));
+  if (ld_R == 0) ld_R = n_naf;
+  const int64_t rows = (int64_t)n_qp * n_mo;
+  const SigmaSizes z = sigma_sizes(prec, n_naf, rows, n_w);
+  GW_REQUIRE(ctx, z.total() <= kNoallocScratchBytes,
+             "gw_sigma_diag_noalloc: the call needs %zu bytes of scratch, the fixed buffer holds "
+             "%zu; split the frequencies or the QP states over several calls",
+             z.total(), kNoallocScratchBytes);
+  GW_HIP(ctx, hipSetDevice(ctx->device));
+  GW_TRY(gw::sigma_scratch_init(ctx, ctx->device));   // no-op once looked up
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = g_scratch_ptr[ctx->device];
+  }
+  unsigned char* p = static_cast<unsigned char*>(base);
+  SigmaBufs b{};
+  b.part = reinterpret_cast<double*>(p);
+  b.W = reinterpret_cast<double*>(p + z.part);
+  b.RT = prec == GW_FP32 ? reinterpret_cast<float*>(p + z.part + z.w) : nullptr;
+  return sigma_diag_run(ctx, prec, n_naf, n_qp, n_mo, eps_mo, eps_F, R_qp, ld_R, n_w, omega,
+                        w_omega, W_hat, n_pade, omega_pade, accumulate, sigma_iw, W_nm, b);
 }
 
 extern "C" gw_status gw_sigma_diag_batched(gw_ctx ctx, gw_precision prec, int n_jobs,

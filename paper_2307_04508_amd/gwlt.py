@@ -39,7 +39,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_set_stream", "gw_sync", "gw_last_error
            "gw_polarizability_lt_batched", "gw_screen_batched", "gw_sigma_diag_batched",
            "gw_qp_solve_batched", "gw_g0w0_batched", "gw_reserve", "gw_naf_compress_batched",
            "gw_naf_apply_batched", "gw_autotune", "gw_evgw", "gw_polarizability_sos",
-           "gw_screen_sos", "gw_lt_grid_auto"]
+           "gw_screen_sos", "gw_lt_grid_auto", "gw_sigma_diag_noalloc"]
 
 c_int, c_i64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_DBL = ctypes.POINTER(ctypes.c_double)
@@ -140,6 +140,8 @@ _sig = {
     "gw_screen": [c_vp, c_int, c_int, c_int, P_DBL, c_vp, c_int, P_DBL, c_vp],
     "gw_sigma_diag": [c_vp, c_int, c_int, c_int, c_int, P_DBL, c_dbl, c_vp, c_i64, c_int,
                       P_DBL, P_DBL, c_vp, c_int, P_DBL, c_int, c_vp, c_vp],
+    "gw_sigma_diag_noalloc": [c_vp, c_int, c_int, c_int, c_int, P_DBL, c_dbl, c_vp, c_i64,
+                              c_int, P_DBL, P_DBL, c_vp, c_int, P_DBL, c_int, c_vp, c_vp],
     "gw_qp_solve": [c_vp, c_int, P_DBL, P_DBL, c_dbl, c_int, P_DBL, c_vp, c_dbl, c_dbl, c_int,
                     P_DBL, P_DBL, P_INT],
     "gw_g0w0": [c_vp, c_int, ctypes.POINTER(GwParams), P_DBL, P_INT, P_DBL, c_vp, c_vp, c_vp,
@@ -375,6 +377,15 @@ def gw_sigma_diag(ctx, prec, n_naf, n_qp, n_mo, eps_mo, eps_F, R_qp, omega, w_om
                               _dev(R_qp, True), _ld(R_qp, n_naf), len(om), _dp(om), _dp(wt),
                               _dev(W_hat), len(op), _dp(op), int(accumulate), _dev(sigma_iw),
                               _dev(W_nm)), ctx)
+
+
+def gw_sigma_diag_noalloc(ctx, prec, n_naf, n_qp, n_mo, eps_mo, eps_F, R_qp, omega, w_omega,
+                          W_hat, omega_pade, accumulate, sigma_iw, W_nm=None):
+    e, om, wt, op = _host(eps_mo), _host(omega), _host(w_omega), _host(omega_pade)
+    _check(_lib.gw_sigma_diag_noalloc(ctx.handle, _prec(prec), n_naf, n_qp, n_mo, _dp(e),
+                                      float(eps_F), _dev(R_qp, True), _ld(R_qp, n_naf), len(om),
+                                      _dp(om), _dp(wt), _dev(W_hat), len(op), _dp(op),
+                                      int(accumulate), _dev(sigma_iw), _dev(W_nm)), ctx)
 
 
 def gw_qp_solve(ctx, eps_n, static_n, eps_F, omega_pade, sigma_iw, eta, tol=1e-6,
