@@ -47,6 +47,19 @@ def m_lt(Rt_ov: np.ndarray, d: np.ndarray, x: np.ndarray, w: np.ndarray) -> np.n
     return out
 
 
+def m_lt_columns(Rt_ov: np.ndarray, d: np.ndarray, x: np.ndarray, w: np.ndarray,
+                 cols: np.ndarray) -> np.ndarray:
+    """Eq. 10 restricted to the columns Q in ``cols``: M^m[:, cols] =
+    sum_ia R_ia w_m D_ia exp(-D_ia^2 x_m) R_ia[cols]^T, shape [L][N][len(cols)]
+    (for sizes where the whole M^m is too costly to form on the host)."""
+    cols = np.asarray(cols)
+    out = np.empty((len(x), Rt_ov.shape[1], len(cols)))
+    for m in range(len(x)):
+        f = w[m] * d * np.exp(-d * d * x[m])
+        out[m] = Rt_ov.T @ (f[:, None] * Rt_ov[:, cols])
+    return out
+
+
 def pi_lt(M: np.ndarray, x: np.ndarray, omega: np.ndarray) -> np.ndarray:
     """Eq. 10: Pi(iw_j) ~ -2 s sum_m M^m exp(-w_j^2 x_m)."""
     out = np.empty((len(omega),) + M.shape[1:])

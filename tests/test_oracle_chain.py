@@ -190,6 +190,27 @@ def test_m_lt_brute_force_loop(tiny_problem, tiny_sos, tiny_lt_grid):
         assert np.allclose(M[m], ref, rtol=1e-12, atol=1e-16)
 
 
+def test_m_lt_columns_brute_force_loop(tiny_problem, tiny_sos, tiny_lt_grid):
+    """The column-restricted Laplace matrices against the explicit ia loop."""
+    p = tiny_problem
+    c = p.cfg
+    x, w = tiny_lt_grid[0][:2], tiny_lt_grid[1][:2]
+    Rt = tiny_sos.Rt_ov[:, :20]
+    cols = np.array([0, 7, 19])
+    Mc = rpa.m_lt_columns(Rt, rpa.delta_ov(p.eps, c.n_fc, c.n_occ), x, w, cols)
+    assert Mc.shape == (2, 20, 3)
+    o, v = c.n_act_occ, c.n_virt
+    for m in range(2):
+        ref = np.zeros((20, 3))
+        for i in range(o):
+            for a in range(v):
+                dd = p.eps[c.n_occ + a] - p.eps[c.n_fc + i]
+                f = w[m] * dd * np.exp(-dd * dd * x[m])
+                row = Rt[i * v + a]
+                ref += f * np.outer(row, row[cols])
+        assert np.allclose(Mc[m], ref, rtol=1e-12, atol=1e-16)
+
+
 def test_lt_polarizability_converges_to_sos(tiny_problem, tiny_sos):
     p = tiny_problem
     c = p.cfg
