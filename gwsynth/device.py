@@ -148,11 +148,12 @@ class DeviceProblem:
 
 def make_problem_device(cfg: Config, device="cuda", dtype=None, with_ov: bool = True,
                         block: int = 4096, with_oo: bool = True,
-                        haar_on_device: bool = False) -> DeviceProblem:
+                        haar_on_device: bool = False, with_qp: bool = True) -> DeviceProblem:
     """The problem of ``make_problem(cfg)`` with its tensors generated on
     ``device`` (default dtype float64).  ``with_ov=False`` / ``with_oo=False``
     leave the occupied-virtual / occupied-occupied blocks to be streamed with
-    ``DeviceProblem.ov_chunk`` / ``oo_chunk``."""
+    ``DeviceProblem.ov_chunk`` / ``oo_chunk``; ``with_qp=False`` skips the
+    QP rows (R_qp is then None)."""
     import torch
     dtype = torch.float64 if dtype is None else dtype
     rng = np.random.default_rng(cfg.seed)
@@ -176,7 +177,9 @@ def make_problem_device(cfg: Config, device="cuda", dtype=None, with_ov: bool = 
     if with_ov:
         vi, va = np.meshgrid(occ, virt, indexing="ij")
         R_ov = src.rows(vi.ravel(), va.ravel(), dtype, block)
-    qn, qm = np.meshgrid(qp, act, indexing="ij")
-    R_qp = src.rows(qn.ravel(), qm.ravel(), dtype, block).reshape(qp.size, M, A)
+    R_qp = None
+    if with_qp:
+        qn, qm = np.meshgrid(qp, act, indexing="ij")
+        R_qp = src.rows(qn.ravel(), qm.ravel(), dtype, block).reshape(qp.size, M, A)
     return DeviceProblem(cfg=cfg, eps=eps, qp=qp, R_oo=R_oo, R_ov=R_ov, R_qp=R_qp,
                          c_scale=src.c, src=src)

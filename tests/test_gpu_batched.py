@@ -14,6 +14,7 @@ import sys
 import numpy as np
 import pytest
 
+from bounds import assert_quadform_close
 from conftest import HARTREE_MEV
 
 pytestmark = pytest.mark.gpu
@@ -155,7 +156,7 @@ def test_screen_batched_reports_non_spd(gw, ctx):
 def test_sigma_batched_matches_oracle(gw, ctx, prec, tol):
     _say(f"sigma batched {prec}")
     shapes = [(3, 70, 333, 2), (2, 45, 128, 3), (1, 200, 257, 1), (2, 9, 64, 2)]
-    jobs, refs, outs = [], [], []
+    jobs, refs, outs, inputs = [], [], [], []
     for s, (Q, Mo, N, F) in enumerate(shapes):
         rng = np.random.default_rng(200 + s)
         R = rng.standard_normal((Q, Mo, N)) / np.sqrt(N)
@@ -168,6 +169,7 @@ def test_sigma_batched_matches_oracle(gw, ctx, prec, tol):
         W_ref = rpa.w_diag(R, What)
         S_ref = sigma.sigma_iw(W_ref, eps_m, eF, om, wom, op)
         refs.append((W_ref, S_ref))
+        inputs.append((R, What))
         sig = torch.zeros((Q, len(op), 2), dtype=torch.float64, device="cuda")
         Wnm = torch.zeros((F, Q, Mo), dtype=torch.float64, device="cuda")
         outs.append((sig, Wnm))
@@ -177,7 +179,9 @@ def test_sigma_batched_matches_oracle(gw, ctx, prec, tol):
     gw.gw_sigma_diag_batched(ctx, prec, jobs, 0)
     gw.gw_sync(ctx)
     for s, ((W_ref, S_ref), (sig, Wnm)) in enumerate(zip(refs, outs)):
-        assert rel_fro(Wnm.cpu().numpy(), W_ref) < tol, s
+        R, What = inputs[s]
+        assert_quadform_close(Wnm.cpu().numpy(), W_ref, R.reshape(-1, R.shape[-1]), What, prec,
+                              rounded_inputs=prec != "fp64")
         sh = sig.cpu().numpy()
         S = sh[..., 0] + 1j * sh[..., 1]
         assert np.max(np.abs(S - S_ref)) < 10 * tol * np.max(np.abs(S_ref)), s
