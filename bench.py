@@ -5,15 +5,17 @@ One step = one whole G0W0 evaluation through the C ABI (gw_g0w0): NAF
 compression of the raw RI tensors, grids, Laplace-transformed
 polarizability, screening, diagonal self-energy, Pade continuation and the
 QP solve, with the seeded synthetic inputs already resident in HBM.  The
-default workload is the ~1000-basis-function configuration (n_occ = 100 with
-30 frozen, n_virt = 900, n_aux = 3000 -> ~1500 NAFs, 10 Laplace points,
-60 frequencies, 10 QP states) in FP32.
+default workload is the ~2500-basis-function configuration (n_occ = 300
+with 80 frozen, n_virt = 2200, n_aux = 7000 -> ~3500 NAFs, 12 Laplace
+points, 80 frequencies, 20 QP states) in FP32, generated on the device.
 
 Prints one JSON line: G0W0 wall time per step (value), the live
 HIP-event roofline of the dominant kernel (the polarizability SYRK), the
-self-energy contraction's rate, the FP64 path's wall time for comparison,
-the QP errors against the stored FP64 oracle values, and the oracle's CPU
-time on a bounded sample.
+self-energy contraction's rate, the FP64 and BF16x3 paths' wall times for
+comparison, the QP errors against the stored FP64 oracle values, the
+oracle's CPU time on a bounded sample and, under "paper_scale", one
+streamed step of the ~7400-basis-function workload (FP32) when the time
+budget allows it.
 """
 from __future__ import annotations
 
@@ -68,37 +70,79 @@ def measured_traffic(kernel, workload):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(prob, n_freq_sample=24):
-    """Oracle (FP64 NumPy) on a bounded sample (about 10 s on 16 cores): the
-    NAF stage once and the per-frequency work (sum-over-states Pi, dense
-    inverse, W_nm) for `n_freq_sample` of the F frequencies, evenly spread
-    over the grid, extrapolated to the full step."""
+def cpu_baseline(prob, torch, n_freq_sample=2, row_frac=0.2, qp_sample=1):
+    """Oracle (FP64 NumPy) on a bounded sample of the step (10-30 s on the
+    box's host cores), extrapolated to the whole step; no Laplace transform.
+    Sample: the NAF metric of the rows of the first ~20% of the occupied
+    orbitals (the metric is a sum over rows), the full A x A
+    eigendecomposition, the transformation of those rows and of one QP
+    state's rows, and per frequency the sum-over-states Pi of those rows, the
+    dense inverse of 1 - Pi and W_nm of one QP state, at `n_freq_sample`
+    frequencies; each part is scaled by the fraction of rows, states and
+    frequencies it covered."""
     from threadpoolctl import threadpool_info
     from oracle import grids, naf, rpa
     c = prob.cfg
-    R_oo = prob.R_oo.astype(np.float64)
-    R_ov = prob.R_ov.astype(np.float64)
-    R_qp = prob.R_qp.astype(np.float64)
+    o, v, A = c.n_act_occ, c.n_virt, c.n_aux
+    ci = max(1, int(round(o * row_frac)))
+    host = lambda t: t.double().cpu().numpy() if hasattr(t, "cpu") else np.asarray(t, np.float64)  # noqa: E731
+    R_oo = host(prob.R_oo[:ci])
+    R_ov = host(prob.R_ov[:ci * v])
+    R_qp = host(prob.R_qp[:qp_sample])
+    timing = {}
     t0 = time.perf_counter()
     K = naf.naf_metric(R_oo, R_ov)
-    _, U = naf.naf_basis(K, c.eps_naf, c.max_keep)
-    Rt_ov = naf.naf_transform(R_ov, U)
-    Rt_qp = naf.naf_transform(R_qp, U)
-    t_naf = time.perf_counter() - t0
-    om, _ = grids.modified_gauss_legendre(c.n_freq, c.x0)
-    sel = om[np.unique(np.linspace(0, len(om) - 1, min(n_freq_sample, len(om))).astype(int))]
-    d = rpa.delta_ov(prob.eps, c.n_fc, c.n_occ)
+    timing["metric"] = (time.perf_counter() - t0) * o / ci
     t0 = time.perf_counter()
-    W = rpa.w_diag(Rt_qp, rpa.screen(rpa.pi_sos(Rt_ov, d, sel)))
-    t_freq = time.perf_counter() - t0
+    _, U = naf.naf_basis(K, c.eps_naf, c.max_keep)
+    timing["eigh"] = time.perf_counter() - t0
+    del K
+    t0 = time.perf_counter()
+    Rt_ov = naf.naf_transform(R_ov, U)
+    t_ov = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Rt_qp = naf.naf_transform(R_qp, U)
+    timing["transform"] = t_ov * o / ci + (time.perf_counter() - t0) * c.n_qp / qp_sample
+    om, _ = grids.modified_gauss_legendre(c.n_freq, c.x0)
+    sel = om[np.unique(np.linspace(0, len(om) - 1, n_freq_sample).astype(int))]
+    d = rpa.delta_ov(prob.eps, c.n_fc, c.n_occ)[:ci * v]
+    t0 = time.perf_counter()
+    Pi = rpa.pi_sos(Rt_ov, d, sel)
+    t_pi = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    What = rpa.screen(Pi)
+    t_inv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    W = rpa.w_diag(Rt_qp, What)
+    t_w = time.perf_counter() - t0
     assert np.all(np.isfinite(W))
+    scale_f = c.n_freq / len(sel)
+    timing["pi_sos"] = t_pi * o / ci * scale_f
+    timing["inverse"] = t_inv * scale_f
+    timing["w_nm"] = t_w * c.n_qp / qp_sample * scale_f
+    measured = (timing["metric"] * ci / o + timing["eigh"] + t_ov +
+                (timing["transform"] - t_ov * o / ci) * qp_sample / c.n_qp + t_pi + t_inv + t_w)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    total = t_naf + t_freq * c.n_freq / len(sel)
-    return {"value": total, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"NAF once ({t_naf:.1f} s) + sum-over-states Pi, inverse and W_nm for "
-                       f"{len(sel)} of {c.n_freq} frequencies ({t_freq:.1f} s), extrapolated "
-                       f"linearly to {c.n_freq}; no Laplace transform"),
-            "measured_s": t_naf + t_freq}
+    return {"value": round(sum(timing.values()), 3), "unit": "s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"rows of occupied orbitals 0..{ci - 1} of {o} ({ci * (o + v)} of "
+                       f"{o * (o + v)} metric rows), the full {A} x {A} eigendecomposition, "
+                       f"{qp_sample} of {c.n_qp} QP states, {len(sel)} of {c.n_freq} "
+                       f"frequencies; each part scaled by the fraction it covered; sum over "
+                       f"states (no Laplace transform)"),
+            "measured_s": round(measured, 3),
+            "parts_s": {k: round(val, 3) for k, val in timing.items()},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def run_streamed(args, cfg, gw, torch):
@@ -251,8 +295,10 @@ def run_streamed(args, cfg, gw, torch):
             "generation_s": round(gen_s, 1), "lt_err_norm": lt_err, "autotune": False,
             "paths": res,
             "eps_qp": {q: out[q][0].tolist() for q in precs}}
-    print(json.dumps(line), flush=True)
     ctx.close()
+    del p, M, Rt_qps
+    torch.cuda.empty_cache()
+    return line
 
 
 def run_grid_sweep(args, cfg, gw, torch):
@@ -376,7 +422,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="medium")
+    ap.add_argument("--config", default="large")
+    ap.add_argument("--paper-key", type=int, default=1,
+                    help="append one streamed paper-scale FP32 step under 'paper_scale' "
+                         "(skipped when --time-limit-s would be exceeded; 0 = off)")
+    ap.add_argument("--paper-budget-s", type=float, default=330.0,
+                    help="time the paper-scale key is allowed for (generation included)")
+    ap.add_argument("--time-limit-s", type=float, default=560.0,
+                    help="whole-run limit the paper-scale key must fit in")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=1,
                     help="steps of the FP64 path timed for comparison (0 = skip)")
@@ -419,7 +472,10 @@ def main():
 
     cfg = get_config(args.config)
     if args.streamed:
-        run_streamed(args, cfg, gw, torch)
+        t0 = time.perf_counter()
+        line = run_streamed(args, cfg, gw, torch)
+        line["wall_s"] = round(time.perf_counter() - t0, 1)
+        print(json.dumps(line), flush=True)
         return
     if args.grid_sweep:
         run_grid_sweep(args, cfg, gw, torch)
@@ -427,14 +483,24 @@ def main():
     if args.batched:
         run_batched(args, gw, torch)
         return
+    t_start = time.perf_counter()
     t0 = time.perf_counter()
-    prob = make_problem(cfg, dtype=np.float32)
-    log(f"generated {cfg.name} inputs in {time.perf_counter() - t0:.1f} s")
+    if cfg.exact_orthonormal:
+        import types
+        hp = make_problem(cfg)
+        prob = types.SimpleNamespace(cfg=cfg, eps=hp.eps, qp=hp.qp,
+                                     **{k: torch.as_tensor(getattr(hp, k)).cuda()
+                                        for k in ("R_oo", "R_ov", "R_qp")})
+    else:
+        from gwsynth.device import make_problem_device
+        prob = make_problem_device(cfg, device="cuda", dtype=torch.float64,
+                                   haar_on_device=cfg.n_aux > 4000)
+    torch.cuda.synchronize()
+    log(f"generated {cfg.name} inputs on the device in {time.perf_counter() - t0:.1f} s")
     dt = torch.float32 if args.prec == "fp32" else torch.float64
 
     def upload(dtype):
-        return [torch.as_tensor(a).to(device="cuda", dtype=dtype).contiguous()
-                for a in (prob.R_oo, prob.R_ov, prob.R_qp)]
+        return [t.to(dtype=dtype).contiguous() for t in (prob.R_oo, prob.R_ov, prob.R_qp)]
 
     R = upload(dt)
     ctx = gw.Context(0)
@@ -451,6 +517,8 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         E, Z, S, sig, st = step(args.prec, R)
+        if (k + 1) % 5 == 0 and k + 1 < args.steps:
+            log(f"timed step {k + 1}/{args.steps}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = (t1 - t0) / args.steps
@@ -487,6 +555,8 @@ def main():
         wb = (time.perf_counter() - t0) / args.bf16x3_steps
         chib = kernel_rate(gw, ctx, "chi_syrk_bf16x3")
         bwbb = kernel_rate(gw, ctx, "bwb_bf16x3")
+        splits = {k: kernel_rate(gw, ctx, n) for k, n in (("chi", "chi_split_bf16x3"),
+                                                           ("sigma_contraction", "bwb_split_bf16x3"))}
         gw.gw_profile_enable(ctx, False)
         bf16 = {"wall_s": wb, "qp_diff_vs_fp32_meV": float(np.max(np.abs(Eb - E)) * HARTREE_MEV),
                 "status": Sb.tolist()}
@@ -496,6 +566,17 @@ def main():
                              "tflops_algorithmic": round(kr["tflops"], 3),
                              "frac_of_bf16_peak_executed": round(3 * kr["tflops"] / 2500.0, 4),
                              "frac_of_fp32_peak": round(kr["tflops"] / 157.3, 4)}
+                sp = splits[key]
+                if sp:
+                    # the one-off split of the operands into BF16 hi / lo pairs
+                    # (HBM-bound), per step, and the rate with it included
+                    per_step = sp["avg_ms"] * sp["launches"] / args.bf16x3_steps
+                    mm = kr["avg_ms"] * kr["launches"] / args.bf16x3_steps
+                    bf16[key]["split_ms_per_step"] = round(per_step, 4)
+                    bf16[key]["split_gbs"] = round(sp["gbs"], 1)
+                    bf16[key]["tflops_algorithmic_with_split"] = round(
+                        kr["flops_per_launch"] * kr["launches"] / args.bf16x3_steps /
+                        ((mm + per_step) * 1e-3) / 1e12, 3)
         log(f"bf16x3 path: {wb * 1e3:.1f} ms/step")
 
     evgw = None
@@ -538,8 +619,6 @@ def main():
 
     fp64 = None
     if args.fp64_steps > 0 and args.prec != "fp64":
-        del R
-        torch.cuda.empty_cache()
         R64 = upload(torch.float64)
         step("fp64", R64)
         torch.cuda.synchronize()
@@ -578,8 +657,27 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
-        cpu = cpu_baseline(prob)
+        cpu = cpu_baseline(prob, torch)
         log(f"oracle: {cpu['measured_s']:.1f} s measured, {cpu['value']:.1f} s extrapolated")
+
+    paper = None
+    if args.paper_key and cfg.name != "paper":
+        elapsed = time.perf_counter() - t_start
+        if elapsed + args.paper_budget_s <= args.time_limit_s:
+            del R, prob
+            ctx.close()
+            ctx = None
+            torch.cuda.empty_cache()
+            log(f"one streamed paper-scale FP32 step ({elapsed:.0f} s elapsed)")
+            t0 = time.perf_counter()
+            pargs = argparse.Namespace(**{**vars(args), "precs": "fp32"})
+            paper = run_streamed(pargs, get_config("paper"), gw, torch)
+            paper["wall_s"] = round(time.perf_counter() - t0, 1)
+            log(f"paper scale: {paper['paths']['fp32']['total_s']:.1f} s of stages, "
+                f"{paper['wall_s']:.0f} s with generation")
+        else:
+            paper = {"skipped": f"time budget: {elapsed:.0f} s elapsed + {args.paper_budget_s} s "
+                                f"needed > {args.time_limit_s} s"}
 
     line = {
         "metric": "G0W0 wall s + chi/Sigma TFLOP/s (% MFMA peak), FP32/BF16x3 vs FP64, "
@@ -608,9 +706,11 @@ def main():
         "no_laplace": no_lt,
         "qp_err": qp_err,
         "cpu_baseline": cpu,
+        "paper_scale": paper,
     }
     print(json.dumps(line), flush=True)
-    ctx.close()
+    if ctx is not None:
+        ctx.close()
 
 
 if __name__ == "__main__":

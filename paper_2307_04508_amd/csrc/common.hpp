@@ -46,6 +46,9 @@ enum WsSlot {
   WS_EIG_Y,         // eigenvectors of the tridiagonal matrix
   WS_NAF_T,         // k-major FP32 copies of the NAF transform's operands
   WS_EIG_BACK,      // block-reflector factors and products of the back-transformation
+  WS_B3_CHI,        // BF16x3 polarizability: split scaled rows (hi, lo) of a chunk
+  WS_B3_R,          // BF16x3 contraction: split QP rows (hi, lo)
+  WS_B3_W,          // BF16x3 contraction: split screened interactions (hi, lo)
   WS_COUNT
 };
 

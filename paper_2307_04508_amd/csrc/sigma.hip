@@ -17,6 +17,7 @@
 #include <cmath>
 #include <mutex>
 
+#include "bf16x3.hpp"
 #include "common.hpp"
 
 namespace {
@@ -176,6 +177,128 @@ __global__ __launch_bounds__(NTD, 4) void bwb_f32_direct_kernel(BwbArgs a0, Batc
     }
     sum = half_wave_sum(sum);
     if ((lane & 31) == 31 && row < a.rows) part[row] = sum;
+  }
+}
+
+// ------------------------------------------------------- BF16x3, pre-split
+// Both operands split once per call into workspace (bf16x3.hpp): the QP rows
+// as [rows_pad][Npad] and each W^_j as [Npad][Npad] (hi and lo, zero
+// padded).  W^_j is symmetric, so row c of W^_j is column c contiguous along
+// k, and both tiles are copied global -> LDS directly.  The symmetric
+// weighting (1 for the diagonal block, 2 below it) scales the accumulators:
+// after the diagonal block they are halved, at the end doubled (exact).
+struct Split3Args {
+  const float* src;     // [batch][rows][ld] with batch stride sstride
+  int64_t rows, ld, sstride;
+  int cols;
+  __bf16* hi;           // [batch][rows_pad][cols_pad]
+  __bf16* lo;
+  int64_t rows_pad, cols_pad;
+  int batch;
+};
+
+__global__ __launch_bounds__(256) void split3_kernel(Split3Args a) {
+  const int64_t per = a.rows_pad * a.cols_pad;
+  const int64_t total = per * a.batch;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / per, e = i % per;
+    const int64_t r = e / a.cols_pad;
+    const int c = (int)(e % a.cols_pad);
+    const float v = (r < a.rows && c < a.cols) ? a.src[b * a.sstride + r * a.ld + c] : 0.f;
+    __bf16 h, l;
+    b3::split(v, h, l);
+    a.hi[i] = h;
+    a.lo[i] = l;
+  }
+}
+
+struct Bwb3Args {
+  const __bf16* rh;     // [rows_pad][Npad]
+  const __bf16* rl;
+  const __bf16* wh;     // [F][Npad][Npad]
+  const __bf16* wl;
+  const float* R;       // FP32 rows for the row-dot epilogue, [rows][ldr]
+  int64_t ldr;
+  int64_t rows;
+  int N, Npad, F, row_tiles, col_tiles;
+  double* part;         // [F][2 * col_tiles][rows]
+};
+
+__global__ __launch_bounds__(b3::NT, 2) void bwb_bf16x3_direct_kernel(Bwb3Args a) {
+  __shared__ __attribute__((aligned(16))) b3::Stage st[2];
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int rt = (int)(lid % a.row_tiles);
+  const int ct = (int)((lid / a.row_tiles) % a.col_tiles);
+  const int j = (int)(lid / ((int64_t)a.row_tiles * a.col_tiles));
+  const int64_t row0 = (int64_t)rt * BM;
+  const int col0 = ct * BM;
+  const __bf16* wh = a.wh + (int64_t)j * a.Npad * a.Npad;
+  const __bf16* wl = a.wl + (int64_t)j * a.Npad * a.Npad;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][jj][r] = 0.f;
+
+  auto issue = [&](int64_t kb, int buf) {
+    b3::load_tile(a.rh, a.Npad, row0, kb, st[buf].t[0], wave, lane);
+    b3::load_tile(a.rl, a.Npad, row0, kb, st[buf].t[1], wave, lane);
+    b3::load_tile(wh, a.Npad, col0, kb, st[buf].t[2], wave, lane);
+    b3::load_tile(wl, a.Npad, col0, kb, st[buf].t[3], wave, lane);
+  };
+  auto publish = [&]() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+  const int kstart = col0;
+  const int nk = (a.Npad - kstart) / b3::BK;
+  constexpr int DIAG_STAGES = BM / b3::BK;
+  issue(kstart, 0);
+  publish();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) issue(kstart + (int64_t)(it + 1) * b3::BK, cur ^ 1);
+    b3::stage_mfma(st[cur], acc, wy, wx, lane);
+    if (it + 1 == DIAG_STAGES && nk > DIAG_STAGES) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 0.5f;
+    }
+    publish();
+  }
+  if (nk > DIAG_STAGES) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 2.0f;
+  }
+
+  // epilogue: per-row dot product with R over this wave's 64 columns
+  double* part = a.part + ((int64_t)j * 2 * a.col_tiles + 2 * ct + wx) * a.rows;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = row0 + wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      double sum = 0.0;
+      if (row < a.rows) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int col = col0 + wx * 64 + jj * 32 + (lane & 31);
+          if (col < a.N) sum += (double)acc[i][jj][r] * (double)a.R[row * a.ldr + col];
+        }
+      }
+      // lanes 0-31 and 32-63 hold different rows: sum within each half
+      sum = half_wave_sum(sum);
+      if ((lane & 31) == 31 && row < a.rows) part[row] = sum;
+    }
   }
 }
 
@@ -604,21 +727,27 @@ struct SigmaBufs {
   double* part;   // [F][2 * col_tiles][rows]
   double* W;      // [F][rows]
   float* RT;      // [N][rt_ld(rows)], FP32 path only
+  __bf16* R3;     // BF16x3 path: split QP rows, hi then lo [rows_pad][Npad]
+  __bf16* W3;     // BF16x3 path: split W^, hi then lo [F][Npad][Npad]
 };
 
 // Bytes of each buffer of one call, each rounded up to 256 bytes.
 struct SigmaSizes {
-  size_t part, w, rt;
-  size_t total() const { return part + w + rt; }
+  size_t part, w, rt, r3, w3;
+  size_t total() const { return part + w + rt + r3 + w3; }
 };
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+inline int64_t pad128(int64_t n) { return (n + BM - 1) / BM * BM; }
 
 SigmaSizes sigma_sizes(gw_precision prec, int N, int64_t rows, int F) {
   SigmaSizes z;
   z.part = round256((size_t)F * 2 * ((N + BM - 1) / BM) * rows * sizeof(double));
   z.w = round256((size_t)F * rows * sizeof(double));
   z.rt = prec == GW_FP32 ? round256((size_t)N * rt_ld(rows) * sizeof(float)) : 0;
+  z.r3 = prec == GW_BF16X3 ? round256((size_t)2 * pad128(rows) * pad128(N) * sizeof(__bf16)) : 0;
+  z.w3 = prec == GW_BF16X3 ? round256((size_t)2 * F * pad128(N) * pad128(N) * sizeof(__bf16)) : 0;
   return z;
 }
 
@@ -661,6 +790,32 @@ gw_status sigma_diag_run(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp, int
     a.ldt = t.ld_dst;
   }
   const int64_t grid = (int64_t)F * row_tiles * col_tiles;
+  if (prec == GW_BF16X3) {
+    // split both operands once, then the direct BF16x3 contraction
+    const int64_t rp = pad128(rows), np = pad128(N);
+    const Split3Args sr{static_cast<const float*>(R_qp), rows, ld_R, 0, N, b.R3,
+                        b.R3 + rp * np, rp, np, 1};
+    const Split3Args sw{static_cast<const float*>(W_hat), N, N, (int64_t)N * N, N, b.W3,
+                        b.W3 + (int64_t)F * np * np, np, np, F};
+    const int ps = gw::prof_begin(ctx);
+    hipLaunchKernelGGL(split3_kernel, dim3(grid_for(rp * np, 256)), dim3(256), 0, ctx->stream,
+                       sr);
+    hipLaunchKernelGGL(split3_kernel, dim3(grid_for((int64_t)F * np * np, 256)), dim3(256), 0,
+                       ctx->stream, sw);
+    gw::prof_end(ctx, ps, "bwb_split_bf16x3", 0.0,
+                 4.0 * ((double)rows * N + (double)F * N * N) +
+                     4.0 * ((double)rp * np + (double)F * np * np));
+    GW_TRY(gw::launch_check(ctx, "split3_kernel"));
+    const Bwb3Args a3{b.R3, b.R3 + rp * np, b.W3, b.W3 + (int64_t)F * np * np,
+                      static_cast<const float*>(R_qp), ld_R, rows, N, (int)np, F, row_tiles,
+                      col_tiles, b.part};
+    const int pi = gw::prof_begin(ctx);
+    hipLaunchKernelGGL(bwb_bf16x3_direct_kernel, dim3((unsigned)grid), dim3(b3::NT), 0,
+                       ctx->stream, a3);
+    gw::prof_end(ctx, pi, "bwb_bf16x3", (double)F * (double)rows * N * (N + 1.0),
+                 4.0 * ((double)rp * np + (double)F * np * np));
+    GW_TRY(gw::launch_check(ctx, "bwb_bf16x3_direct_kernel"));
+  } else {
   const int pi = gw::prof_begin(ctx);
   launch_bwb(ctx, prec, a, Batch{}, grid, w_rows_aligned(W_hat, N));
   {
@@ -671,6 +826,7 @@ gw_status sigma_diag_run(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp, int
                  (double)rows * N * esz + (double)F * N * (double)N * esz);
   }
   GW_TRY(gw::launch_check(ctx, "bwb kernel"));
+  }
   hipLaunchKernelGGL(w_reduce_kernel, dim3(grid_for((int64_t)F * rows, 256)), dim3(256), 0,
                      ctx->stream, WRedArgs{b.part, n_part, rows, F, b.W, W_nm});
   GW_TRY(gw::launch_check(ctx, "w_reduce_kernel"));
@@ -739,6 +895,11 @@ extern "C" gw_status gw_sigma_diag(gw_ctx ctx, gw_precision prec, int n_naf, int
     b.RT = static_cast<float*>(gw::ws_get(ctx, WS_SIGMA_RT, z.rt));
     if (!b.RT) return GW_ENOMEM;
   }
+  if (prec == GW_BF16X3) {
+    b.R3 = static_cast<__bf16*>(gw::ws_get(ctx, WS_B3_R, z.r3));
+    b.W3 = static_cast<__bf16*>(gw::ws_get(ctx, WS_B3_W, z.w3));
+    if (!b.R3 || !b.W3) return GW_ENOMEM;
+  }
   return sigma_diag_run(ctx, prec, n_naf, n_qp, n_mo, eps_mo, eps_F, R_qp, ld_R, n_w, omega,
                         w_omega, W_hat, n_pade, omega_pade, accumulate, sigma_iw, W_nm, b);
 }
@@ -773,6 +934,8 @@ extern "C" gw_status gw_sigma_diag_noalloc(gw_ctx ctx, gw_precision prec, int n_
   b.part = reinterpret_cast<double*>(p);
   b.W = reinterpret_cast<double*>(p + z.part);
   b.RT = prec == GW_FP32 ? reinterpret_cast<float*>(p + z.part + z.w) : nullptr;
+  b.R3 = prec == GW_BF16X3 ? reinterpret_cast<__bf16*>(p + z.part + z.w + z.rt) : nullptr;
+  b.W3 = prec == GW_BF16X3 ? reinterpret_cast<__bf16*>(p + z.part + z.w + z.rt + z.r3) : nullptr;
   return sigma_diag_run(ctx, prec, n_naf, n_qp, n_mo, eps_mo, eps_F, R_qp, ld_R, n_w, omega,
                         w_omega, W_hat, n_pade, omega_pade, accumulate, sigma_iw, W_nm, b);
 }

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <string>
 
+#include "bf16x3.hpp"
 #include "common.hpp"
 
 namespace {
@@ -478,6 +479,168 @@ __global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a0, Batch 
       }
 }
 
+// ------------------------------------------------------- BF16x3, pre-split
+// The scaled rows are split once per call into workspace: Y_m[P][r] =
+// sqrt(s_m(r)) X[r][P] as BF16 hi and lo, transposed so k (the row r of X)
+// is contiguous; then M^m = Y_m Y_m^T is a plain BF16x3 SYRK over tiles
+// copied global -> LDS directly (bf16x3.hpp).  The square root splits the
+// positive scale evenly over both operands.
+struct ChiSplitArgs {
+  const float* X;       // rows r_base .. r_base + k_rows - 1 of [k_total][ld]
+  int64_t ld;
+  int64_t k_rows;       // rows of this chunk
+  int N;
+  int L;
+  const float* scale;   // [L][k_total] or nullptr (constant cscale)
+  float cscale;
+  int64_t k_total;
+  int64_t r_base;
+  __bf16* hi;           // [L][Npad][kp]
+  __bf16* lo;
+  int64_t kp;           // k stride of Y (rows of the chunk rounded up to BK)
+  int Npad;
+};
+
+// 64 rows x 64 columns of X per workgroup, read once, written for every m.
+__global__ __launch_bounds__(256) void chi_split_kernel(ChiSplitArgs a) {
+  __shared__ float tile[64][65];
+  __shared__ float sq[32][64];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int p0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int y = ty; y < 64; y += 4) {
+    const int64_t r = r0 + y;
+    const int P = p0 + tx;
+    tile[y][tx] = (r < a.k_rows && P < a.N) ? a.X[(a.r_base + r) * a.ld + P] : 0.f;
+  }
+  const int64_t mstride = (int64_t)a.Npad * a.kp;
+  // the square-rooted scales of 32 points at a time
+  for (int m0 = 0; m0 < a.L; m0 += 32) {
+    const int nm = min(32, a.L - m0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nm * 64; idx += 256) {
+      const int m = idx >> 6, y = idx & 63;
+      const int64_t r = r0 + y;
+      float v = 0.f;
+      if (r < a.k_rows)
+        v = a.scale ? a.scale[(int64_t)(m0 + m) * a.k_total + a.r_base + r] : a.cscale;
+      sq[m][y] = sqrtf(v);
+    }
+    __syncthreads();
+    for (int m = 0; m < nm; ++m) {
+      for (int y = ty; y < 64; y += 4) {
+        const int P = p0 + y;
+        const int64_t r = r0 + tx;
+        if (r >= a.kp) continue;
+        __bf16 h, l;
+        b3::split(tile[tx][y] * sq[m][tx], h, l);
+        const int64_t o = (m0 + m) * mstride + (int64_t)P * a.kp + r;
+        a.hi[o] = h;
+        a.lo[o] = l;
+      }
+    }
+  }
+}
+
+struct Syrk3Args {
+  const __bf16* hi;     // [L][Npad][kp]
+  const __bf16* lo;
+  int64_t kp;
+  int Npad;
+  int L, n_tiles, splits;
+  int64_t rows_per_split;   // multiple of FLUSH_ROWS
+  double* part;         // [splits][L][n_tiles][BM*BM]
+};
+
+// Work units: tile fastest, then Laplace point, then split-K slice, so the
+// tiles that read one slice of one Y_m run together on one XCD.
+// Accumulation is blocked: the MFMA accumulators sum FLUSH_ROWS rows, then
+// are added into a second FP32 sum per element, so an entry's rounding
+// error is bounded by gamma(FLUSH_ROWS + blocks) (blocked summation) while a
+// wave holds ~130 registers.  NBUF stages of LDS: with two, two workgroups
+// share a CU; with three, one workgroup per CU keeps the copies of stage
+// it + 2 in flight while stage it is multiplied.  Stage hand-over: wait for
+// this wave's copies of the next stage (those of later stages may stay in
+// flight), then a plain s_barrier (a __syncthreads() would also wait for
+// every copy still in flight).
+template <int NBUF>
+__global__ __launch_bounds__(b3::NT, NBUF == 2 ? 2 : 1) void syrk_bf16x3_direct_kernel(
+    Syrk3Args a) {
+  __shared__ __attribute__((aligned(16))) b3::Stage st[NBUF];
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int t = (int)(lid % a.n_tiles);
+  const int m = (int)((lid / a.n_tiles) % a.L);
+  const int s = (int)(lid / ((int64_t)a.n_tiles * a.L));
+  int ti, tj;
+  tile_coords(t, ti, tj);
+  const int64_t p0 = (int64_t)ti * BM, q0 = (int64_t)tj * BM;
+  const int64_t r0 = (int64_t)s * a.rows_per_split;
+  const int64_t r1 = min(r0 + a.rows_per_split, a.kp);
+  const int nk = r1 > r0 ? (int)((r1 - r0) / b3::BK) : 0;
+  const int64_t mo = (int64_t)m * a.Npad * a.kp;
+  const __bf16* hi = a.hi + mo;
+  const __bf16* lo = a.lo + mo;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+
+  f32x16 acc[2][2], sum[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { acc[i][j][r] = 0.f; sum[i][j][r] = 0.f; }
+
+  // 8 global -> LDS copies per wave per stage (four tiles, two each)
+  auto issue = [&](int it) {
+    const int64_t kb = r0 + (int64_t)it * b3::BK;
+    b3::Stage& d = st[it % NBUF];
+    b3::load_tile(hi, a.kp, p0, kb, d.t[0], wave, lane);
+    b3::load_tile(lo, a.kp, p0, kb, d.t[1], wave, lane);
+    b3::load_tile(hi, a.kp, q0, kb, d.t[2], wave, lane);
+    b3::load_tile(lo, a.kp, q0, kb, d.t[3], wave, lane);
+  };
+  auto handover = [&](int it) {   // after stage it: stage it + 1 visible to all waves
+    // (lgkmcnt(0): this wave's LDS reads of the stage about to be refilled
+    // have completed before any wave passes the barrier)
+    if (NBUF == 3 && it + 2 < nk)
+      asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  };
+  constexpr int FLUSH_STAGES = FLUSH_ROWS / b3::BK;
+  for (int it = 0; it < NBUF - 1 && it < nk; ++it) issue(it);
+  handover(-1);
+  for (int blk = 0; blk < nk; blk += FLUSH_STAGES) {
+    const int end = min(blk + FLUSH_STAGES, nk);
+    for (int it = blk; it < end; ++it) {
+      if (it + NBUF - 1 < nk) issue(it + NBUF - 1);
+      b3::stage_mfma(st[it % NBUF], acc, wy, wx, lane);
+      handover(it);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        sum[i][j] += acc[i][j];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+      }
+  }
+
+  double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = wx * 64 + j * 32 + (lane & 31);
+        out[row * BM + col] = (double)sum[i][j][r];
+      }
+}
+
 // ------------------------------------------------------------------ FP64 MFMA
 constexpr int BK64 = 16;
 
@@ -756,9 +919,93 @@ static bool fast_rows(gw_precision prec, const void* X, int64_t ld) {
          (reinterpret_cast<uintptr_t>(X) % 16 == 0);
 }
 
+// Bytes of split rows one chunk of the BF16x3 path may hold (hi + lo of all
+// Laplace points); longer row ranges are processed in chunks.
+constexpr size_t kSplitChunkBytes = size_t(16) << 30;
+
+static int64_t split_chunk_rows(int64_t k_rows, int Npad, int L) {
+  const int64_t per_row = (int64_t)L * Npad * 2 * (int64_t)sizeof(__bf16);
+  int64_t kc = (int64_t)(kSplitChunkBytes / per_row) / FLUSH_ROWS * FLUSH_ROWS;
+  kc = std::max<int64_t>(kc, FLUSH_ROWS);
+  return std::min<int64_t>(kc, (k_rows + b3::BK - 1) / b3::BK * b3::BK);
+}
+
+// BF16x3 scaled SYRK with the operand split once per chunk of rows.
+static gw_status syrk_bf16x3_split(gw_ctx ctx, const float* X, int64_t k_rows, int N,
+                                   int64_t ld, int L, const float* scale, double cscale,
+                                   double* out, int accumulate, const char* prof_name) {
+  const int T = (N + BM - 1) / BM;
+  const int Npad = T * BM;
+  const int n_tiles = T * (T + 1) / 2;
+  const int64_t kc = split_chunk_rows(k_rows, Npad, L);
+  const size_t y_elems = (size_t)L * Npad * kc;
+  __bf16* Y = static_cast<__bf16*>(ws_get(ctx, WS_B3_CHI, 2 * y_elems * sizeof(__bf16)));
+  if (!Y) return GW_ENOMEM;
+  const int S0 = choose_splits(kc, (int64_t)n_tiles * L);
+  std::vector<int> cand{S0};
+  if (S0 > 1) cand.push_back(std::max(1, S0 / 2));
+  if (2 * S0 <= 16 && kc / (2 * S0) >= 1024) cand.push_back(2 * S0);
+  const int S_max = *std::max_element(cand.begin(), cand.end());
+  double* part = static_cast<double*>(
+      ws_get(ctx, WS_SYRK_PART, (size_t)S_max * L * n_tiles * BM * BM * sizeof(double)));
+  if (!part) return GW_ENOMEM;
+  for (int64_t c0 = 0; c0 < k_rows; c0 += kc) {
+    const int64_t kr = std::min(kc, k_rows - c0);
+    const int64_t kp = (kr + b3::BK - 1) / b3::BK * b3::BK;
+    const ChiSplitArgs sa{X, ld, kr, N, L, scale, (float)cscale, k_rows, c0, Y,
+                          Y + (size_t)L * Npad * kp, kp, Npad};
+    const int ps = prof_begin(ctx);
+    hipLaunchKernelGGL(chi_split_kernel, dim3((unsigned)((kp + 63) / 64), (unsigned)(Npad / 64)),
+                       dim3(256), 0, ctx->stream, sa);
+    prof_end(ctx, ps, "chi_split_bf16x3", 0.0,
+             (double)kr * N * 4.0 + (double)L * Npad * kp * 4.0);
+    GW_TRY(launch_check(ctx, "chi_split_kernel"));
+    auto args = [&](int S) {
+      int64_t rps = (kp + S - 1) / S;
+      rps = (rps + FLUSH_ROWS - 1) / FLUSH_ROWS * FLUSH_ROWS;
+      const int Se = (int)((kp + rps - 1) / rps);
+      return Syrk3Args{sa.hi, sa.lo, kp, Npad, L, n_tiles, Se, rps, part};
+    };
+    // candidates: split-K factor x pipeline depth (2 stages, two workgroups
+    // per CU, or 3 stages, one), encoded as 4 S + stages
+    auto launch = [&](int code) {
+      const Syrk3Args a = args(code / 4);
+      const dim3 grid((unsigned)((int64_t)a.splits * L * n_tiles));
+      if (code % 4 == 3)
+        hipLaunchKernelGGL(syrk_bf16x3_direct_kernel<3>, grid, dim3(b3::NT), 0, ctx->stream, a);
+      else
+        hipLaunchKernelGGL(syrk_bf16x3_direct_kernel<2>, grid, dim3(b3::NT), 0, ctx->stream, a);
+      return launch_check(ctx, "syrk_bf16x3_direct_kernel");
+    };
+    std::vector<int> codes;
+    for (int c : cand) {
+      codes.push_back(4 * c + 2);
+      codes.push_back(4 * c + 3);
+    }
+    const std::string key = "syrk3:" + std::to_string(N) + ":" + std::to_string(L) + ":" +
+                            std::to_string(kp);
+    const int code = tune(ctx, key, codes, launch);
+    const Syrk3Args a = args(code / 4);
+    const int pi = prof_begin(ctx);
+    GW_TRY(launch(code));
+    prof_end(ctx, pi, prof_name, (double)L * N * (N + 1.0) * (double)kr,
+             (double)L * Npad * kp * 4.0 + (double)L * N * (N + 1.0) / 2.0 * 8.0);
+    const int64_t tot = (int64_t)L * n_tiles * BM * BM;
+    const RedArgs r{part, a.splits, L, n_tiles, N, out, (accumulate || c0 > 0) ? 1 : 0};
+    hipLaunchKernelGGL(syrk_reduce_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, ctx->stream,
+                       r);
+    GW_TRY(launch_check(ctx, "syrk_reduce_kernel"));
+  }
+  return GW_OK;
+}
+
 gw_status syrk_launch(gw_ctx ctx, gw_precision prec, const void* X, int64_t k_rows,
                       int N, int64_t ld, int L, const void* scale, double cscale,
                       double* out, int accumulate, const char* prof_name) {
+  if (prec == GW_BF16X3 && k_rows > 0)
+    return syrk_bf16x3_split(ctx, static_cast<const float*>(X), k_rows, N, ld, L,
+                             static_cast<const float*>(scale), cscale, out, accumulate,
+                             prof_name);
   const int T = (N + BM - 1) / BM;
   const int n_tiles = T * (T + 1) / 2;
   const int S0 = k_rows > 0 ? choose_splits(k_rows, (int64_t)n_tiles * L) : 1;
