@@ -225,7 +225,13 @@ struct Bwb3Args {
   double* part;         // [F][2 * col_tiles][rows]
 };
 
-__global__ __launch_bounds__(b3::NT, 2) void bwb_bf16x3_direct_kernel(Bwb3Args a) {
+// NW = 4: waves of 64 rows x 64 columns; NW = 8: waves of 32 rows x 64
+// columns (four waves per SIMD with two workgroups per CU).  Either way a
+// wave's columns are one 64-column slice, so each row's slice partial comes
+// from one wave.
+template <int NW>
+__global__ __launch_bounds__(NW * 64, 2) void bwb_bf16x3_direct_kernel(Bwb3Args a) {
+  constexpr int WI = NW == 4 ? 2 : 1, WJ = 2;
   __shared__ __attribute__((aligned(16))) b3::Stage st[2];
   const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
   const int rt = (int)(lid % a.row_tiles);
@@ -236,21 +242,23 @@ __global__ __launch_bounds__(b3::NT, 2) void bwb_bf16x3_direct_kernel(Bwb3Args a
   const __bf16* wh = a.wh + (int64_t)j * a.Npad * a.Npad;
   const __bf16* wl = a.wl + (int64_t)j * a.Npad * a.Npad;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wy = wave >> 1, wx = wave & 1;
+  const int wx = wave & 1;
+  const int ar = (wave >> 1) * (WI * 32);          // first tile row of the wave
+  const int br = wx * 64;                          // first tile column
 
-  f32x16 acc[2][2];
+  f32x16 acc[WI][WJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj)
+    for (int jj = 0; jj < WJ; ++jj)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][jj][r] = 0.f;
 
   auto issue = [&](int64_t kb, int buf) {
-    b3::load_tile(a.rh, a.Npad, row0, kb, st[buf].t[0], wave, lane);
-    b3::load_tile(a.rl, a.Npad, row0, kb, st[buf].t[1], wave, lane);
-    b3::load_tile(wh, a.Npad, col0, kb, st[buf].t[2], wave, lane);
-    b3::load_tile(wl, a.Npad, col0, kb, st[buf].t[3], wave, lane);
+    b3::load_tile<b3::BK, NW>(a.rh, a.Npad, row0, kb, st[buf].t[0], wave, lane);
+    b3::load_tile<b3::BK, NW>(a.rl, a.Npad, row0, kb, st[buf].t[1], wave, lane);
+    b3::load_tile<b3::BK, NW>(wh, a.Npad, col0, kb, st[buf].t[2], wave, lane);
+    b3::load_tile<b3::BK, NW>(wl, a.Npad, col0, kb, st[buf].t[3], wave, lane);
   };
   auto publish = [&]() {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -264,34 +272,34 @@ __global__ __launch_bounds__(b3::NT, 2) void bwb_bf16x3_direct_kernel(Bwb3Args a
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
     if (it + 1 < nk) issue(kstart + (int64_t)(it + 1) * b3::BK, cur ^ 1);
-    b3::stage_mfma(st[cur], acc, wy, wx, lane);
+    b3::stage_mfma<b3::BK, WI, WJ>(st[cur], acc, ar, br, lane);
     if (it + 1 == DIAG_STAGES && nk > DIAG_STAGES) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WI; ++i)
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 0.5f;
+        for (int jj = 0; jj < WJ; ++jj) acc[i][jj] *= 0.5f;
     }
     publish();
   }
   if (nk > DIAG_STAGES) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) acc[i][jj] *= 2.0f;
+      for (int jj = 0; jj < WJ; ++jj) acc[i][jj] *= 2.0f;
   }
 
   // epilogue: per-row dot product with R over this wave's 64 columns
   double* part = a.part + ((int64_t)j * 2 * a.col_tiles + 2 * ct + wx) * a.rows;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < WI; ++i) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int64_t row = row0 + wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int64_t row = row0 + ar + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
       double sum = 0.0;
       if (row < a.rows) {
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const int col = col0 + wx * 64 + jj * 32 + (lane & 31);
+        for (int jj = 0; jj < WJ; ++jj) {
+          const int col = col0 + br + jj * 32 + (lane & 31);
           if (col < a.N) sum += (double)acc[i][jj][r] * (double)a.R[row * a.ldr + col];
         }
       }
@@ -809,9 +817,21 @@ gw_status sigma_diag_run(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp, int
     const Bwb3Args a3{b.R3, b.R3 + rp * np, b.W3, b.W3 + (int64_t)F * np * np,
                       static_cast<const float*>(R_qp), ld_R, rows, N, (int)np, F, row_tiles,
                       col_tiles, b.part};
+    // 4 or 8 waves per workgroup, autotuned per shape (trials write only partials)
+    auto launch = [&](int nw) {
+      if (nw == 8)
+        hipLaunchKernelGGL(bwb_bf16x3_direct_kernel<8>, dim3((unsigned)grid), dim3(512), 0,
+                           ctx->stream, a3);
+      else
+        hipLaunchKernelGGL(bwb_bf16x3_direct_kernel<4>, dim3((unsigned)grid), dim3(256), 0,
+                           ctx->stream, a3);
+      return gw::launch_check(ctx, "bwb_bf16x3_direct_kernel");
+    };
+    const int nw = gw::tune(ctx, "bwb3:" + std::to_string(N) + ":" + std::to_string(rows) + ":" +
+                                     std::to_string(F),
+                            {4, 8}, launch);
     const int pi = gw::prof_begin(ctx);
-    hipLaunchKernelGGL(bwb_bf16x3_direct_kernel, dim3((unsigned)grid), dim3(b3::NT), 0,
-                       ctx->stream, a3);
+    GW_TRY(launch(nw));
     gw::prof_end(ctx, pi, "bwb_bf16x3", (double)F * (double)rows * N * (N + 1.0),
                  4.0 * ((double)rp * np + (double)F * np * np));
     GW_TRY(gw::launch_check(ctx, "bwb_bf16x3_direct_kernel"));

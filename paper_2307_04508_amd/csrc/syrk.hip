@@ -556,17 +556,21 @@ struct Syrk3Args {
 // tiles that read one slice of one Y_m run together on one XCD.
 // Accumulation is blocked: the MFMA accumulators sum FLUSH_ROWS rows, then
 // are added into a second FP32 sum per element, so an entry's rounding
-// error is bounded by gamma(FLUSH_ROWS + blocks) (blocked summation) while a
-// wave holds ~130 registers.  NBUF stages of LDS: with two, two workgroups
-// share a CU; with three, one workgroup per CU keeps the copies of stage
-// it + 2 in flight while stage it is multiplied.  Stage hand-over: wait for
-// this wave's copies of the next stage (those of later stages may stay in
-// flight), then a plain s_barrier (a __syncthreads() would also wait for
-// every copy still in flight).
-template <int NBUF>
-__global__ __launch_bounds__(b3::NT, NBUF == 2 ? 2 : 1) void syrk_bf16x3_direct_kernel(
-    Syrk3Args a) {
-  __shared__ __attribute__((aligned(16))) b3::Stage st[NBUF];
+// error is bounded by gamma(FLUSH_ROWS + blocks) (blocked summation).
+// Shapes (the autotuner picks one): 4 waves of 64 x 64 with 2 stages of LDS
+// (two workgroups per CU) or 3 stages (one workgroup per CU, the copies of
+// stage it + 2 in flight while stage it is multiplied), or 8 waves of
+// 64 x 32 with 2 stages (two workgroups, four waves per SIMD).  Stage
+// hand-over: wait for this wave's copies of the next stage (those of later
+// stages may stay in flight) and its LDS reads, then a plain s_barrier (a
+// __syncthreads() would also wait for every copy still in flight).
+template <int NBUF, int MINB, int NW>
+__global__ __launch_bounds__(NW * 64, MINB) void syrk_bf16x3_direct_kernel(Syrk3Args a) {
+  constexpr int BKT = 32;
+  constexpr int WI = 2, WJ = NW == 4 ? 2 : 1;          // 32 x 32 blocks per wave
+  constexpr int LOADS = 4 * BM / (64 / (BKT / 8)) / NW;  // copies per wave per stage
+  static_assert(NBUF == 2 || (NBUF == 3 && LOADS == 8), "three stages: 4 waves only");
+  __shared__ __attribute__((aligned(16))) b3::StageT<BKT> st[NBUF];
   const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
   const int t = (int)(lid % a.n_tiles);
   const int m = (int)((lid / a.n_tiles) % a.L);
@@ -576,52 +580,50 @@ __global__ __launch_bounds__(b3::NT, NBUF == 2 ? 2 : 1) void syrk_bf16x3_direct_
   const int64_t p0 = (int64_t)ti * BM, q0 = (int64_t)tj * BM;
   const int64_t r0 = (int64_t)s * a.rows_per_split;
   const int64_t r1 = min(r0 + a.rows_per_split, a.kp);
-  const int nk = r1 > r0 ? (int)((r1 - r0) / b3::BK) : 0;
+  const int nk = r1 > r0 ? (int)((r1 - r0) / BKT) : 0;
   const int64_t mo = (int64_t)m * a.Npad * a.kp;
   const __bf16* hi = a.hi + mo;
   const __bf16* lo = a.lo + mo;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wy = wave >> 1, wx = wave & 1;
+  const int ar = (NW == 4 ? (wave >> 1) : (wave >> 2)) * 64;   // first A (P) row of the wave
+  const int br = NW == 4 ? (wave & 1) * 64 : (wave & 3) * 32;  // first B (Q) row
 
-  f32x16 acc[2][2], sum[2][2];
+  f32x16 acc[WI][WJ], sum[WI][WJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) { acc[i][j][r] = 0.f; sum[i][j][r] = 0.f; }
 
-  // 8 global -> LDS copies per wave per stage (four tiles, two each)
   auto issue = [&](int it) {
-    const int64_t kb = r0 + (int64_t)it * b3::BK;
-    b3::Stage& d = st[it % NBUF];
-    b3::load_tile(hi, a.kp, p0, kb, d.t[0], wave, lane);
-    b3::load_tile(lo, a.kp, p0, kb, d.t[1], wave, lane);
-    b3::load_tile(hi, a.kp, q0, kb, d.t[2], wave, lane);
-    b3::load_tile(lo, a.kp, q0, kb, d.t[3], wave, lane);
+    const int64_t kb = r0 + (int64_t)it * BKT;
+    b3::StageT<BKT>& d = st[it % NBUF];
+    b3::load_tile<BKT, NW>(hi, a.kp, p0, kb, d.t[0], wave, lane);
+    b3::load_tile<BKT, NW>(lo, a.kp, p0, kb, d.t[1], wave, lane);
+    b3::load_tile<BKT, NW>(hi, a.kp, q0, kb, d.t[2], wave, lane);
+    b3::load_tile<BKT, NW>(lo, a.kp, q0, kb, d.t[3], wave, lane);
   };
   auto handover = [&](int it) {   // after stage it: stage it + 1 visible to all waves
-    // (lgkmcnt(0): this wave's LDS reads of the stage about to be refilled
-    // have completed before any wave passes the barrier)
     if (NBUF == 3 && it + 2 < nk)
       asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     else
       asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   };
-  constexpr int FLUSH_STAGES = FLUSH_ROWS / b3::BK;
+  constexpr int FLUSH_STAGES = FLUSH_ROWS / BKT;
   for (int it = 0; it < NBUF - 1 && it < nk; ++it) issue(it);
   handover(-1);
   for (int blk = 0; blk < nk; blk += FLUSH_STAGES) {
     const int end = min(blk + FLUSH_STAGES, nk);
     for (int it = blk; it < end; ++it) {
       if (it + NBUF - 1 < nk) issue(it + NBUF - 1);
-      b3::stage_mfma(st[it % NBUF], acc, wy, wx, lane);
+      b3::stage_mfma<BKT, WI, WJ>(st[it % NBUF], acc, ar, br, lane);
       handover(it);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < WJ; ++j) {
         sum[i][j] += acc[i][j];
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
@@ -630,13 +632,13 @@ __global__ __launch_bounds__(b3::NT, NBUF == 2 ? 2 : 1) void syrk_bf16x3_direct_
 
   double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = wy * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = wx * 64 + j * 32 + (lane & 31);
+        const int row = ar + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = br + j * 32 + (lane & 31);
         out[row * BM + col] = (double)sum[i][j][r];
       }
 }
@@ -966,22 +968,29 @@ static gw_status syrk_bf16x3_split(gw_ctx ctx, const float* X, int64_t k_rows, i
       const int Se = (int)((kp + rps - 1) / rps);
       return Syrk3Args{sa.hi, sa.lo, kp, Npad, L, n_tiles, Se, rps, part};
     };
-    // candidates: split-K factor x pipeline depth (2 stages, two workgroups
-    // per CU, or 3 stages, one), encoded as 4 S + stages
+    // candidates: split-K factor x kernel shape, encoded as 4 S + shape
+    // (0: 4 waves, 2 stages; 1: 4 waves, 3 stages; 2: 8 waves, 2 stages)
     auto launch = [&](int code) {
       const Syrk3Args a = args(code / 4);
       const dim3 grid((unsigned)((int64_t)a.splits * L * n_tiles));
-      if (code % 4 == 3)
-        hipLaunchKernelGGL(syrk_bf16x3_direct_kernel<3>, grid, dim3(b3::NT), 0, ctx->stream, a);
-      else
-        hipLaunchKernelGGL(syrk_bf16x3_direct_kernel<2>, grid, dim3(b3::NT), 0, ctx->stream, a);
+      switch (code % 4) {
+        case 1:
+          hipLaunchKernelGGL((syrk_bf16x3_direct_kernel<3, 1, 4>), grid, dim3(256), 0,
+                             ctx->stream, a);
+          break;
+        case 2:
+          hipLaunchKernelGGL((syrk_bf16x3_direct_kernel<2, 2, 8>), grid, dim3(512), 0,
+                             ctx->stream, a);
+          break;
+        default:
+          hipLaunchKernelGGL((syrk_bf16x3_direct_kernel<2, 2, 4>), grid, dim3(256), 0,
+                             ctx->stream, a);
+      }
       return launch_check(ctx, "syrk_bf16x3_direct_kernel");
     };
     std::vector<int> codes;
-    for (int c : cand) {
-      codes.push_back(4 * c + 2);
-      codes.push_back(4 * c + 3);
-    }
+    for (int c : cand)
+      for (int shape = 0; shape < 3; ++shape) codes.push_back(4 * c + shape);
     const std::string key = "syrk3:" + std::to_string(N) + ":" + std::to_string(L) + ":" +
                             std::to_string(kp);
     const int code = tune(ctx, key, codes, launch);
