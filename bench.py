@@ -57,7 +57,8 @@ def source_hash(path):
 def measured_traffic(kernel, workload):
     """HBM bytes per launch from the stored PMC passes (FETCH_SIZE +
     WRITE_SIZE, scaled by a plain copy), or None if none were taken for this
-    kernel and workload or the kernel's source changed since."""
+    kernel and workload or the kernel's source text (the function the record
+    names, hashed) changed since."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -65,7 +66,15 @@ def measured_traffic(kernel, workload):
     if not rec:
         return None
     src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src) or source_hash(src) != rec["source_sha256"]:
+    if not os.path.exists(src):
+        return None
+    text = open(src).read()
+    i = text.find(rec["region_start"])
+    if i < 0:
+        return None
+    region = text[i:text.index("\n}\n", i) + 3]
+    import hashlib
+    if hashlib.sha256(region.encode()).hexdigest() != rec["region_sha256"]:
         return None
     return rec["bytes_per_launch"]
 
