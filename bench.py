@@ -537,7 +537,8 @@ def main():
     chi = kernel_rate(gw, ctx, kname)
     bwb = kernel_rate(gw, ctx, bname)
     others = {n: kernel_rate(gw, ctx, n) for n in
-              ("naf_syrk", "screen_sweep", "naf_eig", "naf_gemm_f32", "naf_gemm_f64")}
+              ("naf_syrk", "screen_sweep", "naf_eig", "naf_tridiag", "naf_bisect", "naf_invit",
+               "naf_orth", "naf_back", "naf_gemm_f32", "naf_gemm_f64")}
     gw.gw_profile_enable(ctx, False)
     stage_ms = {"naf": st.t_naf_ms, "chi": st.t_chi_ms, "screen": st.t_screen_ms,
                 "sigma": st.t_sigma_ms, "qp": st.t_qp_ms, "total": st.t_total_ms}

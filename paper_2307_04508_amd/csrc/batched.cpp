@@ -177,7 +177,9 @@ extern "C" gw_status gw_g0w0_batched(gw_ctx ctx, gw_precision prec, const gw_bat
     if (st == GW_OK) st = gw::syrk_batched_launch(ctx, mp, ov, "naf_syrk");
     if (st != GW_OK) return fail_after(st);
     std::vector<gw::NafEigJob> ej;
-    for (Mol& g : mo) ej.push_back(gw::NafEigJob{U + g.u_off, g.A, U + g.u_off, g.eig.data()});
+    for (int d = 0; d < n; ++d)
+      ej.push_back(gw::NafEigJob{U + mo[d].u_off, mo[d].A, U + mo[d].u_off, mo[d].eig.data(),
+                                 mols[d].eps_naf, mols[d].max_keep});
     st = gw::naf_eig_batched(ctx, ej);
     if (st != GW_OK) return fail_after(st);
   }

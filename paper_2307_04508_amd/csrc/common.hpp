@@ -45,7 +45,6 @@ enum WsSlot {
   WS_TRI,           // tridiagonalisation exchange buffers and barrier counters
   WS_EIG_Y,         // eigenvectors of the tridiagonal matrix
   WS_NAF_T,         // k-major FP32 copies of the NAF transform's operands
-  WS_EIG_BACK,      // block-reflector factors and products of the back-transformation
   WS_B3_CHI,        // BF16x3 polarizability: split scaled rows (hi, lo) of a chunk
   WS_B3_R,          // BF16x3 contraction: split QP rows (hi, lo)
   WS_B3_W,          // BF16x3 contraction: split screened interactions (hi, lo)
@@ -195,8 +194,10 @@ gw_status qp_batched_launch(gw_ctx ctx, const std::vector<QpJob>& jobs, double e
 struct NafEigJob {
   const double* K;      // device [A][A] metric, lower triangle
   int A;
-  double* U;            // device [A][A]: eigenvectors as rows, descending
+  double* U;            // device [A][A]: eigenvectors as rows, descending (may alias K)
   double* eig;          // host [A]: eigenvalues, descending
+  double eps_naf;       // eigenvectors needed: eigenvalue > eps_naf,
+  int max_keep;         // at most max_keep of them when > 0
 };
 gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs);
 // FP32 transposes dst[c][r] = src[r][c] (c < cols, r < rows; rows up to
@@ -220,8 +221,8 @@ struct TriIn {
 };
 // Largest order the on-chip reduction takes on this context's device.
 int tridiag_max_order(gw_ctx ctx);
-// Workspace of the NAF back-transformation (WS_EIG_BACK) at order n.
-size_t back_ws_bytes(int n);
+// Workspace (WS_EIG_Y, doubles) of naf_tri_solve at order n.
+size_t tri_solve_ws_elems(int n);
 gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& jobs);
 struct NafGemmJob {
   const void* A;        // [rows][K]

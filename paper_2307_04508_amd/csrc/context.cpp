@@ -284,7 +284,8 @@ gw_status gw_reserve(gw_ctx ctx, gw_precision prec, const gw_dims* d) {
       {WS_SIGMA_W, gwb},
       {WS_SIGMA_RT, grt},
       {WS_EIG, (3 * (size_t)d->n_aux + 8) * sizeof(double)},
-      {WS_EIG_BACK, d->n_aux <= gw::tridiag_max_order(ctx) ? gw::back_ws_bytes(d->n_aux) : 0},
+      {WS_EIG_Y, d->n_aux <= gw::tridiag_max_order(ctx)
+                     ? gw::tri_solve_ws_elems(d->n_aux) * sizeof(double) : 0},
       {WS_QP, 3 * (size_t)d->n_qp * sizeof(double)},
   };
   for (const auto& w : want)

@@ -4,10 +4,10 @@
 //    virtual block omitted (Sec. 2), on the scaled-SYRK kernels with a
 //    constant scale.
 //  * Eigendecomposition of K in FP64 on the device: Householder reduction to
-//    tridiagonal form held on chip (tridiag.hip), rocSOLVER's divide-and-
-//    conquer stedc on the tridiagonal matrix, then the kept eigenvectors
-//    back-transformed in blocks of reflectors (compact WY form, GEMMs and a
-//    triangular solve); past the on-chip limit, rocSOLVER syevd.  The kept
+//    tridiagonal form held on chip (tridiag.hip), then bisection, inverse
+//    iteration and the back-transformation of the kept eigenvectors in
+//    blocks of reflectors (eig.hip); past the on-chip limit, rocSOLVER
+//    syevd.  The kept
 //    eigenvectors (eigenvalue > eps_NAF, at most max_keep) are copied in
 //    descending order into U (row p = p-th eigenvector).
 //  * Transform R~ = R U (Eq. 13): a GEMM with both operands contiguous along
@@ -23,16 +23,12 @@
 #include "common.hpp"
 
 namespace gw {
-// Eigenvalues (ascending, d_eval) of the symmetric matrix K (full storage;
-// destroyed: it receives the Householder reflectors, tau in d_tau) and the
-// eigenvectors of its tridiagonal form in the columns of Y (column-major).
-// d_e: n doubles of scratch.  Asynchronous.
-gw_status tri_eig(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_eval, double* d_e,
-                  double* d_tau, rocblas_int* d_info, double* Y);
-// Back-transformation of the last `cols` columns of Y to eigenvectors of
-// the original matrix (Y <- Q Y), from tri_eig's reflectors.
-gw_status tri_back(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_tau, double* Y,
-                   int cols);
+// Eigenpairs from the tridiagonal form (eig.hip): eigenvalues descending in
+// ev, the kept eigenvectors of the original matrix in U's first rows.
+gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const double* d_e,
+                        const double* d_tau, double eps_naf, int max_keep, double* U,
+                        std::vector<double>& ev, int* keep_out);
+rocblas_handle naf_rocblas(gw_ctx ctx);
 // Synchronises; GW_EDEVICE if a tridiagonalisation barrier timed out.
 gw_status check_tridiag(gw_ctx ctx);
 gw_status gemm_f32_direct(gw_ctx ctx, const std::vector<NafGemmJob>& jobs, const char* prof);
@@ -102,48 +98,6 @@ __global__ void reorder_kernel(const double* __restrict__ V, int n, int rows,
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = idx / n, c = idx % n;
     U[idx] = V[(int64_t)(n - 1 - p) * n + c];
-  }
-}
-
-// Back-transformation of the tridiagonal eigenvectors (Y <- Q Y with
-// Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^T) in blocks of kBackNb
-// reflectors, each block in the compact form I - V T V^T.  T comes from the
-// identity T^{-1} = diag(1 / tau) + (strictly upper part of V^T V), which
-// follows from appending one reflector at a time to the product (the larft
-// recurrence): the Gram matrices of all blocks are one batched GEMM, and T is
-// applied by a triangular solve with T^{-1} instead of being formed.
-constexpr int kBackNb = 256;
-
-// Reflector storage (column-major, ld n; v_k below row k + 1 of column k)
-// made explicit in place: zeros above row k + 1 and a one at row k + 1.  A
-// reflector with tau = 0 (H_k = I) becomes the zero vector.
-__global__ void explicit_reflectors_kernel(double* __restrict__ V, int n,
-                                           const double* __restrict__ tau) {
-  const int k = blockIdx.x;                        // column, 0 .. n - 2
-  const bool zero = tau[k] == 0.0;
-  double* col = V + (int64_t)k * n;
-  const int top = zero ? n : k + 2;                // rows rewritten
-  for (int i = threadIdx.x; i < top; i += blockDim.x)
-    col[i] = (i == k + 1 && !zero) ? 1.0 : 0.0;
-}
-
-// S (Gram matrices of the blocks, column-major nb x nb each, ld kBackNb)
-// becomes T^{-1} in place: strictly upper part kept, 1 / tau on the
-// diagonal (1 for tau = 0, whose zero reflector contributes nothing), zeros
-// below.
-__global__ void tinv_kernel(double* __restrict__ S, int n_blocks, int n_refl,
-                            const double* __restrict__ tau) {
-  const int b = blockIdx.x;
-  double* T = S + (int64_t)b * kBackNb * kBackNb;
-  for (int e = threadIdx.x; e < kBackNb * kBackNb; e += blockDim.x) {
-    const int i = e % kBackNb, j = e / kBackNb;
-    if (i > j) {
-      T[e] = 0.0;
-    } else if (i == j) {
-      const int k = b * kBackNb + i;
-      const double t = k < n_refl ? tau[k] : 0.0;
-      T[e] = t != 0.0 ? 1.0 / t : 1.0;
-    }
   }
 }
 
@@ -525,61 +479,50 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
   if (!finalize) return GW_OK;
 
   GW_TRY(gw::mirror_lower(ctx, K, 1, n_aux));
-  if (!ctx->rocblas) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success)
-      return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocblas_create_handle failed");
-    ctx->rocblas = h;
-  }
-  rocblas_handle h = static_cast<rocblas_handle>(ctx->rocblas);
-  rocblas_set_stream(h, ctx->stream);
   double* ws = static_cast<double*>(gw::ws_get(ctx, WS_EIG, (3 * (size_t)n_aux + 8) * sizeof(double)));
   if (!ws) return GW_ENOMEM;
   double* d_eval = ws;
   double* d_e = ws + n_aux;
   double* d_tau = ws + 2 * n_aux;
-  rocblas_int* d_info = reinterpret_cast<rocblas_int*>(ws + 3 * n_aux);
   const int pe = gw::prof_begin(ctx);
-  // orders the on-chip reduction takes: tridiagonalisation, tridiagonal
-  // eigenvectors, then only the kept ones back-transformed; larger ones:
-  // rocSOLVER syevd
-  const bool tri = n_aux <= gw::tridiag_max_order(ctx);
-  double* V = K;
-  if (tri) {
-    V = static_cast<double*>(gw::ws_get(ctx, WS_EIG_Y, (size_t)n_aux * n_aux * sizeof(double)));
-    if (!V) return GW_ENOMEM;
-    GW_TRY(gw::tri_eig(ctx, h, K, n_aux, d_eval, d_e, d_tau, d_info, V));
+  std::vector<double> ev(n_aux);
+  int keep = 0;
+  if (n_aux <= gw::tridiag_max_order(ctx)) {
+    // on-chip reduction to tridiagonal form, its eigenpairs, and only the
+    // kept eigenvectors back-transformed
+    const int pt = gw::prof_begin(ctx);
+    GW_TRY(gw::tridiag_jobs(ctx, {gw::TriIn{K, n_aux, d_eval, d_e, d_tau}}));
+    gw::prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
+    GW_TRY(gw::check_tridiag(ctx));
+    GW_TRY(gw::naf_tri_solve(ctx, K, n_aux, d_eval, d_e, d_tau, eps_naf, max_keep, U, ev, &keep));
   } else {
+    // larger orders: rocSOLVER syevd, ascending, eigenvectors in K's columns
+    rocblas_handle h = gw::naf_rocblas(ctx);
+    if (!h) return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocblas_create_handle failed");
+    rocblas_int* d_info = reinterpret_cast<rocblas_int*>(ws + 3 * n_aux);
     const rocblas_status rs = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_lower,
                                                n_aux, K, n_aux, d_eval, d_e, d_info);
     if (rs != rocblas_status_success)
       return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocsolver_dsyevd failed (%d)", (int)rs);
+    rocblas_int info = 0;
+    GW_HIP(ctx, hipMemcpyAsync(ev.data(), d_eval, n_aux * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    GW_HIP(ctx, hipMemcpyAsync(&info, d_info, sizeof info, hipMemcpyDeviceToHost, ctx->stream));
+    GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (info != 0)
+      return gw::fail(ctx, GW_ENOCONV, "gw_naf_compress: eigensolver info = %d", (int)info);
+    std::reverse(ev.begin(), ev.end());
+    while (keep < n_aux && ev[keep] > eps_naf) ++keep;
+    if (max_keep > 0) keep = std::min(keep, max_keep);
+    if (keep > 0) {
+      hipLaunchKernelGGL(reorder_kernel, dim3(grid_for((int64_t)keep * n_aux, 256)), dim3(256), 0,
+                         ctx->stream, K, n_aux, keep, U);
+      GW_TRY(gw::launch_check(ctx, "reorder_kernel"));
+    }
   }
-  std::vector<double> ev(n_aux);
-  rocblas_int info = 0;
-  GW_HIP(ctx, hipMemcpyAsync(ev.data(), d_eval, n_aux * sizeof(double), hipMemcpyDeviceToHost,
-                             ctx->stream));
-  GW_HIP(ctx, hipMemcpyAsync(&info, d_info, sizeof info, hipMemcpyDeviceToHost, ctx->stream));
-  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  GW_TRY(gw::check_tridiag(ctx));
-  if (info != 0)
-    return gw::fail(ctx, GW_ENOCONV, "gw_naf_compress: eigensolver info = %d", (int)info);
-  int keep = 0;
-  for (int i = n_aux - 1; i >= 0; --i) {
-    if (ev[i] > eps_naf) ++keep; else break;
-  }
-  if (max_keep > 0) keep = std::min(keep, max_keep);
-  if (tri && keep > 0) GW_TRY(gw::tri_back(ctx, h, K, n_aux, d_tau, V, keep));
   gw::prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
-  const int rows = tri ? keep : n_aux;
-  if (rows > 0) {
-    hipLaunchKernelGGL(reorder_kernel, dim3(grid_for((int64_t)rows * n_aux, 256)), dim3(256), 0,
-                       ctx->stream, V, n_aux, rows, U);
-    GW_TRY(gw::launch_check(ctx, "reorder_kernel"));
-  }
   *n_naf = keep;
-  if (eigvals)
-    for (int i = 0; i < n_aux; ++i) eigvals[i] = ev[n_aux - 1 - i];
+  if (eigvals) std::copy(ev.begin(), ev.end(), eigvals);
   return GW_OK;
 }
 
@@ -617,81 +560,6 @@ extern "C" gw_status gw_naf_apply(gw_ctx ctx, gw_precision prec, int n_aux, int 
 
 namespace gw {
 
-gw_status tri_eig(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_eval, double* d_e,
-                  double* d_tau, rocblas_int* d_info, double* Y) {
-  int pt = prof_begin(ctx);
-  GW_TRY(tridiag_jobs(ctx, {TriIn{K, n, d_eval, d_e, d_tau}}));
-  prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
-  pt = prof_begin(ctx);
-  const rocblas_status rs = rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, d_eval, d_e, Y, n,
-                                             d_info);
-  if (rs != rocblas_status_success)
-    return fail(ctx, GW_EDEVICE, "rocsolver_dstedc failed (%d)", (int)rs);
-  prof_end(ctx, pt, "naf_stedc", 0.0, 0.0);
-  return GW_OK;
-}
-
-size_t back_ws_bytes(int n) {
-  const size_t blocks = n > 1 ? (size_t)(n - 1 + kBackNb - 1) / kBackNb : 0;
-  return (blocks * kBackNb * kBackNb + (size_t)kBackNb * n) * sizeof(double);
-}
-
-gw_status tri_back(gw_ctx ctx, rocblas_handle h, double* K, int n, double* d_tau, double* Y,
-                   int cols) {
-  if (n < 2 || cols < 1) return GW_OK;
-  const int pt = prof_begin(ctx);
-  const int n_refl = n - 1, nb = kBackNb;
-  const int n_blocks = (n_refl + nb - 1) / nb, n_full = n_refl / nb;
-  double* ws = static_cast<double*>(ws_get(ctx, WS_EIG_BACK, back_ws_bytes(n)));
-  if (!ws) return GW_ENOMEM;
-  double* S = ws;                                        // [n_blocks][nb][nb]
-  double* W = ws + (size_t)n_blocks * nb * nb;           // [cols][nb]
-  double* Yk = Y + (size_t)(n - cols) * n;               // kept columns, ld n
-  hipLaunchKernelGGL(explicit_reflectors_kernel, dim3(n_refl), dim3(256), 0, ctx->stream, K, n,
-                     d_tau);
-  GW_TRY(launch_check(ctx, "explicit_reflectors_kernel"));
-  const double one = 1.0, zero = 0.0, minus_one = -1.0;
-  auto ok = [&](rocblas_status rs, const char* what) {
-    return rs == rocblas_status_success
-               ? GW_OK
-               : fail(ctx, GW_EDEVICE, "naf back-transformation: %s failed (%d)", what, (int)rs);
-  };
-  // Gram matrices V_b^T V_b over the full height (rows above the block are zeros)
-  if (n_full > 0)
-    GW_TRY(ok(rocblas_dgemm_strided_batched(h, rocblas_operation_transpose,
-                                            rocblas_operation_none, nb, nb, n, &one, K, n,
-                                            (rocblas_stride)nb * n, K, n, (rocblas_stride)nb * n,
-                                            &zero, S, nb, (rocblas_stride)nb * nb, n_full),
-              "Gram GEMM"));
-  if (n_full < n_blocks) {
-    const int w = n_refl - n_full * nb;
-    const double* Vb = K + (size_t)n_full * nb * n;
-    GW_TRY(ok(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, w, w, n, &one,
-                            Vb, n, Vb, n, &zero, S + (size_t)n_full * nb * nb, nb),
-              "Gram GEMM"));
-  }
-  hipLaunchKernelGGL(tinv_kernel, dim3(n_blocks), dim3(256), 0, ctx->stream, S, n_blocks, n_refl,
-                     d_tau);
-  GW_TRY(launch_check(ctx, "tinv_kernel"));
-  // Y <- Q_0 (Q_1 (... Q_last Y)): the last block first
-  for (int b = n_blocks - 1; b >= 0; --b) {
-    const int k0 = b * nb, w = std::min(nb, n_refl - k0), r0 = k0 + 1, m = n - r0;
-    const double* Vb = K + (size_t)k0 * n + r0;          // rows r0.., ld n
-    GW_TRY(ok(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, w, cols, m,
-                            &one, Vb, n, Yk + r0, n, &zero, W, nb),
-              "V^T Y"));
-    GW_TRY(ok(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                            rocblas_diagonal_non_unit, w, cols, &one, S + (size_t)b * nb * nb, nb,
-                            W, nb),
-              "T solve"));
-    GW_TRY(ok(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, cols, w,
-                            &minus_one, Vb, n, W, nb, &one, Yk + r0, n),
-              "Y - V W"));
-  }
-  prof_end(ctx, pt, "naf_ormtr", 4.0 * (double)n * n * cols, 0.0);
-  return GW_OK;
-}
-
 gw_status check_tridiag(gw_ctx ctx) {
   int f = 0;
   GW_HIP(ctx, hipMemcpyAsync(&f, ctx->d_flags + 1, sizeof f, hipMemcpyDeviceToHost, ctx->stream));
@@ -715,12 +583,64 @@ rocblas_handle naf_rocblas(gw_ctx ctx) {
   return h;
 }
 
-// Eigendecompositions of several metrics: jobs grouped into buckets of
-// similar size, each bucket one strided-batched FP64 divide-and-conquer
-// solve over padded copies.  K[d] (lower triangle) is read; U[d] receives
-// the eigenvectors as rows, descending; eig[d] (host, descending) the
-// eigenvalues.  Synchronises.
-gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs) {
+// Eigendecompositions of several metrics.  K[d] (lower triangle) is read;
+// U[d] receives the needed eigenvectors as rows, descending (at least those
+// above eps_naf, up to max_keep); eig[d] (host, descending) all eigenvalues.
+// Orders within the on-chip limit: every metric copied and mirrored, all
+// reduced to tridiagonal form together (packed cooperative launches), then
+// bisection, inverse iteration and back-transformation per metric.  Larger
+// orders: buckets of similar size, each one strided-batched rocSOLVER syevd
+// over padded copies.  Synchronises.
+static gw_status naf_eig_dsyevd_buckets(gw_ctx ctx, const std::vector<NafEigJob>& jobs);
+
+gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& all) {
+  std::vector<NafEigJob> big, small;
+  const int lim = tridiag_max_order(ctx);
+  for (const NafEigJob& j : all) (j.A <= lim ? small : big).push_back(j);
+  GW_TRY(naf_eig_dsyevd_buckets(ctx, big));
+  if (small.empty()) return GW_OK;
+  size_t k_tot = 0, v_tot = 0;
+  int a_max = 0;
+  for (const NafEigJob& j : small) {
+    k_tot += (size_t)j.A * j.A;
+    v_tot += (size_t)j.A;
+    a_max = std::max(a_max, j.A);
+  }
+  double* Kt = static_cast<double*>(ws_get(ctx, WS_B_K, k_tot * sizeof(double)));
+  double* dv = static_cast<double*>(ws_get(ctx, WS_B_EIG, (3 * v_tot + 8) * sizeof(double)));
+  if (!Kt || !dv) return GW_ENOMEM;
+  if (!ws_get(ctx, WS_EIG_Y, tri_solve_ws_elems(a_max) * sizeof(double))) return GW_ENOMEM;
+  std::vector<TriIn> tri;
+  std::vector<MirrorJob> mir;
+  size_t ko = 0, vo = 0;
+  for (const NafEigJob& j : small) {
+    GW_HIP(ctx, hipMemcpyAsync(Kt + ko, j.K, (size_t)j.A * j.A * sizeof(double),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    mir.push_back(MirrorJob{Kt + ko, 1, j.A});
+    tri.push_back(TriIn{Kt + ko, j.A, dv + vo, dv + v_tot + vo, dv + 2 * v_tot + vo});
+    ko += (size_t)j.A * j.A;
+    vo += (size_t)j.A;
+  }
+  GW_TRY(mirror_lower_batched(ctx, mir));
+  const int pe = prof_begin(ctx);
+  const int pt = prof_begin(ctx);
+  GW_TRY(tridiag_jobs(ctx, tri));
+  prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
+  GW_TRY(check_tridiag(ctx));
+  std::vector<double> ev;
+  for (size_t d = 0; d < small.size(); ++d) {
+    const NafEigJob& j = small[d];
+    int keep = 0;
+    GW_TRY(naf_tri_solve(ctx, tri[d].K, j.A, tri[d].d, tri[d].e, tri[d].tau, j.eps_naf,
+                         j.max_keep, j.U, ev, &keep));
+    std::copy(ev.begin(), ev.end(), j.eig);
+  }
+  prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return GW_OK;
+}
+
+static gw_status naf_eig_dsyevd_buckets(gw_ctx ctx, const std::vector<NafEigJob>& jobs) {
   const int n = (int)jobs.size();
   if (n == 0) return GW_OK;
   std::vector<int> order(n);
@@ -919,7 +839,8 @@ extern "C" gw_status gw_naf_compress_batched(gw_ctx ctx, gw_precision prec, int 
   std::vector<gw::NafEigJob> ej;
   for (int d = 0; d < n_jobs; ++d) {
     ev[d].resize(jobs[d].n_aux);
-    ej.push_back(gw::NafEigJob{jobs[d].K, jobs[d].n_aux, jobs[d].U, ev[d].data()});
+    ej.push_back(gw::NafEigJob{jobs[d].K, jobs[d].n_aux, jobs[d].U, ev[d].data(),
+                               jobs[d].eps_naf, jobs[d].max_keep});
   }
   GW_TRY(gw::naf_eig_batched(ctx, ej));
   for (int d = 0; d < n_jobs; ++d) {
