@@ -6,10 +6,9 @@
 //     A_RR <- A_RR - A_RK D^-1 A_KR,   A_RK <- A_RK D^-1,   A_KK <- -D^-1,
 // which keeps every intermediate symmetric, so only the lower triangle is
 // stored and updated; after the last block A holds -A^-1.  Sweeping a block
-// equals sweeping its sub-blocks in turn, which gives two levels: 256-wide
-// outer blocks, whose 256 x 256 pivot D is inverted by sweeping a dense copy
-// of it with 64-wide inner blocks (each 64 x 64 pivot inverted in
-// registers).  The pivots are Schur complements of the symmetric positive
+// equals sweeping its columns in turn, so each 256 x 256 pivot block D is
+// inverted by a column-by-column sweep held in the registers of one
+// workgroup per matrix.  The pivots are Schur complements of the symmetric positive
 // definite 1 - Pi, so no pivoting is needed; a non-positive pivot raises the
 // deferred GW_ENOTSPD flag.  The rank-256 trailing update (the whole O(N^3)
 // cost, N^3 flops per matrix on the triangle) and the panel product run on
@@ -85,22 +84,23 @@ __global__ void assemble_batched_kernel(Batch bt) {
 }
 
 // Arguments of one sweep step (pivot block kt, columns kb .. kb + bw - 1)
-// for one set of F matrices.  The inner level sweeps 64-wide pivot blocks
-// (pw = 64), inverting each 64 x 64 pivot in registers; the outer level
-// sweeps 256-wide blocks (pw = 256), inverting each 256 x 256 pivot block
-// by an inner-level sweep of a dense copy of it (Dw), so the O(N^3) trailing
-// update is a rank-256 MFMA product and the matrices are streamed through
-// HBM once per 256 columns.
+// for one set of F matrices.  Width pw = 64 inverts each 64 x 64 pivot in
+// registers (Dinv) and updates 64-tiles; pw = 128 or 256 sweeps each pivot
+// block whole in one workgroup (-D^-1 into Dw), so the O(N^3) trailing
+// update is a rank-pw MFMA product and the matrices are streamed through
+// HBM once per pw columns.
 struct SwArgs {
   double* A;            // [F][N][N] lower triangle
   double* C;            // [F][N][pw] pivot column panel
   double* P;            // [F][N][pw] scaled panel
-  double* Dinv;         // inner: [F][B][B] D^-1
-  double* Dw;           // outer: [F][bw][bw] pivot block, -D^-1 after its sweep
+  double* Dinv;         // pw = B: [F][B][B] D^-1
+  double* Dw;           // pw > B: [F][bw][bw], -D^-1 (lower triangle)
   int N, F, kb, bw, T, kt;
-  int pw;               // panel width (B or BO)
+  int pw;               // panel width (B, BI or BO)
   int flag_base;        // flag value offset of this set's first matrix
   int panel_blocks;     // inner panel kernel: workgroups per matrix
+  double* Cn;           // fused update (pw = 128): the next step's panel, [F][N][pw]
+  int kbn, bwn;         //   its first column and width (bwn = 0: no next step)
 };
 
 // C[j][r][c] = A_j(r, kb + c) read from the lower triangle; zero for c >= bw.
@@ -125,7 +125,7 @@ __global__ void gather_panel_batched_kernel(Batch bt) {
   for (int e = 0; e < kBatchElems; e += 256) gather_elem(a, first + e + threadIdx.x);
 }
 
-// Outer level: Dw[j][p][q] = D[p][q] (the pivot block, from the panel rows).
+// Dw[j][p][q] = D[p][q] (the pivot block, from the panel rows).
 __device__ __forceinline__ void extract_elem(const SwArgs& a, int64_t idx) {
   const int64_t bb = (int64_t)a.bw * a.bw;
   if (idx >= (int64_t)a.F * bb) return;
@@ -216,6 +216,106 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_batched_kernel(Batch bt,
   const int d = find_problem(bt.off, bt.n, blockIdx.x);
   const SwArgs a = static_cast<const SwArgs*>(bt.descs)[d];
   pivot_unit(a, (int)(blockIdx.x - bt.off[d]), flags);
+}
+
+// One workgroup per matrix sweeps its bw x bw pivot block D (PB >= bw;
+// padded with the identity), read from the panel rows kb .. of C.  The
+// lower triangle is held in registers as E x E blocks, thread u owning
+// lower block (tr, tc), tr >= tc (the diagonal blocks whole).  Each step
+// the owners of row k and of column k publish column k of the symmetric
+// block through double-buffered LDS (one barrier per step), then every block
+// takes the update a_ij -= a_ik a_kj / p and the owners rescale row and
+// column k.  Leaves -D^-1 (lower triangle) in Dw; a non-positive or
+// non-finite pivot raises the deferred flag and leaves zeros.
+template <int PB, int E>
+struct PivDense {
+  static constexpr int NB = PB / E;                       // blocks per side
+  static constexpr int BLOCKS = NB * (NB + 1) / 2;        // lower blocks
+  static constexpr int THREADS = (BLOCKS + 63) / 64 * 64;
+};
+
+template <int PB, int E>
+__global__ __launch_bounds__((PivDense<PB, E>::THREADS), 1) void pivot_dense_kernel(
+    Batch bt, int* __restrict__ flags) {
+  constexpr int NB = PivDense<PB, E>::NB;
+  __shared__ double v[2][PB];
+  const int dd = find_problem(bt.off, bt.n, blockIdx.x);
+  const SwArgs a = static_cast<const SwArgs*>(bt.descs)[dd];
+  const int j = (int)(blockIdx.x - bt.off[dd]);
+  const int u = threadIdx.x;
+  const bool own = u < PivDense<PB, E>::BLOCKS;
+  int tr = 0, tc = 0;
+  if (own) {
+    tr = (int)((sqrtf(8.0f * u + 1.0f) - 1.0f) * 0.5f);
+    while ((tr + 1) * (tr + 2) / 2 <= u) ++tr;
+    while (tr * (tr + 1) / 2 > u) --tr;
+    tc = u - tr * (tr + 1) / 2;
+  }
+  const int bw = a.bw, pw = a.pw;
+  const double* Cj = a.C + (int64_t)j * a.N * pw + (int64_t)a.kb * pw;   // D[p][q] = Cj[p pw + q]
+  double d[E][E];
+#pragma unroll
+  for (int r = 0; r < E; ++r)
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+      const int gr = E * tr + r, gc = E * tc + c;
+      d[r][c] = (own && gr < bw && gc < bw) ? Cj[(int64_t)gr * pw + gc] : (gr == gc ? 1.0 : 0.0);
+    }
+  bool bad = false;
+  for (int kq = 0; kq < NB; ++kq) {
+#pragma unroll
+    for (int kk = 0; kk < E; ++kk) {
+      const int k = E * kq + kk, buf = k & 1;
+      if (own && tc == kq) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) v[buf][E * tr + r] = d[r][kk];
+      }
+      if (own && tr == kq) {
+#pragma unroll
+        for (int c = 0; c < E; ++c) v[buf][E * tc + c] = d[kk][c];
+      }
+      __syncthreads();
+      const double piv = v[buf][k];
+      bad = bad || !(piv > 0.0) || !isfinite(piv);
+      // 1 / piv from the hardware estimate r and its correction
+      // r (1 + e + e^2), e = 1 - piv r (rounding-level; shorter than a division)
+      const double r0 = __builtin_amdgcn_rcp(piv), e0 = fma(-piv, r0, 1.0);
+      const double inv = fma(r0, fma(e0, e0, e0), r0);
+      if (own) {
+        double vc[E];
+#pragma unroll
+        for (int c = 0; c < E; ++c) vc[c] = v[buf][E * tc + c];
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const double vr = v[buf][E * tr + r] * inv;
+#pragma unroll
+          for (int c = 0; c < E; ++c) d[r][c] = fma(-vr, vc[c], d[r][c]);
+          if (tc == kq) d[r][kk] = vr;                  // a_ik / p
+        }
+        if (tr == kq) {
+#pragma unroll
+          for (int c = 0; c < E; ++c) d[kk][c] = vc[c] * inv;   // a_kj / p
+          if (tc == kq) d[kk][kk] = -inv;
+        }
+      }
+    }
+  }
+  // every thread sees the same pivots, so `bad` is uniform
+  if (bad && u == 0) atomicCAS(flags, 0, a.flag_base + j + 1);
+  if (own) {
+    double* out = a.Dw + (int64_t)j * bw * bw;
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+#pragma unroll
+      for (int c = 0; c < E; ++c) {
+        const int gr = E * tr + r, gc = E * tc + c;
+        if (gr < bw && gc < bw && gr >= gc) {
+          const double w = bad ? 0.0 : d[r][c];
+          out[(int64_t)gr * bw + gc] = w;
+          out[(int64_t)gc * bw + gr] = w;
+        }
+      }
+  }
 }
 
 // Inner level: P[j][r][c] = sum_c' C[j][r][c'] Dinv[j][c'][c] for every row r; this
@@ -526,6 +626,227 @@ __global__ __launch_bounds__(512, 2) void update128_batched_kernel(Batch bt) {
       }
 }
 
+// Width 128: P = C D^-1 = -C Dw for every 128-row tile of the panel (Dw
+// holds -D^-1 in both triangles, so its rows serve as the k-contiguous
+// second operand), with the update kernel's tile pipeline: 8 waves of
+// 32 x 64, k in double-buffered chunks of 16 stored k-major in LDS.
+// Columns c >= bw of P are zero.
+__global__ __launch_bounds__(512, 2) void panel128_kernel(Batch bt) {
+  __shared__ double Xs[2][BKU][LDU];
+  __shared__ double Ds[2][BKU][LDU];
+  SwArgs sa;
+  int64_t lid;
+  if (!unit_of(SwArgs{}, bt, sa, lid)) return;
+  const int N = sa.N, pw = sa.pw, bw = sa.bw;
+  const int T = (N + BU - 1) / BU;
+  const int j = (int)(lid / T), I = (int)(lid % T);
+  const double* Cj = sa.C + (int64_t)j * N * pw;
+  const double* Dj = sa.Dw + (int64_t)j * bw * bw;
+  double* Pj = sa.P + (int64_t)j * N * pw;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;
+  f64x4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int lr = tid >> 3, lk = (tid & 7) * 2;
+  double rx[2][2], rd[2][2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int xr = I * BU + lr + 64 * h, dr = lr + 64 * h;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int k = k0 + lk + e;
+        rx[h][e] = (xr < N && k < bw) ? Cj[(int64_t)xr * pw + k] : 0.0;
+        rd[h][e] = (dr < bw && k < bw) ? Dj[(int64_t)dr * bw + k] : 0.0;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        Xs[buf][lk + e][lr + 64 * h] = rx[h][e];
+        Ds[buf][lk + e][lr + 64 * h] = rd[h][e];
+      }
+  };
+  const int nk = (bw + BKU - 1) / BKU;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) gload((it + 1) * BKU);
+#pragma unroll
+    for (int kk = 0; kk < BKU / 4; ++kk) {
+      const int kr = 4 * kk + (lane >> 4);
+      double af[2], bf[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = Xs[cur][kr][wy * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bf[b] = Ds[cur][kr][wx * 64 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = I * BU + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int col = wx * 64 + b * 16 + (lane & 15);
+        if (row < N) Pj[(int64_t)row * pw + col] = col < bw ? -acc[a][b][r] : 0.0;
+      }
+}
+
+// Width 128 (one 128-tile per pivot block K), the whole step after the
+// panel product in one pass over the lower 128-tiles of A:
+//   tiles off row and column K:  A[I][J] -= P[I rows] C[J rows]^T (as above);
+//   tiles in column K:           A(r, K) <- P[r]        (the swept column);
+//   tiles in row K:              A(K, c) <- P[c]^T      (its mirror in the lower triangle);
+//   the pivot tile:              A(K, K) <- -D^-1       (lower triangle, from Dw);
+// and every tile in row or column K + 1 also writes its new values into the
+// next step's panel Cn (transposed for row K + 1; the diagonal tile fills
+// both triangles; zeros past N), which replaces that step's gather.
+__global__ __launch_bounds__(512, 2) void update_fused_kernel(Batch bt) {
+  __shared__ double Ps[2][BKU][LDU];
+  __shared__ double Cs[2][BKU][LDU];
+  SwArgs sa;
+  int64_t lid;
+  if (!unit_of(SwArgs{}, bt, sa, lid)) return;
+  const int N = sa.N, pw = sa.pw, bw = sa.bw, kb = sa.kb;
+  const int T = (N + BU - 1) / BU;
+  const int n_tiles = T * (T + 1) / 2;
+  const int j = (int)(lid / n_tiles);
+  int I, J;
+  lower_tile((int)(lid % n_tiles), I, J);
+  const int K = kb / BU, Kn = sa.bwn > 0 ? sa.kbn / BU : -1;
+  const bool in_row = I == K, in_col = J == K;
+  const double* Pj = sa.P + (int64_t)j * N * pw;
+  const double* Cj = sa.C + (int64_t)j * N * pw;
+  double* Aj = sa.A + (int64_t)j * N * N;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wy = wave >> 1, wx = wave & 1;            // rows wy*32, cols wx*64
+  f64x4 acc[2][4];
+  if (!in_row && !in_col) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = I * BU + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+          const int col = J * BU + wx * 64 + b * 16 + (lane & 15);
+          acc[a][b][r] = (row < N && col < N) ? Aj[(int64_t)row * N + col] : 0.0;
+        }
+    const int lr = tid >> 3, lk = (tid & 7) * 2;
+    double2 rp[2], rc[2];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int pr = I * BU + lr + 64 * h, cr = J * BU + lr + 64 * h;
+        rp[h] = pr < N ? *reinterpret_cast<const double2*>(Pj + (int64_t)pr * pw + k0 + lk)
+                       : make_double2(0.0, 0.0);
+        rc[h] = cr < N ? *reinterpret_cast<const double2*>(Cj + (int64_t)cr * pw + k0 + lk)
+                       : make_double2(0.0, 0.0);
+      }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        Ps[buf][lk][lr + 64 * h] = -rp[h].x;
+        Ps[buf][lk + 1][lr + 64 * h] = -rp[h].y;
+        Cs[buf][lk][lr + 64 * h] = rc[h].x;
+        Cs[buf][lk + 1][lr + 64 * h] = rc[h].y;
+      }
+    };
+    const int nk = (bw + BKU - 1) / BKU;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+      const int cur = it & 1;
+      if (it + 1 < nk) gload((it + 1) * BKU);
+#pragma unroll
+      for (int kk = 0; kk < BKU / 4; ++kk) {
+        const int kr = 4 * kk + (lane >> 4);
+        double af[2], bf[4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) af[a] = Ps[cur][kr][wy * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = Cs[cur][kr][wx * 64 + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+      }
+      if (it + 1 < nk) sstore(cur ^ 1);
+      __syncthreads();
+    }
+  } else {
+    const double* Dj = sa.Dw + (int64_t)j * bw * bw;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = I * BU + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+          const int col = J * BU + wx * 64 + b * 16 + (lane & 15);
+          double v = 0.0;
+          if (row < N && col < N) {
+            if (in_row && in_col)
+              v = row >= col ? Dj[(int64_t)(row - kb) * bw + (col - kb)] : 0.0;
+            else if (in_col)
+              v = Pj[(int64_t)row * pw + (col - kb)];
+            else
+              v = Pj[(int64_t)col * pw + (row - kb)];
+          }
+          acc[a][b][r] = v;
+        }
+  }
+  const bool next_col = J == Kn, next_row = I == Kn;
+  double* Cn = sa.Cn + (int64_t)j * N * pw;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = I * BU + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int col = J * BU + wx * 64 + b * 16 + (lane & 15);
+        const double v = acc[a][b][r];
+        // the pivot tile's upper triangle is not part of the lower storage
+        if (row < N && col < N && !(in_row && in_col && row < col))
+          Aj[(int64_t)row * N + col] = v;
+        if (next_col && next_row) {                    // diagonal tile of the next block
+          if (row < N) {
+            if (col >= N) {
+              Cn[(int64_t)row * pw + (col - sa.kbn)] = 0.0;
+            } else if (row >= col) {
+              Cn[(int64_t)row * pw + (col - sa.kbn)] = v;
+              Cn[(int64_t)col * pw + (row - sa.kbn)] = v;
+            }
+          }
+        } else if (next_col) {
+          if (row < N) Cn[(int64_t)row * pw + (col - sa.kbn)] = col < N ? v : 0.0;
+        } else if (next_row) {
+          if (col < N) Cn[(int64_t)col * pw + (row - sa.kbn)] = row < N ? v : 0.0;
+        }
+      }
+}
+
 // Pivot rows / columns after the update: A(r, K) <- P[r] for r outside K;
 // A(K, K) <- -D^-1 (inner: from Dinv; outer: Dw already holds it), lower
 // triangle storage.
@@ -621,16 +942,19 @@ struct SweepSet {
   int N, F, flag_base;
 };
 
-constexpr int BO = 256;   // outer pivot block width
+constexpr int BO = 256;   // widest pivot block
+constexpr int BI = 128;   // pivot blocks swept whole in one workgroup
+static_assert(BI == BU, "the fused update takes one 128-tile per pivot block");
+constexpr int kPivE = 4;  // register block edge of the whole-block pivot sweep
 
 // Scratch (doubles) of a two-level sweep of the given sets.
 size_t sweep_scratch(const std::vector<SweepSet>& sets) {
   size_t t = 0;
   for (const SweepSet& s : sets) {
-    t += 2 * (size_t)s.F * s.N * BO;               // outer C, P
-    t += (size_t)s.F * BO * BO;                    // outer Dw
-    t += 2 * (size_t)s.F * BO * B;                 // inner C, P (over Dw)
-    t += (size_t)s.F * B * B;                      // inner Dinv
+    t += 3 * (size_t)s.F * s.N * BO;               // panels C (two, by step parity), P
+    t += (size_t)s.F * BO * BO;                    // pivot block Dw (or Dinv)
+    t += 3 * (size_t)s.F * BO * BI;                // width BO: C, C, P of the Dw sweep
+    t += (size_t)s.F * BI * BI;                    //   and its pivot blocks
   }
   return t;
 }
@@ -640,7 +964,8 @@ size_t sweep_scratch(const std::vector<SweepSet>& sets) {
 // single staging copy, and the launches then read their slices of it (one
 // copy per sweep instead of one or two per launch).
 struct SweepLaunch {
-  void (*kern)(Batch);    // nullptr: pivot_batched_kernel
+  void (*kern)(Batch);    // nullptr: a pivot kernel (kind), which also takes the flags
+  int kind;               // 0 pivot_batched_kernel, 1 pivot_dense_kernel<BI, kPivE>
   size_t args_at, off_at; // byte offsets of the SwArgs and offsets arrays in the blob
   int n, chunk, threads;
   int64_t units, grid;
@@ -661,7 +986,8 @@ struct SweepPlan {
 
 template <typename F>
 void plan_units(SweepPlan& plan, size_t args_at, const std::vector<SwArgs>& st, F units,
-                int chunk, bool elems, void (*kern)(Batch), int threads, const char* what) {
+                int chunk, bool elems, void (*kern)(Batch), int threads, const char* what,
+                int kind = 0) {
   std::vector<int64_t> off(1, 0);
   for (const SwArgs& a : st) {
     const int64_t u = units(a);
@@ -670,28 +996,31 @@ void plan_units(SweepPlan& plan, size_t args_at, const std::vector<SwArgs>& st, 
   if (off.back() == 0) return;
   const int64_t grid = chunk > 1 ? (off.back() + 8 * chunk - 1) / (8 * chunk) * (8 * chunk)
                                  : off.back();
-  plan.launches.push_back(SweepLaunch{kern, args_at, plan.put(off.data(), off.size()),
+  plan.launches.push_back(SweepLaunch{kern, kind, args_at, plan.put(off.data(), off.size()),
                                       (int)st.size(), chunk, threads, off.back(), grid, what});
 }
 
-// Plan the sweep of every set to -A^-1 with pivot blocks of width pw: B (one
-// level, each 64 x 64 pivot inverted in registers) or 128 / 256 (outer
-// level, whose pivot blocks are inverted by a one-level sweep of their
-// copies).  `scr` holds sweep_scratch(sets) doubles.
+// Plan the sweep of every set to -A^-1 with pivot blocks of width pw: B
+// (each 64 x 64 pivot inverted in registers, tiles of 64), BI (each pivot
+// block swept whole in the registers of one workgroup, the trailing update
+// on 128-tiles) or BO (each pivot block copied and swept at width BI).
+// `scr` holds sweep_scratch(sets) doubles.
 void plan_sweep(SweepPlan& plan, const std::vector<SweepSet>& sets, int pw, double* scr) {
   const int n = (int)sets.size();
-  std::vector<double*> C(n), P(n), X(n);   // X: Dw (outer) or Dinv (inner)
+  std::vector<double*> C(n), C2(n), P(n), X(n);   // X: Dw (outer) or Dinv (inner)
   size_t o = 0;
   for (int d = 0; d < n; ++d) {
     const SweepSet& s = sets[d];
     C[d] = scr + o;
+    o += (size_t)s.F * s.N * pw;
+    C2[d] = scr + o;
     o += (size_t)s.F * s.N * pw;
     P[d] = scr + o;
     o += (size_t)s.F * s.N * pw;
     X[d] = scr + o;
     o += pw > B ? (size_t)s.F * pw * pw : (size_t)s.F * B * B;
   }
-  double* inner_scr = scr + o;              // outer level: scratch of the inner sweeps
+  double* inner_scr = scr + o;              // width BO: scratch of the pivot-block sweeps
   int T_max = 0;
   for (const SweepSet& s : sets) T_max = std::max(T_max, (s.N + pw - 1) / pw);
   for (int kt = 0; kt < T_max; ++kt) {
@@ -702,26 +1031,50 @@ void plan_sweep(SweepPlan& plan, const std::vector<SweepSet>& sets, int pw, doub
       const int kb = kt * pw;
       if (kb >= s.N) continue;
       const int bw = std::min(pw, s.N - kb);
-      SwArgs a{s.A, C[d], P[d], pw == B ? X[d] : nullptr, pw > B ? X[d] : nullptr, s.N, s.F,
-               kb, bw, (s.N + B - 1) / B, kt, pw, s.flag_base, std::min(1024, (s.N + 15) / 16)};
+      // width BI: the fused update writes the next panel into the other buffer
+      double* cur = (pw == BI && (kt & 1)) ? C2[d] : C[d];
+      double* nxt = (pw == BI && (kt & 1)) ? C[d] : C2[d];
+      const int kbn = kb + pw, bwn = std::max(0, std::min(pw, s.N - kbn));
+      SwArgs a{s.A, cur, P[d], pw == B ? X[d] : nullptr, pw > B ? X[d] : nullptr, s.N, s.F,
+               kb, bw, (s.N + B - 1) / B, kt, pw, s.flag_base, std::min(1024, (s.N + 15) / 16),
+               nxt, kbn, bwn};
       st.push_back(a);
-      if (pw > B) dsets.push_back(SweepSet{X[d], bw, s.F, s.flag_base});
+      if (pw > BI) dsets.push_back(SweepSet{X[d], bw, s.F, s.flag_base});
     }
     const size_t at = plan.put(st.data(), st.size());
-    plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; }, 1, true,
-               gather_panel_batched_kernel, 256, "gather_panel");
+    if (pw != BI || kt == 0)
+      plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; }, 1, true,
+                 gather_panel_batched_kernel, 256, "gather_panel");
     if (pw == B) {
       plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F; }, 1, false, nullptr,
                  PIV_THREADS, "pivot_batched_kernel");
       plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.panel_blocks; }, 1,
                  false, panel_batched_kernel, 256, "panel_batched_kernel");
-    } else {
+    } else if (pw > BI) {
+      // copies of the pivot blocks, swept at width BI
       plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.bw * a.bw; }, 1,
                  true, extract_pivot_batched_kernel, 256, "extract_pivot");
-      plan_sweep(plan, dsets, B, inner_scr);
+      plan_sweep(plan, dsets, BI, inner_scr);
       plan_units(plan, at, st,
                  [](const SwArgs& a) { return (int64_t)a.F * ((a.N + B - 1) / B) * (a.pw / B); },
                  8, false, panel_gemm_batched_kernel, 256, "panel_gemm");
+    } else {
+      // the pivot block of every matrix swept whole by one workgroup
+      plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F; }, 1, false, nullptr,
+                 PivDense<BI, kPivE>::THREADS, "pivot_dense_kernel", 1);
+      plan_units(plan, at, st,
+                 [](const SwArgs& a) { return (int64_t)a.F * ((a.N + BU - 1) / BU); }, 8, false,
+                 panel128_kernel, 512, "panel128_kernel");
+    }
+    if (pw == BI) {
+      // update, write-back and the next panel in one pass
+      plan_units(plan, at, st,
+                 [](const SwArgs& a) {
+                   const int64_t t = (a.N + BU - 1) / BU;
+                   return (int64_t)a.F * t * (t + 1) / 2;
+                 },
+                 8, false, update_fused_kernel, 512, "update_fused_kernel");
+      continue;
     }
     if (pw > B) {
       plan_units(plan, at, st,
@@ -751,6 +1104,9 @@ gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* s
                    reinterpret_cast<const int64_t*>(dev + l.off_at), l.n, l.chunk, l.units};
     if (l.kern)
       hipLaunchKernelGGL(l.kern, dim3((unsigned)l.grid), dim3(l.threads), 0, ctx->stream, bt);
+    else if (l.kind == 1)
+      hipLaunchKernelGGL((pivot_dense_kernel<BI, kPivE>), dim3((unsigned)l.grid), dim3(l.threads), 0,
+                         ctx->stream, bt, ctx->d_flags);
     else
       hipLaunchKernelGGL(pivot_batched_kernel, dim3((unsigned)l.grid), dim3(l.threads), 0,
                          ctx->stream, bt, ctx->d_flags);
