@@ -313,8 +313,11 @@ def run_streamed(args, cfg, gw, torch):
 def run_grid_sweep(args, cfg, gw, torch):
     """Fig. 4 on the synthetic workload: G0W0 wall time and the largest QP
     error over the QP states for Laplace grids of L points x modified-GL
-    grids of F frequencies, against the sum-over-states (no Laplace) result
-    on the largest F; plus the smallest L whose normalised minimax error is
+    grids of F frequencies, against the FP64 oracle's sum-over-states (no
+    Laplace) result on the largest F where it is stored (medium:
+    tests/golden/medium_sweep_oracle.json, also giving each SOS row's
+    difference from the oracle at its own F), else against this path's own
+    sum over states; plus the smallest L whose normalised minimax error is
     below eps_LT = 1e-7 (Sec. 3) on the workload's bounds."""
     import dataclasses
     from gwsynth import make_problem
@@ -336,12 +339,22 @@ def run_grid_sweep(args, cfg, gw, torch):
     ref_cfg = dataclasses.replace(cfg, n_freq=F_list[-1])
     t_ref, E_ref, S_ref, _ = timed(gw.params_for(ref_cfg, no_lt=True))
     log(f"reference (no Laplace, F={F_list[-1]}): {t_ref * 1e3:.1f} ms")
+    gpath = os.path.join(ROOT, "tests", "golden", f"{cfg.name}_sweep_oracle.json")
+    oracle = json.load(open(gpath)) if os.path.exists(gpath) else None
+    ref_kind = "this path's sum over states"
+    if oracle is not None and list(oracle["qp"]) == [int(q) for q in prob.qp]:
+        E_ref = np.array(oracle[f"eps_qp_sos_F{F_list[-1]}"])
+        ref_kind = "FP64 oracle sum over states"
+    log(f"QP errors against the {ref_kind} at F={F_list[-1]}")
     rows = []
     for F in F_list:
         t_sos, E_sos, _, _ = timed(gw.params_for(dataclasses.replace(cfg, n_freq=F), no_lt=True))
         rows.append({"F": F, "L": None, "ms": round(t_sos * 1e3, 2),
                      "speedup": round(t_ref / t_sos, 2),
                      "qp_err_meV": float(np.max(np.abs(E_sos - E_ref)) * HARTREE_MEV)})
+        if oracle is not None and f"eps_qp_sos_F{F}" in oracle:
+            rows[-1]["vs_oracle_same_F_meV"] = float(
+                np.max(np.abs(E_sos - np.array(oracle[f"eps_qp_sos_F{F}"]))) * HARTREE_MEV)
         for L in L_list:
             c2 = dataclasses.replace(cfg, n_freq=F, n_lt=L)
             t, E, S, st = timed(gw.params_for(c2))
@@ -351,7 +364,8 @@ def run_grid_sweep(args, cfg, gw, torch):
             log(f"F={F} L={L}: {t * 1e3:.1f} ms, QP error {rows[-1]['qp_err_meV']:.3f} meV")
     auto = gw.lt_points_for(prob.eps, cfg, 1e-7)
     print(json.dumps({"grid_sweep": cfg.name, "prec": args.prec, "reference_ms": t_ref * 1e3,
-                      "rows": rows, "auto_L_eps_lt_1e-7": auto}), flush=True)
+                      "reference": ref_kind, "rows": rows, "auto_L_eps_lt_1e-7": auto}),
+          flush=True)
     ctx.close()
 
 
@@ -420,6 +434,19 @@ def run_batched(args, gw, torch):
         out[f"batched_{prec}_qp_diff_vs_fp64_meV"] = qp_diff([(E, S) for (E, _, S, _, _) in res])
         out[f"batched_{prec}_status_ok"] = ok
         log(f"batched {prec} (graph): {tb:.3f} s, NAF {stats.t_naf_ms:.0f} ms")
+        if prec == "fp32":
+            # one more pass with kernel timing: the NAF eigensolver's stages
+            gw.gw_profile_enable(ctx, True)
+            gw.gw_g0w0_batched(ctx, prec, params, m32, graph=True)
+            torch.cuda.synchronize()
+            parts = {}
+            for name in ("naf_eig", "naf_tridiag", "naf_bisect", "naf_invit", "naf_orth",
+                         "naf_back"):
+                ms, n, _, _ = gw.gw_profile_get(ctx, name)
+                parts[name] = round(ms, 2) if n else None
+            gw.gw_profile_enable(ctx, False)
+            out["batched_naf_stages_ms"] = parts
+            log(f"batched NAF stages (ms, summed over molecules): {parts}")
     out["speedup_batched_fp32_vs_per_molecule_fp64"] = t64 / out["batched_fp32_graph_s"]
     out["speedup_batched_fp32_vs_per_molecule_fp32"] = t32 / out["batched_fp32_graph_s"]
     print(json.dumps({"batched": out}), flush=True)

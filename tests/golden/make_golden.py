@@ -15,7 +15,11 @@ occupied-index chunks of the generator, and the transformation (Eq. 13) is
 applied chunk by chunk; everything after the transformation is the oracle's
 chain unchanged.
 
-usage: python tests/golden/make_golden.py medium|large|medium_literal
+"medium_sweep" stores the sum-over-states QP energies of the medium
+workload at F = 32, 64 and 128 imaginary frequencies (the references of the
+grid sweep, Fig. 4 and Sec. 3).
+
+usage: python tests/golden/make_golden.py medium|large|medium_literal|medium_sweep
 """
 from __future__ import annotations
 
@@ -63,7 +67,33 @@ def _streamed_naf(cfg, t0, chunk=16):
     return src.eps, src.qp, lam, U, Rt_ov, Rt_qp
 
 
+def sweep_references(t0, F_list=(32, 64, 128)):
+    """Sum-over-states QP energies of the medium workload at several F."""
+    cfg = get_config("medium")
+    prob = make_problem(cfg)
+    _log(t0, "generated medium")
+    common = dict(n_pade=cfg.n_pade, x0=cfg.x0, eta=cfg.eta)
+    out = {"config": "medium_sweep", "qp": np.asarray(prob.qp).tolist(), "F": list(F_list)}
+    base = None
+    for F in F_list:
+        if base is None:
+            base = g0w0_problem(prob, n_freq=F)
+            res = base
+        else:
+            res = g0w0_naf(prob.eps, cfg.n_fc, cfg.n_occ, prob.qp, base.Rt_ov, base.Rt_qp,
+                           lam=base.lam, U=base.U, n_freq=F, **common)
+        out[f"eps_qp_sos_F{F}"] = res.eps_qp.tolist()
+        out[f"z_sos_F{F}"] = res.z.tolist()
+        _log(t0, f"sum-over-states chain at F = {F} done")
+    path = os.path.join(HERE, "medium_sweep_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    _log(t0, f"wrote {path}")
+
+
 def main(name: str):
+    if name == "medium_sweep":
+        return sweep_references(time.time())
     cfg = get_config(name)
     t0 = time.time()
     common = dict(n_freq=cfg.n_freq, n_pade=cfg.n_pade, x0=cfg.x0, eta=cfg.eta)
