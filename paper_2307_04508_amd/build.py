@@ -1,8 +1,8 @@
 """Build libgwlt.so (HIP for gfx950) in-tree.
 
 Every source under csrc/ is compiled with hipcc for gfx950 into _build/ and
-linked into paper_2307_04508_amd/libgwlt.so together with rocSOLVER and
-rocBLAS.  Always recompiles (the build check must exercise the compiler).
+linked into paper_2307_04508_amd/libgwlt.so (HIP runtime only, no math
+libraries).  Always recompiles (the build check must exercise the compiler).
 """
 from __future__ import annotations
 
@@ -51,7 +51,7 @@ def build(verbose: bool = False) -> str:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-           f"-L{ROCM}/lib", "-lrocsolver", "-lrocblas", f"-Wl,-rpath,{ROCM}/lib"]
+           f"-Wl,-rpath,{ROCM}/lib"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")

@@ -78,7 +78,6 @@ struct gw_ctx_s {
   size_t stage_off = 0;
   // device flags for deferred errors: [0] screening non-SPD (freq index + 1)
   int* d_flags = nullptr;
-  void* rocblas = nullptr;               // rocblas_handle, created lazily
   // kernel timing (gw_profile_enable)
   bool prof = false;
   std::vector<ProfEvent> prof_pending;
@@ -221,6 +220,27 @@ struct TriIn {
 };
 // Largest order the on-chip reduction takes on this context's device.
 int tridiag_max_order(gw_ctx ctx);
+// Householder reduction to tridiagonal form (same outputs as tridiag_jobs)
+// of one matrix of any order, held in HBM: panels of columns, each one
+// cooperative launch, and a rank-2·panel trailing update on FP64 MFMA.
+// Asynchronous; a barrier timeout raises ctx->d_flags[1].
+gw_status tridiag_blocked(gw_ctx ctx, const TriIn& job);
+// C (+)= alpha op(A) op(B) in FP64 on MFMA (eig.hip): ak, A stored [k][m]
+// (else [m][k]); bk, B stored [k][n] (else [n][k]); all row-major.  With
+// splits > 1 the K range is cut into `splits` pieces whose products go to
+// ws ([S][M][N] per product, in order) and are summed in a fixed order into
+// C.  The products of one call share the layout and launch together, so
+// they must write disjoint C.
+struct DGemm {
+  bool ak, bk;
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K;
+  int64_t lda, ldb, ldc;
+  double alpha, beta;
+};
+gw_status dgemm_run(gw_ctx ctx, const std::vector<DGemm>& v, int splits, double* ws);
 // Workspace (WS_EIG_Y, doubles) of naf_tri_solve at order n.
 size_t tri_solve_ws_elems(int n);
 gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& jobs);

@@ -397,8 +397,6 @@ gw_status gw_create(gw_ctx* out, int device, void* hip_stream) {
   return GW_OK;
 }
 
-void gw_release_rocblas(void* h);  // naf.hip
-
 gw_status gw_destroy(gw_ctx ctx) {
   if (!ctx) return GW_OK;
   hipSetDevice(ctx->device);
@@ -409,7 +407,6 @@ gw_status gw_destroy(gw_ctx ctx) {
     if (ctx->ws[i]) hipFree(ctx->ws[i]);
   if (ctx->d_flags) hipFree(ctx->d_flags);
   if (ctx->stage_host) hipHostFree(ctx->stage_host);
-  if (ctx->rocblas) gw_release_rocblas(ctx->rocblas);
   for (auto& e : ctx->prof_pending) {
     hipEventDestroy(e.a);
     hipEventDestroy(e.b);

@@ -574,22 +574,7 @@ namespace gw {
 constexpr int kTriBackNb = 256;       // reflectors per compact-WY block
 static_assert(kTriBackNb % kLeaf == 0, "block of reflectors: whole leaves");
 
-// C (+)= alpha op(A) op(B): ak, A stored [k][m] (else [m][k]); bk, B stored
-// [k][n] (else [n][k]); all row-major.  With splits > 1 the K range is cut
-// into `splits` pieces whose products go to ws ([S][M][N] per product, in
-// order) and are summed in a fixed order into C.  The products of one call
-// share the layout and launch together.
-struct DGemm {
-  bool ak, bk;
-  const double* A;
-  const double* B;
-  double* C;
-  int M, N, K;
-  int64_t lda, ldb, ldc;
-  double alpha, beta;
-};
-
-static gw_status dgemm_run(gw_ctx ctx, const std::vector<DGemm>& v, int splits, double* ws) {
+gw_status dgemm_run(gw_ctx ctx, const std::vector<DGemm>& v, int splits, double* ws) {
   if (v.empty()) return GW_OK;
   const bool ak = v[0].ak, bk = v[0].bk;
   std::vector<G64> descs;

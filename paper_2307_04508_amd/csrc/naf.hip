@@ -6,16 +6,13 @@
 //  * Eigendecomposition of K in FP64 on the device: Householder reduction to
 //    tridiagonal form held on chip (tridiag.hip), then bisection, inverse
 //    iteration and the back-transformation of the kept eigenvectors in
-//    blocks of reflectors (eig.hip); past the on-chip limit, rocSOLVER
-//    syevd.  The kept
+//    blocks of reflectors (eig.hip); past the on-chip limit the reduction
+//    runs in HBM by panels (tridiag.hip).  The kept
 //    eigenvectors (eigenvalue > eps_NAF, at most max_keep) are copied in
 //    descending order into U (row p = p-th eigenvector).
 //  * Transform R~ = R U (Eq. 13): a GEMM with both operands contiguous along
 //    the auxiliary index; FP32 MFMA with FP64 partial sums every 256 terms,
 //    or FP64 MFMA.
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
-
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -28,7 +25,6 @@ namespace gw {
 gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const double* d_e,
                         const double* d_tau, double eps_naf, int max_keep, double* U,
                         std::vector<double>& ev, int* keep_out);
-rocblas_handle naf_rocblas(gw_ctx ctx);
 // Synchronises; GW_EDEVICE if a tridiagonalisation barrier timed out.
 gw_status check_tridiag(gw_ctx ctx);
 gw_status gemm_f32_direct(gw_ctx ctx, const std::vector<NafGemmJob>& jobs, const char* prof);
@@ -42,63 +38,6 @@ constexpr int NT = 256;
 inline int grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
-}
-
-// U[p][:] = eigenvector of the p-th largest eigenvalue.  syevd leaves the
-// eigenvectors in the rows of V (column-major output of a symmetric input)
-// in ascending order.
-// Batched NAF: metric K (lower triangle, [A][A]) copied into a padded
-// [Ap][Ap] matrix with a decoupled -1 diagonal block; after the solve the
-// eigenvectors of the A largest eigenvalues are taken back, descending, as
-// rows of U [A][A] (their padded components are exact zeros: the block
-// structure is preserved exactly by the reduction to tridiagonal form).
-struct PadArgs {
-  const double* K;      // [A][A] lower triangle
-  int A, Ap;
-  double* Kp;           // [Ap][Ap] (column-major = row-major, symmetric)
-  const double* V;      // [Ap][Ap] eigenvectors as rows (column-major solve output)
-  double* U;            // [A][A]
-};
-
-__device__ __forceinline__ void pad_elem(const PadArgs& a, int64_t idx) {
-  if (idx >= (int64_t)a.Ap * a.Ap) return;
-  const int p = (int)(idx / a.Ap), q = (int)(idx % a.Ap);
-  double v;
-  if (p < a.A && q < a.A)
-    v = p >= q ? a.K[(int64_t)p * a.A + q] : a.K[(int64_t)q * a.A + p];
-  else
-    v = p == q ? -1.0 : 0.0;
-  a.Kp[idx] = v;
-}
-
-__global__ void pad_batched_kernel(Batch bt) {
-  PadArgs a;
-  int64_t first;
-  if (!block_of(bt, a, first)) return;
-  for (int e = 0; e < kBatchElems; e += 256) pad_elem(a, first + e + threadIdx.x);
-}
-
-__device__ __forceinline__ void unpad_elem(const PadArgs& a, int64_t idx) {
-  if (idx >= (int64_t)a.A * a.A) return;
-  const int p = (int)(idx / a.A), c = (int)(idx % a.A);
-  a.U[idx] = a.V[(int64_t)(a.Ap - 1 - p) * a.Ap + c];
-}
-
-__global__ void unpad_batched_kernel(Batch bt) {
-  PadArgs a;
-  int64_t first;
-  if (!block_of(bt, a, first)) return;
-  for (int e = 0; e < kBatchElems; e += 256) unpad_elem(a, first + e + threadIdx.x);
-}
-
-__global__ void reorder_kernel(const double* __restrict__ V, int n, int rows,
-                               double* __restrict__ U) {
-  const int64_t total = (int64_t)rows * n;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = idx / n, c = idx % n;
-    U[idx] = V[(int64_t)(n - 1 - p) * n + c];
-  }
 }
 
 struct GemmArgs {
@@ -444,9 +383,6 @@ __global__ __launch_bounds__(NT, 1) void nt_gemm_f64_kernel(GemmArgs g0, Batch b
 
 }  // namespace
 
-extern "C" void gw_release_rocblas(void* h) {
-  if (h) rocblas_destroy_handle(static_cast<rocblas_handle>(h));
-}
 
 extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
                                      int64_t n_oo_rows, const void* R_oo, int64_t n_ov_rows,
@@ -487,39 +423,19 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
   const int pe = gw::prof_begin(ctx);
   std::vector<double> ev(n_aux);
   int keep = 0;
+  // reduction to tridiagonal form: held on chip up to the register limit,
+  // in HBM by panels past it; then the eigenpairs of the tridiagonal matrix
+  // and only the kept eigenvectors back-transformed
+  const gw::TriIn tj{K, n_aux, d_eval, d_e, d_tau};
   if (n_aux <= gw::tridiag_max_order(ctx)) {
-    // on-chip reduction to tridiagonal form, its eigenpairs, and only the
-    // kept eigenvectors back-transformed
     const int pt = gw::prof_begin(ctx);
-    GW_TRY(gw::tridiag_jobs(ctx, {gw::TriIn{K, n_aux, d_eval, d_e, d_tau}}));
+    GW_TRY(gw::tridiag_jobs(ctx, {tj}));
     gw::prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
-    GW_TRY(gw::check_tridiag(ctx));
-    GW_TRY(gw::naf_tri_solve(ctx, K, n_aux, d_eval, d_e, d_tau, eps_naf, max_keep, U, ev, &keep));
   } else {
-    // larger orders: rocSOLVER syevd, ascending, eigenvectors in K's columns
-    rocblas_handle h = gw::naf_rocblas(ctx);
-    if (!h) return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocblas_create_handle failed");
-    rocblas_int* d_info = reinterpret_cast<rocblas_int*>(ws + 3 * n_aux);
-    const rocblas_status rs = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_lower,
-                                               n_aux, K, n_aux, d_eval, d_e, d_info);
-    if (rs != rocblas_status_success)
-      return gw::fail(ctx, GW_EDEVICE, "gw_naf_compress: rocsolver_dsyevd failed (%d)", (int)rs);
-    rocblas_int info = 0;
-    GW_HIP(ctx, hipMemcpyAsync(ev.data(), d_eval, n_aux * sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    GW_HIP(ctx, hipMemcpyAsync(&info, d_info, sizeof info, hipMemcpyDeviceToHost, ctx->stream));
-    GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (info != 0)
-      return gw::fail(ctx, GW_ENOCONV, "gw_naf_compress: eigensolver info = %d", (int)info);
-    std::reverse(ev.begin(), ev.end());
-    while (keep < n_aux && ev[keep] > eps_naf) ++keep;
-    if (max_keep > 0) keep = std::min(keep, max_keep);
-    if (keep > 0) {
-      hipLaunchKernelGGL(reorder_kernel, dim3(grid_for((int64_t)keep * n_aux, 256)), dim3(256), 0,
-                         ctx->stream, K, n_aux, keep, U);
-      GW_TRY(gw::launch_check(ctx, "reorder_kernel"));
-    }
+    GW_TRY(gw::tridiag_blocked(ctx, tj));
   }
+  GW_TRY(gw::check_tridiag(ctx));
+  GW_TRY(gw::naf_tri_solve(ctx, K, n_aux, d_eval, d_e, d_tau, eps_naf, max_keep, U, ev, &keep));
   gw::prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
   *n_naf = keep;
   if (eigvals) std::copy(ev.begin(), ev.end(), eigvals);
@@ -572,36 +488,19 @@ gw_status check_tridiag(gw_ctx ctx) {
   return GW_OK;
 }
 
-rocblas_handle naf_rocblas(gw_ctx ctx) {
-  if (!ctx->rocblas) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
-    ctx->rocblas = h;
-  }
-  rocblas_handle h = static_cast<rocblas_handle>(ctx->rocblas);
-  rocblas_set_stream(h, ctx->stream);
-  return h;
-}
-
 // Eigendecompositions of several metrics.  K[d] (lower triangle) is read;
 // U[d] receives the needed eigenvectors as rows, descending (at least those
 // above eps_naf, up to max_keep); eig[d] (host, descending) all eigenvalues.
-// Orders within the on-chip limit: every metric copied and mirrored, all
-// reduced to tridiagonal form together (packed cooperative launches), then
-// bisection, inverse iteration and back-transformation per metric.  Larger
-// orders: buckets of similar size, each one strided-batched rocSOLVER syevd
-// over padded copies.  Synchronises.
-static gw_status naf_eig_dsyevd_buckets(gw_ctx ctx, const std::vector<NafEigJob>& jobs);
-
-gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& all) {
-  std::vector<NafEigJob> big, small;
+// Every metric is copied and mirrored; those within the on-chip limit are
+// reduced to tridiagonal form together (packed cooperative launches), the
+// larger ones one by one in HBM; then bisection, inverse iteration and the
+// back-transformation per metric.  Synchronises.
+gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs) {
+  if (jobs.empty()) return GW_OK;
   const int lim = tridiag_max_order(ctx);
-  for (const NafEigJob& j : all) (j.A <= lim ? small : big).push_back(j);
-  GW_TRY(naf_eig_dsyevd_buckets(ctx, big));
-  if (small.empty()) return GW_OK;
   size_t k_tot = 0, v_tot = 0;
   int a_max = 0;
-  for (const NafEigJob& j : small) {
+  for (const NafEigJob& j : jobs) {
     k_tot += (size_t)j.A * j.A;
     v_tot += (size_t)j.A;
     a_max = std::max(a_max, j.A);
@@ -610,26 +509,31 @@ gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& all) {
   double* dv = static_cast<double*>(ws_get(ctx, WS_B_EIG, (3 * v_tot + 8) * sizeof(double)));
   if (!Kt || !dv) return GW_ENOMEM;
   if (!ws_get(ctx, WS_EIG_Y, tri_solve_ws_elems(a_max) * sizeof(double))) return GW_ENOMEM;
-  std::vector<TriIn> tri;
+  std::vector<TriIn> tri, small;
   std::vector<MirrorJob> mir;
   size_t ko = 0, vo = 0;
-  for (const NafEigJob& j : small) {
+  for (const NafEigJob& j : jobs) {
     GW_HIP(ctx, hipMemcpyAsync(Kt + ko, j.K, (size_t)j.A * j.A * sizeof(double),
                                hipMemcpyDeviceToDevice, ctx->stream));
     mir.push_back(MirrorJob{Kt + ko, 1, j.A});
     tri.push_back(TriIn{Kt + ko, j.A, dv + vo, dv + v_tot + vo, dv + 2 * v_tot + vo});
+    if (j.A <= lim) small.push_back(tri.back());
     ko += (size_t)j.A * j.A;
     vo += (size_t)j.A;
   }
   GW_TRY(mirror_lower_batched(ctx, mir));
   const int pe = prof_begin(ctx);
-  const int pt = prof_begin(ctx);
-  GW_TRY(tridiag_jobs(ctx, tri));
-  prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
+  if (!small.empty()) {
+    const int pt = prof_begin(ctx);
+    GW_TRY(tridiag_jobs(ctx, small));
+    prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
+  }
+  for (const TriIn& t : tri)
+    if (t.n > lim) GW_TRY(tridiag_blocked(ctx, t));
   GW_TRY(check_tridiag(ctx));
   std::vector<double> ev;
-  for (size_t d = 0; d < small.size(); ++d) {
-    const NafEigJob& j = small[d];
+  for (size_t d = 0; d < jobs.size(); ++d) {
+    const NafEigJob& j = jobs[d];
     int keep = 0;
     GW_TRY(naf_tri_solve(ctx, tri[d].K, j.A, tri[d].d, tri[d].e, tri[d].tau, j.eps_naf,
                          j.max_keep, j.U, ev, &keep));
@@ -637,96 +541,6 @@ gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& all) {
   }
   prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return GW_OK;
-}
-
-static gw_status naf_eig_dsyevd_buckets(gw_ctx ctx, const std::vector<NafEigJob>& jobs) {
-  const int n = (int)jobs.size();
-  if (n == 0) return GW_OK;
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return jobs[x].A > jobs[y].A; });
-  // greedy buckets, largest first: add a job while the padded cubic cost of
-  // the bucket stays within 25% of its unpadded cost
-  struct Bucket { int Ap; std::vector<int> ids; };
-  std::vector<Bucket> buckets;
-  for (int id : order) {
-    const double a3 = std::pow((double)jobs[id].A, 3);
-    if (!buckets.empty()) {
-      Bucket& b = buckets.back();
-      double cost = 0;
-      for (int j : b.ids) cost += std::pow((double)jobs[j].A, 3);
-      cost += a3;
-      if ((double)(b.ids.size() + 1) * std::pow((double)b.Ap, 3) <= 1.25 * cost) {
-        b.ids.push_back(id);
-        continue;
-      }
-    }
-    buckets.push_back(Bucket{jobs[id].A, {id}});
-  }
-  size_t kp_tot = 0, ev_tot = 0;
-  for (const Bucket& b : buckets) {
-    kp_tot += b.ids.size() * (size_t)b.Ap * b.Ap;
-    ev_tot += b.ids.size() * (size_t)b.Ap;
-  }
-  double* Kp = static_cast<double*>(ws_get(ctx, WS_B_K, kp_tot * sizeof(double)));
-  double* ev = static_cast<double*>(
-      ws_get(ctx, WS_B_EIG, (2 * ev_tot + (size_t)n + 8) * sizeof(double)));
-  if (!Kp || !ev) return GW_ENOMEM;
-  double* E = ev + ev_tot;
-  rocblas_int* info = reinterpret_cast<rocblas_int*>(ev + 2 * ev_tot);
-  rocblas_handle h = naf_rocblas(ctx);
-  if (!h) return fail(ctx, GW_EDEVICE, "rocblas_create_handle failed");
-  std::vector<PadArgs> pads(n);
-  std::vector<int64_t> pad_n(n), un_n(n);
-  std::vector<size_t> ev_off(n);
-  size_t ko = 0, eo = 0, io = 0;
-  std::vector<std::pair<size_t, size_t>> bucket_at;   // (Kp offset, ev offset)
-  for (const Bucket& b : buckets) {
-    bucket_at.push_back({ko, eo});
-    for (int id : b.ids) {
-      pads[id] = PadArgs{jobs[id].K, jobs[id].A, b.Ap, Kp + ko, Kp + ko, jobs[id].U};
-      pad_n[id] = (int64_t)b.Ap * b.Ap;
-      un_n[id] = (int64_t)jobs[id].A * jobs[id].A;
-      ev_off[id] = eo;
-      ko += (size_t)b.Ap * b.Ap;
-      eo += b.Ap;
-    }
-  }
-  GW_TRY(elementwise_batched(ctx, pads, pad_n, pad_batched_kernel, "pad_batched_kernel"));
-  const int pe = prof_begin(ctx);
-  for (size_t bi = 0; bi < buckets.size(); ++bi) {
-    const Bucket& b = buckets[bi];
-    const rocblas_stride sA = (rocblas_stride)b.Ap * b.Ap;
-    rocblas_status rs = rocsolver_dsyevd_strided_batched(
-        h, rocblas_evect_original, rocblas_fill_lower, b.Ap, Kp + bucket_at[bi].first, b.Ap, sA,
-        ev + bucket_at[bi].second, b.Ap, E + bucket_at[bi].second, b.Ap, info + io,
-        (rocblas_int)b.ids.size());
-    if (rs != rocblas_status_success)
-      return fail(ctx, GW_EDEVICE, "rocsolver_dsyevd_strided_batched failed (%d)", (int)rs);
-    io += b.ids.size();
-  }
-  prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
-  GW_TRY(elementwise_batched(ctx, pads, un_n, unpad_batched_kernel, "unpad_batched_kernel"));
-  std::vector<double> hev(ev_tot);
-  std::vector<rocblas_int> hinfo(n);
-  GW_HIP(ctx, hipMemcpyAsync(hev.data(), ev, ev_tot * sizeof(double), hipMemcpyDeviceToHost,
-                             ctx->stream));
-  GW_HIP(ctx, hipMemcpyAsync(hinfo.data(), info, n * sizeof(rocblas_int), hipMemcpyDeviceToHost,
-                             ctx->stream));
-  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < n; ++i)
-    if (hinfo[i] != 0) return fail(ctx, GW_ENOCONV, "batched eigensolver info = %d", (int)hinfo[i]);
-  for (int id = 0; id < n; ++id) {
-    const int A = jobs[id].A;
-    int Ap = 0;
-    for (const Bucket& b : buckets)
-      for (int j : b.ids)
-        if (j == id) Ap = b.Ap;
-    // ascending; the top A belong to the molecule (padding sits at -1)
-    for (int p = 0; p < A; ++p) jobs[id].eig[p] = hev[ev_off[id] + Ap - 1 - p];
-  }
   return GW_OK;
 }
 

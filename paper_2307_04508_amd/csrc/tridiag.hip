@@ -291,6 +291,281 @@ __global__ __launch_bounds__(TNT, 1) void tridiag_kernel(const TriJob* __restric
   }
 }
 
+// ---------------------------------------------------------------- blocked
+// Orders past the on-chip limit: the matrix stays in HBM (full symmetric
+// storage) and is reduced in panels of HB columns (the LAPACK dsytrd /
+// dlatrd scheme).  Within a panel the trailing matrix keeps its values at
+// the panel start; column k is corrected by the panel's earlier reflectors,
+//   a = A(k:, k) - V W(k, :)^T - W V(k, :)^T,
+// its Householder vector v taken, and
+//   w = tau (A22 v - V (W^T v) - W (V^T v)),  w -= (tau / 2)(w^T v) v
+// stored as a column of W.  After the panel, A22 -= V W^T + W V^T on FP64
+// MFMA.  One cooperative launch per panel, two device-wide barriers per
+// column: (1) the corrected column and its partial norms, (2) A22 v and the
+// partial products W^T v, V^T v and v^T A22 v, from which every workgroup
+// finishes w on its rows (yhat^T v = v^T A22 v - 2 (W^T v).(V^T v)).
+// Workgroup g owns rows g, g + G, ...: thread t of it row g + G t in the
+// row-wise phases; in A22 v each wave takes every fourth owned row and its
+// lanes stride over the row, with v staged in LDS in chunks.  Values that
+// cross workgroups are written and read with device-scope atomic accesses
+// (as in the on-chip kernel); the matrix itself is read with plain loads
+// (nothing writes the trailing rows during a launch).
+constexpr int HB = 32;            // panel width (columns)
+constexpr int HT = 512;           // threads per workgroup
+constexpr int HCH = 8192;         // v chunk staged in LDS (doubles)
+constexpr int HB2 = 2 * HB;       // row stride of the panel buffers
+constexpr int HRED = 2 * HB + 2;  // per-workgroup partials: norm, W^T v, V^T v, v^T A22 v
+
+struct HbmArgs {
+  double* K;          // [n][n]; out: reflector k in K[k n + i], i >= k + 2
+  int n, k0, jb;      // panel columns k0 .. k0 + jb - 1
+  int last;           // this panel holds reflector n - 2 (also sets d[n - 1])
+  double* d;
+  double* e;
+  double* tau;
+  double* VW;         // [n][2 HB]: V in columns 0 .. HB-1, W in HB .. 2 HB-1
+  double* WV;         // [n][2 HB]: the same with the halves swapped
+  double* abuf;       // [HB][n] corrected column j of the panel in row j
+  double* ybuf;       // [n] A22 v, then the corrected y
+  double* red;        // [G][HRED]
+  unsigned* count;    // barrier counters, zero before the first panel
+  unsigned pass0;     // barriers passed by the earlier panels
+  int* err;
+  int spin_limit;
+};
+
+// Sum over the workgroup, result in every thread (deterministic order).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_total(v);
+  __syncthreads();
+  if (lane == kLastLane) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < HT / 64; ++q) t += sh[q];
+  return t;
+}
+
+// Sum over workgroups of red[g][col] for cols in [c0, c0 + nc) (nc <= 64),
+// into out[0 .. nc) in LDS: thread (col, q) sums workgroups q, q + 4, ...
+// (loads issued 16 at a time), then the four partials in order.
+__device__ __forceinline__ void sum_partials(const double* red, int G, int c0, int nc,
+                                             double* part, double* out) {
+  const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+  double s = 0.0;
+  if (c < nc) {
+    for (int g0 = q; g0 < G; g0 += 16 * (HT / 64)) {
+      double t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int g = g0 + u * (HT / 64);
+        t[u] = g < G ? ld_dev(&red[(size_t)g * HRED + c0 + c]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += t[u];
+    }
+  }
+  part[q * 64 + c] = s;
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < HT / 64; ++r) t += part[r * 64 + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// Sum over workgroups of red[g][col] for one column, in every thread.
+__device__ __forceinline__ double sum_column(const double* red, int G, int col, double* sh) {
+  double s = 0.0;
+  for (int g = threadIdx.x; g < G; g += HT) s += ld_dev(&red[(size_t)g * HRED + col]);
+  return block_sum(s, sh);
+}
+
+constexpr int HROWS = 128;        // rows per workgroup (n <= HROWS x workgroups)
+
+__global__ __launch_bounds__(HT) void tri_hbm_panel_kernel(HbmArgs a) {
+  __shared__ double vch[HCH];
+  __shared__ double own[HROWS * HB2];               // own rows of [V | W] for this panel
+  __shared__ double ownY[HROWS];                    // own rows of y (raw, then corrected)
+  __shared__ double part[HT];
+  __shared__ double sh[HT / 64];
+  __shared__ double rowV[HB], rowW[HB], sWV[2 * HB];
+  __shared__ int s_ok;
+  const int g = blockIdx.x, G = gridDim.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int n = a.n;
+  const int R = (n - g + G - 1) / G;                // rows owned (<= HROWS)
+  const int my = g + G * tid;                       // row of this thread in row-wise phases
+  const bool mine = tid < R;                        // (my < n)
+  double* ow = own + (size_t)(mine ? tid : 0) * HB2;
+  unsigned pass = a.pass0;
+  double tau_p = 0.0;                               // previous column's tau
+  // Each column's corrected values go to a region of abuf of their own,
+  // written once per launch (device-scope stores, which bypass the
+  // per-XCD L2), so after the barrier the other workgroups read them with
+  // plain loads: no cache holds an older copy once the caches are
+  // invalidated here, at the start of the launch.
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  for (int j = 0; j <= a.jb; ++j) {
+    const int k = a.k0 + j;
+    double* acol = a.abuf + (size_t)j * n;
+    // ---- phase 1: finish w of column j - 1 (jp), correct column k.
+    // From the previous barrier: sWV = [W^T v, V^T v, v^T A22 v], so that
+    // yhat = y - V (W^T v) - W (V^T v) and yhat^T v = v^T A22 v - 2 (W^T v).(V^T v)
+    const int jp = j - 1;
+    double c_p = 0.0;
+    if (j > 0) {
+      sum_partials(a.red, G, 1, 2 * jp + 1, part, sWV);
+      double cross = 0.0;
+      for (int q = 0; q < jp; ++q) cross += sWV[q] * sWV[jp + q];
+      c_p = 0.5 * tau_p * tau_p * (sWV[2 * jp] - 2.0 * cross);
+    }
+    if (tid < j) {
+      rowV[tid] = ld_dev(&a.VW[(size_t)k * HB2 + tid]);
+      if (tid < jp) rowW[tid] = ld_dev(&a.VW[(size_t)k * HB2 + HB + tid]);
+    }
+    __syncthreads();
+    if (j > 0 && tid == 0) {
+      // row k of the just-finished column, from its raw y (v_k = 1)
+      double y = ld_dev(&a.ybuf[k]);
+      for (int q = 0; q < jp; ++q) y -= rowV[q] * sWV[q] + rowW[q] * sWV[jp + q];
+      rowW[jp] = tau_p * y - c_p;
+    }
+    if (j > 0 && mine && my >= k) {
+      double y = ownY[tid];
+      for (int q = 0; q < jp; ++q) y -= ow[q] * sWV[q] + ow[HB + q] * sWV[jp + q];
+      const double wi = tau_p * y - c_p * ow[jp];
+      ow[HB + jp] = wi;
+      st_dev(&a.VW[(size_t)my * HB2 + HB + jp], wi);
+      st_dev(&a.WV[(size_t)my * HB2 + jp], wi);
+    }
+    __syncthreads();
+    if (j == a.jb) {
+      // after the panel's last column: the final diagonal entry
+      if (a.last && mine && my == n - 1) {
+        double x = a.K[(size_t)(n - 1) * n + (n - 1)];
+        for (int q = 0; q < j; ++q) x -= ow[q] * rowW[q] + ow[HB + q] * rowV[q];
+        a.d[n - 1] = x;
+      }
+      break;
+    }
+    double ai = 0.0, nrm = 0.0;
+    if (mine && my >= k) {
+      double x = a.K[(size_t)my * n + k];
+      for (int q = 0; q < j; ++q) x -= ow[q] * rowW[q] + ow[HB + q] * rowV[q];
+      ai = x;
+      st_dev(&acol[my], x);
+      if (my >= k + 2) nrm = x * x;
+    }
+    nrm = block_sum(nrm, sh);
+    if (tid == 0) st_dev(&a.red[(size_t)g * HRED], nrm);
+    if (!group_barrier(a.count, g, G, ++pass, a.err, a.spin_limit, &s_ok)) return;
+    // ---- phase 2: Householder vector, A22 v, partial W^T v, V^T v, v^T A22 v
+    const double xn2 = sum_column(a.red, G, 0, sh);
+    const double alpha = acol[k + 1];
+    double beta = alpha, t = 0.0, scal = 0.0;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      t = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (g == 0 && tid == 0) {
+      a.d[k] = acol[k];
+      a.e[k] = beta;
+      a.tau[k] = t;
+    }
+    const int lo = k + 1;
+    if (mine && my >= lo) {
+      const double vi = my == lo ? 1.0 : ai * scal;
+      ow[j] = vi;
+      st_dev(&a.VW[(size_t)my * HB2 + j], vi);
+      st_dev(&a.WV[(size_t)my * HB2 + HB + j], vi);
+      if (my >= k + 2) a.K[(size_t)k * n + my] = vi;
+    }
+    // A22 v over rows and columns >= k + 1, v staged in LDS chunk by chunk;
+    // row r of the workgroup's own rows is summed by wave r % (HT / 64) and
+    // kept in lane r / (HT / 64) of it
+    double yacc = 0.0;
+    for (int c0 = lo; c0 < n; c0 += HCH) {
+      const int c1 = min(n, c0 + HCH);
+      __syncthreads();
+      for (int l0 = c0 + tid; l0 < c1; l0 += 8 * HT) {
+        double t8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int l = l0 + u * HT;
+          t8[u] = (l < c1 && l > lo) ? acol[l] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int l = l0 + u * HT;
+          if (l < c1) vch[l - c0] = l == lo ? 1.0 : t8[u] * scal;
+        }
+      }
+      __syncthreads();
+      for (int r = wave; r < R; r += HT / 64) {
+        const int i = g + G * r;
+        if (i < lo) continue;
+        const double* row = a.K + (size_t)i * n;
+        // eight independent partial sums keep eight loads in flight per
+        // lane (the pass is bound by memory latency times the loads in flight)
+        double p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = 0.0;
+        int l = c0 + lane;
+        for (; l + 7 * 64 < c1; l += 8 * 64) {
+          double x[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) x[u] = row[l + u * 64];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) p[u] += x[u] * vch[l + u * 64 - c0];
+        }
+        for (; l < c1; l += 64) p[0] += row[l] * vch[l - c0];
+        double s = wave_total(((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
+        const double sr = __shfl(s, kLastLane);
+        if (lane == r / (HT / 64)) yacc += sr;
+      }
+    }
+    {
+      const int r = (HT / 64) * lane + wave;         // the row this lane accumulated
+      const int i = g + G * r;
+      if (r < R) {
+        ownY[r] = yacc;
+        if (i >= lo) st_dev(&a.ybuf[i], yacc);
+      }
+    }
+    __syncthreads();
+    // partials over own rows: W^T v (0 .. j-1), V^T v (j .. 2j-1), v^T y (2j)
+    {
+      const int c = tid & 63, q = tid >> 6;
+      double sacc = 0.0;
+      if (c <= 2 * j) {
+        for (int r = q; r < R; r += HT / 64) {
+          const int i = g + G * r;
+          if (i < lo) continue;
+          const double vr = own[(size_t)r * HB2 + j];
+          const double x = c < j ? own[(size_t)r * HB2 + HB + c]
+                                 : (c < 2 * j ? own[(size_t)r * HB2 + c - j] : ownY[r]);
+          sacc += x * vr;
+        }
+      }
+      part[q * 64 + c] = sacc;
+      __syncthreads();
+      if (tid <= 2 * j) {
+        double u = 0.0;
+#pragma unroll
+        for (int q2 = 0; q2 < HT / 64; ++q2) u += part[q2 * 64 + tid];
+        st_dev(&a.red[(size_t)g * HRED + 1 + tid], u);
+      }
+    }
+    tau_p = t;
+    if (!group_barrier(a.count, g, G, ++pass, a.err, a.spin_limit, &s_ok)) return;
+  }
+}
+
 template <int C>
 void* tridiag_fn() {
   return reinterpret_cast<void*>(&tridiag_kernel<C>);
@@ -391,6 +666,54 @@ gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in) {
     void* args[] = {&dj, &nj, &err, &spin};
     GW_HIP(ctx, hipLaunchCooperativeKernel(fn, dim3(wg), dim3(TNT), args, 0, ctx->stream));
   }
+  return GW_OK;
+}
+
+gw_status tridiag_blocked(gw_ctx ctx, const TriIn& job) {
+  const int n = job.n;
+  if (n < 1) return fail(ctx, GW_EINVAL, "tridiag_blocked: order %d", n);
+  if (n == 1) {
+    GW_HIP(ctx, hipMemcpyAsync(job.d, job.K, sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    return GW_OK;
+  }
+  int n_cu = 0, per_cu = 0;
+  GW_HIP(ctx, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  GW_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &per_cu, reinterpret_cast<const void*>(&tri_hbm_panel_kernel), HT, 0));
+  if (per_cu < 1) return fail(ctx, GW_EDEVICE, "tridiag_blocked: kernel does not fit a CU");
+  const int G = std::min(n_cu, (n + 7) / 8);          // workgroups, one per CU
+  if ((int64_t)G * HROWS < n) return fail(ctx, GW_EINVAL, "tridiag_blocked: order %d too large", n);
+  const size_t ctr = (size_t)(1 + (G + kBarGroup - 1) / kBarGroup) * kCtrStride / 2;
+  const size_t sc = 2 * (size_t)n * HB2 + (size_t)(HB + 1) * n + (size_t)G * HRED + ctr;
+  double* ws = static_cast<double*>(ws_get(ctx, WS_TRI, sc * sizeof(double)));
+  if (!ws) return GW_ENOMEM;
+  double* VW = ws;
+  double* WV = VW + (size_t)n * HB2;
+  double* abuf = WV + (size_t)n * HB2;
+  double* ybuf = abuf + (size_t)HB * n;
+  double* red = ybuf + n;
+  unsigned* count = reinterpret_cast<unsigned*>(red + (size_t)G * HRED);
+  GW_TRY(fill_zero(ctx, reinterpret_cast<double*>(count), (int64_t)ctr));
+  const int pt = prof_begin(ctx);
+  unsigned pass0 = 0;
+  for (int k0 = 0; k0 < n - 1; k0 += HB) {
+    const int jb = std::min(HB, n - 1 - k0);
+    HbmArgs a{job.K, n, k0, jb, k0 + jb == n - 1 ? 1 : 0, job.d, job.e, job.tau, VW, WV, abuf,
+              ybuf, red, count, pass0, ctx->d_flags + 1, 1 << 21};
+    void* args[] = {&a};
+    GW_HIP(ctx, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&tri_hbm_panel_kernel),
+                                           dim3(G), dim3(HT), args, 0, ctx->stream));
+    pass0 += 2u * (unsigned)jb;
+    if (!a.last) {
+      // A22 -= [V W] [W V]^T over the rows and columns past the panel
+      const int kend = k0 + jb, m = n - kend;
+      GW_TRY(dgemm_run(ctx, {DGemm{false, false, VW + (size_t)kend * HB2, WV + (size_t)kend * HB2,
+                                   job.K + (size_t)kend * n + kend, m, m, HB2, HB2, HB2, n, -1.0,
+                                   1.0}},
+                       1, nullptr));
+    }
+  }
+  prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
   return GW_OK;
 }
 

@@ -417,12 +417,14 @@ def test_naf_matches_oracle(gw, ctx, tiny_problem, prec):
     assert n2 == 37
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 64, 200, 513, 1030, 3100])
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 200, 513, 1030, 3100, 3400, 4700])
 def test_naf_eigensolver_orders(gw, ctx, n):
     """Eigendecomposition of the NAF metric across orders that exercise every
     column-slot count of the on-chip tridiagonalisation (512 columns per slot,
-    the seventh slot in LDS) and the 1 x 1 and 2 x 2 cases: eigenvalues
-    against LAPACK, orthonormal eigenvectors, small residual K u = lambda u."""
+    the seventh slot in LDS), the 1 x 1 and 2 x 2 cases, and orders past the
+    on-chip limit (3328), reduced in HBM by panels of 32 columns (3400: a
+    partial last panel; 4700): eigenvalues against LAPACK, orthonormal
+    eigenvectors, small residual K u = lambda u."""
     _say(f"naf eigensolver n={n}")
     rng = np.random.default_rng(100 + n)
     m = n + 7
@@ -442,11 +444,11 @@ def test_naf_eigensolver_orders(gw, ctx, n):
     assert np.abs(res).max() < 1e-12 * scale * max(1.0, np.sqrt(n) / 8)
 
 
-def test_naf_eigensolver_degenerate_spectrum(gw, ctx):
+@pytest.mark.parametrize("n", [300, 3350])
+def test_naf_eigensolver_degenerate_spectrum(gw, ctx, n):
     """A metric with one eigenvalue of multiplicity n (columns of R already
     orthogonal): every reflector is the identity (tau = 0) and any orthonormal
-    basis is an answer."""
-    n = 300
+    basis is an answer; on chip (300) and in HBM (3350)."""
     X = np.zeros((n + 5, n))
     X[:n, :n] = np.eye(n) * 0.5
     K = torch.zeros((n, n), dtype=torch.float64, device="cuda")
