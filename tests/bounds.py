@@ -14,7 +14,10 @@ kernels accumulate:
   * BF16x3: each product as hi*hi + hi*lo + lo*hi of BF16 parts.  With
     round-to-nearest splits |x - hi| <= 2^-9 |x| and |x - hi - lo| <=
     2^-18 |x|, so the omitted lo*lo and the split residuals cost at most
-    3 * 2^-18 |x y| per product, on top of the FP32 accumulation.
+    3 * 2^-18 |x y| per product, on top of the accumulation: the SYRK sums
+    256 rows in the MFMA accumulators and adds each block into a second
+    FP32 sum (blocked summation: gamma_{256 + nb}(u32)), the split-K slices
+    in FP64.
 
 Inputs rounded from FP64 to FP32 before the call add u32 per factor (3 u32
 for a quadratic form x^T A x with x and A both rounded).
@@ -35,10 +38,9 @@ def syrk_coeff(prec, rows, block=256):
     nb = max(1, -(-rows // block)) + 16          # blocks plus the split-K partial sums
     if prec == "fp64":
         return gamma(rows + 16, U64)
-    c = gamma(block, U32) + gamma(nb, U64)
     if prec == "bf16x3":
-        c += SPLIT3
-    return c
+        return gamma(block + nb, U32) + SPLIT3
+    return gamma(block, U32) + gamma(nb, U64)
 
 
 def quadform_coeff(prec, N, rounded_inputs):
