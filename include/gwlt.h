@@ -371,6 +371,23 @@ gw_status gw_evgw(gw_ctx ctx, gw_precision prec, const gw_params* params, int n_
  * the number of kept choices. */
 gw_status gw_autotune(gw_ctx ctx, int enable, int* n_tuned);
 
+/* Restrict the launch-shape candidates of one kernel family on this context
+ * to the codes c with c % modulus == residue (modulus 0 lifts the
+ * restriction; a restriction that matches no candidate of a shape is
+ * ignored for it).  With tuning on the autotuner times the remaining
+ * candidates; with tuning off the first remaining one is used.  For tests
+ * that cover every shape, and for pinning a shape.  Families and codes:
+ *   "syrk3"  BF16x3 polarizability SYRK: 4 S + shape, S the split-K factor;
+ *            128 x 128 tiles: shape 0: 4 waves, 2 LDS stages; 1: 4 waves,
+ *            3 stages; 2: 8 waves, 2 stages; 3: 256 x 128 tiles, 8 waves,
+ *            3 stages
+ *   "syrk"   FP32 / FP64 polarizability SYRK: the split-K factor S
+ *   "screen", "screen_sos"  screening sweep: outer pivot width (64, 128, 256)
+ *   "bwb3"   BF16x3 B W B contraction: waves per workgroup
+ * Errors: GW_EINVAL for a NULL ctx or family, modulus < 0, or a residue
+ * outside [0, modulus). */
+gw_status gw_autotune_restrict(gw_ctx ctx, const char* family, int modulus, int residue);
+
 /* ----------------------------------------------------------- workspace */
 
 /* Largest sizes the per-step calls will see on a context. */

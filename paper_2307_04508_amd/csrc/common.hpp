@@ -95,6 +95,8 @@ struct gw_ctx_s {
   // launch-shape autotuner (gw_autotune): chosen candidate per shape key
   bool autotune = true;
   std::map<std::string, int> tuned;
+  // gw_autotune_restrict: family -> (modulus, residue) filter on candidates
+  std::map<std::string, std::pair<int, int>> tune_filter;
 };
 
 // A captured, instantiated graph and the arena its kernels read.
@@ -121,7 +123,10 @@ inline const T* stage_t(gw_ctx ctx, const T* host, size_t n) {
 // capturing), time trial(c) for every candidate with HIP events on the
 // context's stream and keep the fastest; later calls (and capture, or tuning
 // off: the first candidate) return the kept choice without trials.  trial
-// must be free of side effects beyond scratch, or idempotent.
+// must be free of side effects beyond scratch, or idempotent.  The family of
+// a key is its text before the first ':'; a restriction set for the family
+// keeps only the candidates c with c % modulus == residue (all of them when
+// none matches).
 int tune(gw_ctx ctx, const std::string& key, const std::vector<int>& cand,
          const std::function<gw_status(int)>& trial);
 // Begin / end a capture on the context (used by the public graph calls and

@@ -152,10 +152,19 @@ static void prof_resolve(gw_ctx ctx) {
   ctx->prof_pending.clear();
 }
 
-int tune(gw_ctx ctx, const std::string& key, const std::vector<int>& cand,
+int tune(gw_ctx ctx, const std::string& key, const std::vector<int>& all,
          const std::function<gw_status(int)>& trial) {
+  std::vector<int> cand = all;
+  auto f = ctx->tune_filter.find(key.substr(0, key.find(':')));
+  if (f != ctx->tune_filter.end()) {
+    std::vector<int> kept;
+    for (int c : all)
+      if (c % f->second.first == f->second.second) kept.push_back(c);
+    if (!kept.empty()) cand = kept;
+  }
   auto it = ctx->tuned.find(key);
-  if (it != ctx->tuned.end()) return it->second;
+  if (it != ctx->tuned.end() && std::find(cand.begin(), cand.end(), it->second) != cand.end())
+    return it->second;
   if (!ctx->autotune || ctx->capturing || cand.size() < 2) return cand.empty() ? 0 : cand[0];
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
@@ -299,6 +308,18 @@ gw_status gw_autotune(gw_ctx ctx, int enable, int* n_tuned) {
   if (enable >= 0) ctx->autotune = enable != 0;
   if (enable == 2) ctx->tuned.clear();
   if (n_tuned) *n_tuned = (int)ctx->tuned.size();
+  return GW_OK;
+}
+
+gw_status gw_autotune_restrict(gw_ctx ctx, const char* family, int modulus, int residue) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_autotune_restrict: ctx is NULL");
+  gw::clear_error(ctx);
+  if (!family || modulus < 0 || (modulus > 0 && (residue < 0 || residue >= modulus)))
+    return gw::fail(ctx, GW_EINVAL, "gw_autotune_restrict: bad family, modulus or residue");
+  if (modulus == 0)
+    ctx->tune_filter.erase(family);
+  else
+    ctx->tune_filter[family] = {modulus, residue};
   return GW_OK;
 }
 

@@ -481,10 +481,12 @@ __global__ __launch_bounds__(NTB, 2) void syrk_bf16x3_kernel(SyrkArgs a0, Batch 
 
 // ------------------------------------------------------- BF16x3, pre-split
 // The scaled rows are split once per call into workspace: Y_m[P][r] =
-// sqrt(s_m(r)) X[r][P] as BF16 hi and lo, transposed so k (the row r of X)
-// is contiguous; then M^m = Y_m Y_m^T is a plain BF16x3 SYRK over tiles
-// copied global -> LDS directly (bf16x3.hpp).  The square root splits the
-// positive scale evenly over both operands.
+// sqrt(s_m(r)) X[r][P] as BF16 hi and lo, transposed into blocks of 32 k
+// (rows r of X), each block [Npad][32], so the pipeline stage of any tile is
+// one contiguous range of the block (whole DRAM pages, few TLB entries);
+// then M^m = Y_m Y_m^T is a plain BF16x3 SYRK over tiles copied global ->
+// LDS directly (bf16x3.hpp).  The square root splits the positive scale
+// evenly over both operands.
 struct ChiSplitArgs {
   const float* X;       // rows r_base .. r_base + k_rows - 1 of [k_total][ld]
   int64_t ld;
@@ -495,13 +497,14 @@ struct ChiSplitArgs {
   float cscale;
   int64_t k_total;
   int64_t r_base;
-  __bf16* hi;           // [L][Npad][kp]
+  __bf16* hi;           // [L][kp / 32][Npad][32]: k blocks of 32, each [row][k]
   __bf16* lo;
-  int64_t kp;           // k stride of Y (rows of the chunk rounded up to BK)
+  int64_t kp;           // k extent of Y (rows of the chunk rounded up to 32)
   int Npad;
 };
 
-// 64 rows x 64 columns of X per workgroup, read once, written for every m.
+// 64 rows x 64 columns of X per workgroup, read once, written for every m
+// (Y rows start 16-byte aligned: Npad and kp are multiples of 32).
 __global__ __launch_bounds__(256) void chi_split_kernel(ChiSplitArgs a) {
   __shared__ float tile[64][65];
   __shared__ float sq[32][64];
@@ -527,29 +530,42 @@ __global__ __launch_bounds__(256) void chi_split_kernel(ChiSplitArgs a) {
       sq[m][y] = sqrtf(v);
     }
     __syncthreads();
+    // 16-byte stores of 8 consecutive k: thread t writes row P = t / 4, k
+    // r0 + 32 h + 8 (t % 4) .. + 7 of k block h, so a wave writes 1 KB of
+    // one block contiguously
+    const int P = threadIdx.x >> 2, q = threadIdx.x & 3;
     for (int m = 0; m < nm; ++m) {
-      for (int y = ty; y < 64; y += 4) {
-        const int P = p0 + y;
-        const int64_t r = r0 + tx;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int y0 = 32 * h + 8 * q;
+        const int64_t r = r0 + y0;
         if (r >= a.kp) continue;
-        __bf16 h, l;
-        b3::split(tile[tx][y] * sq[m][tx], h, l);
-        const int64_t o = (m0 + m) * mstride + (int64_t)P * a.kp + r;
-        a.hi[o] = h;
-        a.lo[o] = l;
+        b3::bf16x8 vh, vl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 hh, ll;
+          b3::split(tile[y0 + e][P] * sq[m][y0 + e], hh, ll);
+          vh[e] = hh;
+          vl[e] = ll;
+        }
+        const int64_t o = (m0 + m) * mstride + (r >> 5) * ((int64_t)a.Npad * 32) +
+                          (int64_t)(p0 + P) * 32 + (r & 31);
+        *reinterpret_cast<b3::bf16x8*>(a.hi + o) = vh;
+        *reinterpret_cast<b3::bf16x8*>(a.lo + o) = vl;
       }
     }
   }
 }
 
 struct Syrk3Args {
-  const __bf16* hi;     // [L][Npad][kp]
+  const __bf16* hi;     // [L][kp / 32][Npad][32]
   const __bf16* lo;
   int64_t kp;
   int Npad;
   int L, n_tiles, splits;
   int64_t rows_per_split;   // multiple of FLUSH_ROWS
   double* part;         // [splits][L][n_tiles][BM*BM]
+  int T;                // 128-row tiles of N (n_tiles = T (T + 1) / 2)
 };
 
 // Work units: tile fastest, then Laplace point, then split-K slice, so the
@@ -598,11 +614,13 @@ __global__ __launch_bounds__(NW * 64, MINB) void syrk_bf16x3_direct_kernel(Syrk3
 
   auto issue = [&](int it) {
     const int64_t kb = r0 + (int64_t)it * BKT;
+    const __bf16* his = hi + kb * a.Npad;          // k block kb / BKT: [Npad][BKT]
+    const __bf16* los = lo + kb * a.Npad;
     b3::StageT<BKT>& d = st[it % NBUF];
-    b3::load_tile<BKT, NW>(hi, a.kp, p0, kb, d.t[0], wave, lane);
-    b3::load_tile<BKT, NW>(lo, a.kp, p0, kb, d.t[1], wave, lane);
-    b3::load_tile<BKT, NW>(hi, a.kp, q0, kb, d.t[2], wave, lane);
-    b3::load_tile<BKT, NW>(lo, a.kp, q0, kb, d.t[3], wave, lane);
+    b3::load_tile<BKT, NW>(his, BKT, p0, 0, d.t[0], wave, lane);
+    b3::load_tile<BKT, NW>(los, BKT, p0, 0, d.t[1], wave, lane);
+    b3::load_tile<BKT, NW>(his, BKT, q0, 0, d.t[2], wave, lane);
+    b3::load_tile<BKT, NW>(los, BKT, q0, 0, d.t[3], wave, lane);
   };
   auto handover = [&](int it) {   // after stage it: stage it + 1 visible to all waves
     if (NBUF == 3 && it + 2 < nk)
@@ -639,6 +657,182 @@ __global__ __launch_bounds__(NW * 64, MINB) void syrk_bf16x3_direct_kernel(Syrk3
       for (int r = 0; r < 16; ++r) {
         const int row = ar + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int col = br + j * 32 + (lane & 31);
+        out[row * BM + col] = (double)sum[i][j][r];
+      }
+}
+
+// Wide shape: 256 rows of P x 128 rows of Q per workgroup, 8 waves of
+// 64 x 64 (two per SIMD), one workgroup per CU, three LDS stages of 48 KB.
+// The CU copies 48 KB of operands into LDS per 2^21 MFMA flops, against
+// 64 KB in the 128 x 128 shapes (two workgroups of 32 KB per 2^20).  The
+// operand fragments are software-pipelined through two register sets: the
+// LDS reads of k step t + 1 are issued before the MFMAs of step t, and the
+// stage hand-over sits between the last reads of a stage and the first reads
+// of the next.
+// Units per (slice, point): 256-row tile rows I2 and 128-column tile
+// columns J < min(2 I2 + 2, T); the two 128 x 128 halves of a unit are the
+// lower tiles (2 I2, J) (when J <= 2 I2) and (2 I2 + 1, J) (when
+// 2 I2 + 1 < T) of the partial layout.  The waves of a half that is not a
+// lower tile, and the wave of the upper 64 x 64 block of a diagonal tile,
+// only take part in the copies and barriers, so the other wave on their
+// SIMD runs alone.  Each accumulator sees the same product order as in the
+// 128 x 128 shapes.  Needs the split rows padded to a multiple of 256.
+__global__ __launch_bounds__(512, 1) void syrk_bf16x3_wide_kernel(Syrk3Args a) {
+  constexpr int NBUF = 3, BKT = 32, WI = 2, WJ = 2;
+  struct WideStage {
+    __bf16 a[2][2 * BM * BKT];   // hi, lo of 256 P rows (two swizzled 128-row tiles)
+    __bf16 b[2][BM * BKT];       // hi, lo of 128 Q rows
+  };
+  struct Frag {
+    b3::bf16x8 ah[WI], al[WI], bh[WJ], bl[WJ];
+  };
+  __shared__ __attribute__((aligned(16))) WideStage st[NBUF];
+  const int T = a.T, T2 = (a.T + 1) / 2;
+  int per = 0;                                   // units per (slice, point)
+  for (int i = 0; i < T2; ++i) per += min(2 * i + 2, T);
+  const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int u = (int)(lid % per);
+  const int m = (int)((lid / per) % a.L);
+  const int s = (int)(lid / ((int64_t)per * a.L));
+  int I2 = 0, J = u;
+  while (J >= min(2 * I2 + 2, T)) {
+    J -= min(2 * I2 + 2, T);
+    ++I2;
+  }
+  const int64_t p0 = (int64_t)I2 * 2 * BM, q0 = (int64_t)J * BM;
+  const int64_t r0 = (int64_t)s * a.rows_per_split;
+  const int64_t r1 = min(r0 + a.rows_per_split, a.kp);
+  const int nk = r1 > r0 ? (int)((r1 - r0) / BKT) : 0;
+  const int64_t mo = (int64_t)m * a.Npad * a.kp;
+  const __bf16* hi = a.hi + mo;
+  const __bf16* lo = a.lo + mo;
+  // the wave index as a scalar, so the idle-half branches are scalar branches
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;       // P rows 64 wr .., Q rows 64 wc ..
+  const int half = wr >> 1;                      // the 128-row half of P of the wave
+  const int ti = 2 * I2 + half;                  // its tile row
+  // idle: not a lower tile, or the wholly upper 64 x 64 block of a diagonal
+  // tile (the reduction reads only the lower triangle)
+  const bool idle = ti >= T || J > ti || (J == ti && (wr & 1) == 0 && wc == 1);
+
+  f32x16 acc[WI][WJ], sum[WI][WJ];
+#pragma unroll
+  for (int i = 0; i < WI; ++i)
+#pragma unroll
+    for (int j = 0; j < WJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { acc[i][j][r] = 0.f; sum[i][j][r] = 0.f; }
+
+  // one copy instruction per wave per 128-row tile, 6 per stage
+  auto issue = [&](int it) {
+    const int64_t kb = r0 + (int64_t)it * BKT;
+    const __bf16* his = hi + kb * a.Npad;          // k block kb / BKT: [Npad][BKT]
+    const __bf16* los = lo + kb * a.Npad;
+    WideStage& d = st[it % NBUF];
+    b3::load_tile<BKT, 8>(his, BKT, p0, 0, d.a[0], wave, lane);
+    b3::load_tile<BKT, 8>(his, BKT, p0 + BM, 0, d.a[0] + BM * BKT, wave, lane);
+    b3::load_tile<BKT, 8>(los, BKT, p0, 0, d.a[1], wave, lane);
+    b3::load_tile<BKT, 8>(los, BKT, p0 + BM, 0, d.a[1] + BM * BKT, wave, lane);
+    b3::load_tile<BKT, 8>(his, BKT, q0, 0, d.b[0], wave, lane);
+    b3::load_tile<BKT, 8>(los, BKT, q0, 0, d.b[1], wave, lane);
+  };
+  // at the hand-over of stage it + 1 the copies of stage it + 2 may stay in
+  // flight
+  auto handover = [&](int it) {
+    if (it + 2 < nk)
+      asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  };
+  if (idle) {   // copies and the same barriers as the other waves, nothing else
+    if (nk > 0) {
+      issue(0);
+      if (nk > 1) issue(1);
+      handover(-1);
+    }
+    for (int it = 0; it + 1 < nk; ++it) {
+      if (it + 2 < nk) issue(it + 2);
+      handover(it);
+    }
+    return;
+  }
+  auto read = [&](Frag& f, const WideStage& d, int ks) {
+    const int kc = 2 * ks + (lane >> 5);
+#pragma unroll
+    for (int i = 0; i < WI; ++i) {
+      f.ah[i] = b3::frag<BKT>(d.a[0] + wr * 64 * BKT, i * 32 + (lane & 31), kc);
+      f.al[i] = b3::frag<BKT>(d.a[1] + wr * 64 * BKT, i * 32 + (lane & 31), kc);
+    }
+#pragma unroll
+    for (int j = 0; j < WJ; ++j) {
+      f.bh[j] = b3::frag<BKT>(d.b[0], wc * 64 + j * 32 + (lane & 31), kc);
+      f.bl[j] = b3::frag<BKT>(d.b[1], wc * 64 + j * 32 + (lane & 31), kc);
+    }
+  };
+  // hi*hi, then hi*lo, then lo*hi into every accumulator
+  auto mma = [&](const Frag& f) {
+#pragma unroll
+    for (int i = 0; i < WI; ++i)
+#pragma unroll
+      for (int j = 0; j < WJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[i], f.bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < WI; ++i)
+#pragma unroll
+      for (int j = 0; j < WJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[i], f.bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < WI; ++i)
+#pragma unroll
+      for (int j = 0; j < WJ; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[i], f.bh[j], acc[i][j], 0, 0, 0);
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < WI; ++i)
+#pragma unroll
+      for (int j = 0; j < WJ; ++j) {
+        sum[i][j] += acc[i][j];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+      }
+  };
+  constexpr int FLUSH_STAGES = FLUSH_ROWS / BKT;
+  Frag f0, f1;
+  if (nk > 0) {
+    issue(0);
+    if (nk > 1) issue(1);
+    handover(-1);
+    read(f0, st[0], 0);
+  }
+  // all stages but the last: no branch between the reads of the next stage
+  // and the MFMAs of this one, so the waits before those MFMAs cover only
+  // their own reads
+  for (int it = 0; it + 1 < nk; ++it) {
+    if (it + 2 < nk) issue(it + 2);     // buffer of stage it - 1: free since its hand-over
+    read(f1, st[it % NBUF], 1);
+    mma(f0);
+    handover(it);
+    read(f0, st[(it + 1) % NBUF], 0);
+    mma(f1);
+    if ((it + 1) % FLUSH_STAGES == 0) flush();
+  }
+  if (nk > 0) {
+    read(f1, st[(nk - 1) % NBUF], 1);
+    mma(f0);
+    mma(f1);
+    flush();
+  }
+  const int t = ti * (ti + 1) / 2 + J;
+  double* out = a.part + (((int64_t)s * a.L + m) * a.n_tiles + t) * (BM * BM);
+#pragma unroll
+  for (int i = 0; i < WI; ++i)
+#pragma unroll
+    for (int j = 0; j < WJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = (wr & 1) * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = wc * 64 + j * 32 + (lane & 31);
         out[row * BM + col] = (double)sum[i][j][r];
       }
 }
@@ -936,9 +1130,12 @@ static int64_t split_chunk_rows(int64_t k_rows, int Npad, int L) {
 static gw_status syrk_bf16x3_split(gw_ctx ctx, const float* X, int64_t k_rows, int N,
                                    int64_t ld, int L, const float* scale, double cscale,
                                    double* out, int accumulate, const char* prof_name) {
+  static_assert(b3::BK == 32, "the split layout blocks k by 32, one stage of every shape");
   const int T = (N + BM - 1) / BM;
-  const int Npad = T * BM;
+  const int Npad = (N + 2 * BM - 1) / (2 * BM) * (2 * BM);   // the wide shapes' 256-row tiles
   const int n_tiles = T * (T + 1) / 2;
+  int wide_units = 0;
+  for (int i = 0; i < (T + 1) / 2; ++i) wide_units += std::min(2 * i + 2, T);
   const int64_t kc = split_chunk_rows(k_rows, Npad, L);
   const size_t y_elems = (size_t)L * Npad * kc;
   __bf16* Y = static_cast<__bf16*>(ws_get(ctx, WS_B3_CHI, 2 * y_elems * sizeof(__bf16)));
@@ -966,14 +1163,19 @@ static gw_status syrk_bf16x3_split(gw_ctx ctx, const float* X, int64_t k_rows, i
       int64_t rps = (kp + S - 1) / S;
       rps = (rps + FLUSH_ROWS - 1) / FLUSH_ROWS * FLUSH_ROWS;
       const int Se = (int)((kp + rps - 1) / rps);
-      return Syrk3Args{sa.hi, sa.lo, kp, Npad, L, n_tiles, Se, rps, part};
+      return Syrk3Args{sa.hi, sa.lo, kp, Npad, L, n_tiles, Se, rps, part, T};
     };
     // candidates: split-K factor x kernel shape, encoded as 4 S + shape
-    // (0: 4 waves, 2 stages; 1: 4 waves, 3 stages; 2: 8 waves, 2 stages)
+    // (128 x 128 tiles: 0: 4 waves, 2 stages; 1: 4 waves, 3 stages; 2: 8
+    // waves, 2 stages; 3: 256 x 128 tiles, 8 waves, 3 stages)
     auto launch = [&](int code) {
       const Syrk3Args a = args(code / 4);
       const dim3 grid((unsigned)((int64_t)a.splits * L * n_tiles));
+      const dim3 wgrid((unsigned)((int64_t)a.splits * L * wide_units));
       switch (code % 4) {
+        case 3:
+          hipLaunchKernelGGL(syrk_bf16x3_wide_kernel, wgrid, dim3(512), 0, ctx->stream, a);
+          break;
         case 1:
           hipLaunchKernelGGL((syrk_bf16x3_direct_kernel<3, 1, 4>), grid, dim3(256), 0,
                              ctx->stream, a);
@@ -990,7 +1192,7 @@ static gw_status syrk_bf16x3_split(gw_ctx ctx, const float* X, int64_t k_rows, i
     };
     std::vector<int> codes;
     for (int c : cand)
-      for (int shape = 0; shape < 3; ++shape) codes.push_back(4 * c + shape);
+      for (int shape = 0; shape < 4; ++shape) codes.push_back(4 * c + shape);
     const std::string key = "syrk3:" + std::to_string(N) + ":" + std::to_string(L) + ":" +
                             std::to_string(kp);
     const int code = tune(ctx, key, codes, launch);

@@ -39,7 +39,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_set_stream", "gw_sync", "gw_last_error
            "gw_polarizability_lt_batched", "gw_screen_batched", "gw_sigma_diag_batched",
            "gw_qp_solve_batched", "gw_g0w0_batched", "gw_reserve", "gw_naf_compress_batched",
            "gw_naf_apply_batched", "gw_autotune", "gw_evgw", "gw_polarizability_sos",
-           "gw_screen_sos", "gw_lt_grid_auto", "gw_sigma_diag_noalloc"]
+           "gw_screen_sos", "gw_lt_grid_auto", "gw_sigma_diag_noalloc", "gw_autotune_restrict"]
 
 c_int, c_i64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_DBL = ctypes.POINTER(ctypes.c_double)
@@ -154,6 +154,7 @@ _sig = {
     "gw_evgw": [c_vp, c_int, ctypes.POINTER(GwParams), c_int, P_DBL, P_INT, P_DBL, c_vp, c_vp,
                 c_vp, P_DBL, P_DBL, P_INT, P_DBL, ctypes.POINTER(GwStats)],
     "gw_autotune": [c_vp, c_int, P_INT],
+    "gw_autotune_restrict": [c_vp, ctypes.c_char_p, c_int, c_int],
     "gw_naf_compress_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafJob)],
     "gw_naf_apply_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafApplyJob)],
     "gw_graph_begin": [c_vp],
@@ -624,6 +625,13 @@ def gw_naf_apply_batched(ctx, prec, jobs):
                          R_out=_dev(R_out), ld_out=R_out.shape[-1]))
     arr = _jobs(NafApplyJob, rows)
     _check(_lib.gw_naf_apply_batched(ctx.handle, _prec(prec), len(rows), arr), ctx)
+
+
+def gw_autotune_restrict(ctx, family: str, modulus: int, residue: int = 0) -> None:
+    """Keep only the candidates c of a kernel family with c % modulus ==
+    residue (modulus 0 lifts the restriction)."""
+    _check(_lib.gw_autotune_restrict(ctx.handle, family.encode(), int(modulus), int(residue)),
+           ctx)
 
 
 def gw_autotune(ctx, enable: int = -1) -> int:

@@ -104,6 +104,48 @@ def test_polarizability_padded_rows(gw, ctx, prec, tol, shape):
         assert rel_fro(Mh[m], ref[m]) < tol
 
 
+@pytest.mark.parametrize("o,v,N", [(6, 700, 300), (5, 900, 520), (7, 640, 700), (3, 301, 129)])
+def test_polarizability_bf16x3_every_shape(gw, ctx, o, v, N):
+    """Each launch shape of the BF16x3 SYRK (128 x 128 and 256 x 128 tiles,
+    4 or 8 waves, 2 or 3 stages) against the oracle.  Every
+    accumulator takes the same products in the same order in all shapes, so
+    at one split-K factor (tuning off: the default) the results agree
+    bitwise.  Tile counts 3, 5, 6 and 2 give odd and even halves of the
+    256-row tiles."""
+    _say(f"polarizability bf16x3 shapes o={o} v={v} N={N}")
+    L = 3
+    eps_i, eps_a, R, x, w = _lt_case(29, o, v, N, L)
+    d = (eps_a[None, :] - eps_i[:, None]).ravel()
+    ref = rpa.m_lt(R, d, x, w)
+    Rd = dev(R, "bf16x3")
+    outs = []
+    gw.gw_autotune(ctx, 2)
+    gw.gw_autotune(ctx, 0)
+    try:
+        for shape in range(4):
+            gw.gw_autotune_restrict(ctx, "syrk3", 4, shape)
+            M = torch.full((L, N, N), float("nan"), dtype=torch.float64, device="cuda")
+            gw.gw_polarizability_lt(ctx, "bf16x3", N, x, w, o, v, eps_i, eps_a, Rd, 0, 1, M)
+            gw.gw_sync(ctx)
+            outs.append(M.cpu().numpy())
+    finally:
+        gw.gw_autotune_restrict(ctx, "syrk3", 0)
+        gw.gw_autotune(ctx, 1)
+    for shape, Mh in enumerate(outs):
+        assert np.all(np.isfinite(Mh)), shape
+        for m in range(L):
+            err = rel_fro(Mh[m], ref[m])
+            assert err < 1e-4, (shape, m, err)
+        assert np.array_equal(Mh, outs[0]), shape
+
+
+def test_autotune_restrict_rejects_bad_arguments(gw, ctx):
+    for mod, res in ((-1, 0), (4, 4), (4, -1)):
+        with pytest.raises(gw.GwError) as ei:
+            gw.gw_autotune_restrict(ctx, "syrk3", mod, res)
+        assert ei.value.status == gw.GW_EINVAL
+
+
 def test_polarizability_chunks_accumulate(gw, ctx):
     o, v, N = 10, 211, 140
     eps_i, eps_a, R, x, w = _lt_case(5, o, v, N, 3)
