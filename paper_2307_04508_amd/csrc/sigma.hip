@@ -182,16 +182,18 @@ __global__ __launch_bounds__(NTD, 4) void bwb_f32_direct_kernel(BwbArgs a0, Batc
 
 // ------------------------------------------------------- BF16x3, pre-split
 // Both operands split once per call into workspace (bf16x3.hpp): the QP rows
-// as [rows_pad][Npad] and each W^_j as [Npad][Npad] (hi and lo, zero
-// padded).  W^_j is symmetric, so row c of W^_j is column c contiguous along
-// k, and both tiles are copied global -> LDS directly.  The symmetric
+// ([rows_pad][Npad]) and each W^_j ([Npad][Npad]), hi and lo, zero padded,
+// stored in blocks of 32 k: block b holds [rows][32] of k 32 b .. 32 b + 31,
+// so one pipeline stage of any tile is one contiguous range.  W^_j is
+// symmetric, so row c of W^_j is column c along k, and both tiles are copied
+// global -> LDS directly.  The symmetric
 // weighting (1 for the diagonal block, 2 below it) scales the accumulators:
 // after the diagonal block they are halved, at the end doubled (exact).
 struct Split3Args {
   const float* src;     // [batch][rows][ld] with batch stride sstride
   int64_t rows, ld, sstride;
   int cols;
-  __bf16* hi;           // [batch][rows_pad][cols_pad]
+  __bf16* hi;           // [batch][cols_pad / 32][rows_pad][32]
   __bf16* lo;
   int64_t rows_pad, cols_pad;
   int batch;
@@ -208,21 +210,23 @@ __global__ __launch_bounds__(256) void split3_kernel(Split3Args a) {
     const float v = (r < a.rows && c < a.cols) ? a.src[b * a.sstride + r * a.ld + c] : 0.f;
     __bf16 h, l;
     b3::split(v, h, l);
-    a.hi[i] = h;
-    a.lo[i] = l;
+    const int64_t o = b * per + (int64_t)(c >> 5) * (a.rows_pad * 32) + r * 32 + (c & 31);
+    a.hi[o] = h;
+    a.lo[o] = l;
   }
 }
 
 struct Bwb3Args {
-  const __bf16* rh;     // [rows_pad][Npad]
+  const __bf16* rh;     // [Npad / 32][rows_pad][32]
   const __bf16* rl;
-  const __bf16* wh;     // [F][Npad][Npad]
+  const __bf16* wh;     // [F][Npad / 32][Npad][32]
   const __bf16* wl;
   const float* R;       // FP32 rows for the row-dot epilogue, [rows][ldr]
   int64_t ldr;
   int64_t rows;
   int N, Npad, F, row_tiles, col_tiles;
   double* part;         // [F][2 * col_tiles][rows]
+  int64_t rows_pad;
 };
 
 // NW = 4: waves of 64 rows x 64 columns; NW = 8: waves of 32 rows x 64
@@ -254,11 +258,12 @@ __global__ __launch_bounds__(NW * 64, 2) void bwb_bf16x3_direct_kernel(Bwb3Args 
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][jj][r] = 0.f;
 
-  auto issue = [&](int64_t kb, int buf) {
-    b3::load_tile<b3::BK, NW>(a.rh, a.Npad, row0, kb, st[buf].t[0], wave, lane);
-    b3::load_tile<b3::BK, NW>(a.rl, a.Npad, row0, kb, st[buf].t[1], wave, lane);
-    b3::load_tile<b3::BK, NW>(wh, a.Npad, col0, kb, st[buf].t[2], wave, lane);
-    b3::load_tile<b3::BK, NW>(wl, a.Npad, col0, kb, st[buf].t[3], wave, lane);
+  static_assert(b3::BK == 32, "one stage is one k block of the split layout");
+  auto issue = [&](int64_t kb, int buf) {   // kb: a multiple of 32
+    b3::load_tile<b3::BK, NW>(a.rh + kb * a.rows_pad, b3::BK, row0, 0, st[buf].t[0], wave, lane);
+    b3::load_tile<b3::BK, NW>(a.rl + kb * a.rows_pad, b3::BK, row0, 0, st[buf].t[1], wave, lane);
+    b3::load_tile<b3::BK, NW>(wh + kb * a.Npad, b3::BK, col0, 0, st[buf].t[2], wave, lane);
+    b3::load_tile<b3::BK, NW>(wl + kb * a.Npad, b3::BK, col0, 0, st[buf].t[3], wave, lane);
   };
   auto publish = [&]() {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -735,8 +740,8 @@ struct SigmaBufs {
   double* part;   // [F][2 * col_tiles][rows]
   double* W;      // [F][rows]
   float* RT;      // [N][rt_ld(rows)], FP32 path only
-  __bf16* R3;     // BF16x3 path: split QP rows, hi then lo [rows_pad][Npad]
-  __bf16* W3;     // BF16x3 path: split W^, hi then lo [F][Npad][Npad]
+  __bf16* R3;     // BF16x3 path: split QP rows, hi then lo, k-blocked [rows_pad][Npad]
+  __bf16* W3;     // BF16x3 path: split W^, hi then lo, k-blocked [F][Npad][Npad]
 };
 
 // Bytes of each buffer of one call, each rounded up to 256 bytes.
@@ -816,7 +821,7 @@ gw_status sigma_diag_run(gw_ctx ctx, gw_precision prec, int n_naf, int n_qp, int
     GW_TRY(gw::launch_check(ctx, "split3_kernel"));
     const Bwb3Args a3{b.R3, b.R3 + rp * np, b.W3, b.W3 + (int64_t)F * np * np,
                       static_cast<const float*>(R_qp), ld_R, rows, N, (int)np, F, row_tiles,
-                      col_tiles, b.part};
+                      col_tiles, b.part, rp};
     // 4 or 8 waves per workgroup, autotuned per shape (trials write only partials)
     auto launch = [&](int nw) {
       if (nw == 8)
