@@ -47,10 +47,28 @@ struct BwbArgs {
   int64_t ldt;        // multiple of 4, >= rows
 };
 
+// Work-unit order: blocks of 8 frequencies outermost, then the column tile,
+// then the row tile with the frequency of the block fastest.  The 32 units
+// an XCD runs at once are then 4 row tiles x 8 frequencies of one column
+// tile: per k step they read 4 slices of R and 8 of W^ (12 distinct
+// slices per 32 units; row tile fastest gives 33), and every XCD's share
+// of the launch spans all column tiles, whose k ranges differ.
+__device__ __forceinline__ void bwb_unit(int64_t lid, int row_tiles, int col_tiles, int F, int& j,
+                                         int& ct, int& rt) {
+  constexpr int JB = 8;
+  const int64_t per_blk = (int64_t)row_tiles * col_tiles * JB;
+  const int jblk = (int)(lid / per_blk);
+  const int j0 = jblk * JB, jn = min(JB, F - j0);
+  const int64_t rem = lid - (int64_t)jblk * per_blk;
+  const int64_t per_ct = (int64_t)row_tiles * jn;
+  ct = (int)(rem / per_ct);
+  const int64_t in = rem - (int64_t)ct * per_ct;
+  rt = (int)(in / jn);
+  j = j0 + (int)(in - (int64_t)rt * jn);
+}
+
 __device__ __forceinline__ void decode(const BwbArgs& a, int64_t lid, int& j, int& ct, int& rt) {
-  rt = (int)(lid % a.row_tiles);
-  ct = (int)((lid / a.row_tiles) % a.col_tiles);
-  j = (int)(lid / ((int64_t)a.row_tiles * a.col_tiles));
+  bwb_unit(lid, a.row_tiles, a.col_tiles, a.F, j, ct, rt);
 }
 
 // ------------------------------------------------------------------ FP32
@@ -238,9 +256,8 @@ __global__ __launch_bounds__(NW * 64, 2) void bwb_bf16x3_direct_kernel(Bwb3Args 
   constexpr int WI = NW == 4 ? 2 : 1, WJ = 2;
   __shared__ __attribute__((aligned(16))) b3::Stage st[2];
   const int64_t lid = xcd_remap(blockIdx.x, gridDim.x);
-  const int rt = (int)(lid % a.row_tiles);
-  const int ct = (int)((lid / a.row_tiles) % a.col_tiles);
-  const int j = (int)(lid / ((int64_t)a.row_tiles * a.col_tiles));
+  int j, ct, rt;
+  bwb_unit(lid, a.row_tiles, a.col_tiles, a.F, j, ct, rt);
   const int64_t row0 = (int64_t)rt * BM;
   const int col0 = ct * BM;
   const __bf16* wh = a.wh + (int64_t)j * a.Npad * a.Npad;
