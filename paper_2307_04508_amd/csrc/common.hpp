@@ -88,6 +88,10 @@ struct gw_ctx_s {
   bool capturing = false;
   hipStream_t user_stream = nullptr;     // restored when the capture ends
   hipStream_t capture_stream = nullptr;  // private, created lazily
+  // second stream of the screening sweep's lookahead (forked from and
+  // joined back into `stream` by events), created lazily
+  hipStream_t side_stream = nullptr;
+  hipEvent_t side_ev[2] = {nullptr, nullptr};
   unsigned char* arena_dev = nullptr;
   std::vector<unsigned char> arena_host;
   int live_graphs = 0;                   // caller-held graphs (workspace pinned)

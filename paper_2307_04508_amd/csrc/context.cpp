@@ -424,6 +424,12 @@ gw_status gw_destroy(gw_ctx ctx) {
   if (ctx->stream) hipStreamSynchronize(ctx->stream); else hipDeviceSynchronize();
   gw::drop_batch_graph(ctx);
   if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
+  if (ctx->side_stream) {
+    hipStreamSynchronize(ctx->side_stream);
+    hipStreamDestroy(ctx->side_stream);
+  }
+  for (hipEvent_t e : ctx->side_ev)
+    if (e) hipEventDestroy(e);
   for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) hipFree(ctx->ws[i]);
   if (ctx->d_flags) hipFree(ctx->d_flags);

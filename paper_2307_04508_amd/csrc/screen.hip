@@ -101,6 +101,8 @@ struct SwArgs {
   int panel_blocks;     // inner panel kernel: workgroups per matrix
   double* Cn;           // fused update (pw = 128): the next step's panel, [F][N][pw]
   int kbn, bwn;         //   its first column and width (bwn = 0: no next step)
+  int mode;             // fused update: 0 every lower tile; 1 the tiles of row and
+                        // column kbn / 128 (the next panel); 2 the others
 };
 
 // C[j][r][c] = A_j(r, kb + c) read from the lower triangle; zero for c >= bw.
@@ -726,11 +728,25 @@ __global__ __launch_bounds__(512, 2) void update_fused_kernel(Batch bt) {
   if (!unit_of(SwArgs{}, bt, sa, lid)) return;
   const int N = sa.N, pw = sa.pw, bw = sa.bw, kb = sa.kb;
   const int T = (N + BU - 1) / BU;
-  const int n_tiles = T * (T + 1) / 2;
-  const int j = (int)(lid / n_tiles);
-  int I, J;
-  lower_tile((int)(lid % n_tiles), I, J);
   const int K = kb / BU, Kn = sa.bwn > 0 ? sa.kbn / BU : -1;
+  int I, J, j;
+  if (sa.mode == 1) {                 // row Kn (J <= Kn), then column Kn (I > Kn)
+    j = (int)(lid / T);
+    const int u = (int)(lid % T);
+    I = u <= Kn ? Kn : u;
+    J = u <= Kn ? u : Kn;
+  } else if (sa.mode == 2 && Kn >= 0) {
+    // the lower tiles of order T - 1, indices at or past Kn shifted by one
+    const int n2 = (T - 1) * T / 2;
+    j = (int)(lid / n2);
+    lower_tile((int)(lid % n2), I, J);
+    I += I >= Kn;
+    J += J >= Kn;
+  } else {
+    const int n_tiles = T * (T + 1) / 2;
+    j = (int)(lid / n_tiles);
+    lower_tile((int)(lid % n_tiles), I, J);
+  }
   const bool in_row = I == K, in_col = J == K;
   const double* Pj = sa.P + (int64_t)j * N * pw;
   const double* Cj = sa.C + (int64_t)j * N * pw;
@@ -951,10 +967,12 @@ constexpr int kPivE = 4;  // register block edge of the whole-block pivot sweep
 size_t sweep_scratch(const std::vector<SweepSet>& sets) {
   size_t t = 0;
   for (const SweepSet& s : sets) {
-    t += 3 * (size_t)s.F * s.N * BO;               // panels C (two, by step parity), P
-    t += (size_t)s.F * BO * BO;                    // pivot block Dw (or Dinv)
-    t += 3 * (size_t)s.F * BO * BI;                // width BO: C, C, P of the Dw sweep
-    t += (size_t)s.F * BI * BI;                    //   and its pivot blocks
+    // panels C and P (two of each, by step parity, at width BI; one P
+    // at width BO) and the pivot blocks Dw (two at width BI)
+    t += 3 * (size_t)s.F * s.N * BO;
+    t += (size_t)s.F * BO * BO;
+    t += 4 * (size_t)s.F * BO * BI;                // width BO: C, C, P, P of the Dw sweep
+    t += 2 * (size_t)s.F * BI * BI;                //   and its pivot blocks
   }
   return t;
 }
@@ -964,12 +982,15 @@ size_t sweep_scratch(const std::vector<SweepSet>& sets) {
 // single staging copy, and the launches then read their slices of it (one
 // copy per sweep instead of one or two per launch).
 struct SweepLaunch {
-  void (*kern)(Batch);    // nullptr: a pivot kernel (kind), which also takes the flags
-  int kind;               // 0 pivot_batched_kernel, 1 pivot_dense_kernel<BI, kPivE>
+  void (*kern)(Batch);    // nullptr: a pivot kernel or a stream operation (kind)
+  int kind;               // 0 pivot_batched_kernel, 1 pivot_dense_kernel<BI, kPivE>,
+                          // 2 wait for event `ev`, 3 record event `ev`
   size_t args_at, off_at; // byte offsets of the SwArgs and offsets arrays in the blob
   int n, chunk, threads;
   int64_t units, grid;
   const char* what;
+  int side = 0;           // 1: on the context's second stream
+  int ev = 0;
 };
 
 struct SweepPlan {
@@ -984,20 +1005,32 @@ struct SweepPlan {
   }
 };
 
+// A stream operation of the lookahead: wait for (kind 2) or record (kind 3)
+// event ev on the main (side 0) or second (side 1) stream.
+void plan_stream_op(SweepPlan& plan, int kind, int side, int ev) {
+  SweepLaunch l{nullptr, kind, 0, 0, 0, 0, 0, 0, 0, "stream op"};
+  l.side = side;
+  l.ev = ev;
+  plan.launches.push_back(l);
+}
+
 template <typename F>
-void plan_units(SweepPlan& plan, size_t args_at, const std::vector<SwArgs>& st, F units,
+bool plan_units(SweepPlan& plan, size_t args_at, const std::vector<SwArgs>& st, F units,
                 int chunk, bool elems, void (*kern)(Batch), int threads, const char* what,
-                int kind = 0) {
+                int kind = 0, int side = 0) {
   std::vector<int64_t> off(1, 0);
   for (const SwArgs& a : st) {
     const int64_t u = units(a);
     off.push_back(off.back() + (elems ? (u + kBatchElems - 1) / kBatchElems : u));
   }
-  if (off.back() == 0) return;
+  if (off.back() == 0) return false;
   const int64_t grid = chunk > 1 ? (off.back() + 8 * chunk - 1) / (8 * chunk) * (8 * chunk)
                                  : off.back();
-  plan.launches.push_back(SweepLaunch{kern, kind, args_at, plan.put(off.data(), off.size()),
-                                      (int)st.size(), chunk, threads, off.back(), grid, what});
+  SweepLaunch l{kern, kind, args_at, plan.put(off.data(), off.size()), (int)st.size(), chunk,
+                threads, off.back(), grid, what};
+  l.side = side;
+  plan.launches.push_back(l);
+  return true;
 }
 
 // Plan the sweep of every set to -A^-1 with pivot blocks of width pw: B
@@ -1007,7 +1040,8 @@ void plan_units(SweepPlan& plan, size_t args_at, const std::vector<SwArgs>& st, 
 // `scr` holds sweep_scratch(sets) doubles.
 void plan_sweep(SweepPlan& plan, const std::vector<SweepSet>& sets, int pw, double* scr) {
   const int n = (int)sets.size();
-  std::vector<double*> C(n), C2(n), P(n), X(n);   // X: Dw (outer) or Dinv (inner)
+  // X: Dw (outer) or Dinv (inner); at width BI P and X by step parity too
+  std::vector<double*> C(n), C2(n), P(n), P2(n), X(n), X2(n);
   size_t o = 0;
   for (int d = 0; d < n; ++d) {
     const SweepSet& s = sets[d];
@@ -1019,6 +1053,14 @@ void plan_sweep(SweepPlan& plan, const std::vector<SweepSet>& sets, int pw, doub
     o += (size_t)s.F * s.N * pw;
     X[d] = scr + o;
     o += pw > B ? (size_t)s.F * pw * pw : (size_t)s.F * B * B;
+    P2[d] = P[d];
+    X2[d] = X[d];
+    if (pw == BI) {
+      P2[d] = scr + o;
+      o += (size_t)s.F * s.N * pw;
+      X2[d] = scr + o;
+      o += (size_t)s.F * pw * pw;
+    }
   }
   double* inner_scr = scr + o;              // width BO: scratch of the pivot-block sweeps
   int T_max = 0;
@@ -1035,11 +1077,13 @@ void plan_sweep(SweepPlan& plan, const std::vector<SweepSet>& sets, int pw, doub
       double* cur = (pw == BI && (kt & 1)) ? C2[d] : C[d];
       double* nxt = (pw == BI && (kt & 1)) ? C[d] : C2[d];
       const int kbn = kb + pw, bwn = std::max(0, std::min(pw, s.N - kbn));
-      SwArgs a{s.A, cur, P[d], pw == B ? X[d] : nullptr, pw > B ? X[d] : nullptr, s.N, s.F,
+      double* Pk = (kt & 1) ? P2[d] : P[d];
+      double* Xk = (kt & 1) ? X2[d] : X[d];
+      SwArgs a{s.A, cur, Pk, pw == B ? Xk : nullptr, pw > B ? Xk : nullptr, s.N, s.F,
                kb, bw, (s.N + B - 1) / B, kt, pw, s.flag_base, std::min(1024, (s.N + 15) / 16),
-               nxt, kbn, bwn};
+               nxt, kbn, bwn, 0};
       st.push_back(a);
-      if (pw > BI) dsets.push_back(SweepSet{X[d], bw, s.F, s.flag_base});
+      if (pw > BI) dsets.push_back(SweepSet{Xk, bw, s.F, s.flag_base});
     }
     const size_t at = plan.put(st.data(), st.size());
     if (pw != BI || kt == 0)
@@ -1067,13 +1111,36 @@ void plan_sweep(SweepPlan& plan, const std::vector<SweepSet>& sets, int pw, doub
                  panel128_kernel, 512, "panel128_kernel");
     }
     if (pw == BI) {
-      // update, write-back and the next panel in one pass
-      plan_units(plan, at, st,
+      // Update, write-back and the next panel in one pass, split in two
+      // launches: the tiles of the next panel's row and column (mode 1, main
+      // stream) and the others (mode 2, second stream).  The next step's
+      // pivot and panel need only the first, so they run on the main stream
+      // while the second stream finishes this step's update (P and Dw are
+      // double-buffered by step parity for that).  Mode 1 of step kt + 1
+      // rewrites the panel buffer that mode 2 of step kt reads, and the
+      // tiles it updates are updated by mode 2 of step kt: it waits for it.
+      // The two modes of one step start together (mode 1 alone fills a
+      // fraction of the GPU: run first on its own it made the step slower).
+      std::vector<SwArgs> s1 = st, s2 = st;
+      for (SwArgs& a : s1) a.mode = 1;
+      for (SwArgs& a : s2) a.mode = 2;
+      const size_t at1 = plan.put(s1.data(), s1.size());
+      const size_t at2 = plan.put(s2.data(), s2.size());
+      plan_stream_op(plan, 3, 0, 0);              // this step's pivot and panel are done
+      if (kt > 0) plan_stream_op(plan, 2, 0, 1);  // the previous step's mode 2 is done
+      plan_units(plan, at1, s1,
                  [](const SwArgs& a) {
-                   const int64_t t = (a.N + BU - 1) / BU;
-                   return (int64_t)a.F * t * (t + 1) / 2;
+                   return a.bwn > 0 ? (int64_t)a.F * ((a.N + BU - 1) / BU) : 0;
                  },
                  8, false, update_fused_kernel, 512, "update_fused_kernel");
+      plan_stream_op(plan, 2, 1, 0);
+      plan_units(plan, at2, s2,
+                 [](const SwArgs& a) {
+                   const int64_t t = (a.N + BU - 1) / BU;
+                   return (int64_t)a.F * (a.bwn > 0 ? (t - 1) * t / 2 : t * (t + 1) / 2);
+                 },
+                 8, false, update_fused_kernel, 512, "update_fused_kernel", 0, 1);
+      plan_stream_op(plan, 3, 1, 1);
       continue;
     }
     if (pw > B) {
@@ -1090,6 +1157,7 @@ void plan_sweep(SweepPlan& plan, const std::vector<SweepSet>& sets, int pw, doub
     plan_units(plan, at, st, [](const SwArgs& a) { return (int64_t)a.F * a.N * a.pw; }, 1, true,
                writeback_batched_kernel, 256, "writeback");
   }
+  if (pw == BI && T_max > 0) plan_stream_op(plan, 2, 0, 1);   // join the second stream
 }
 
 gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* scr) {
@@ -1099,17 +1167,34 @@ gw_status sweep(gw_ctx ctx, const std::vector<SweepSet>& sets, int pw, double* s
   const unsigned char* dev =
       static_cast<const unsigned char*>(gw::stage(ctx, plan.blob.data(), plan.blob.size()));
   if (!dev) return GW_EINVAL;
+  bool two = false;
+  for (const SweepLaunch& l : plan.launches) two = two || l.side != 0;
+  if (two && !ctx->side_stream) {
+    // default priority, like every stream of the library
+    GW_HIP(ctx, hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking));
+    for (hipEvent_t& e : ctx->side_ev)
+      GW_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   for (const SweepLaunch& l : plan.launches) {
+    hipStream_t st = l.side ? ctx->side_stream : ctx->stream;
+    if (l.kind == 2 && !l.kern) {
+      if (two) GW_HIP(ctx, hipStreamWaitEvent(st, ctx->side_ev[l.ev], 0));
+      continue;
+    }
+    if (l.kind == 3 && !l.kern) {
+      if (two) GW_HIP(ctx, hipEventRecord(ctx->side_ev[l.ev], st));
+      continue;
+    }
     const Batch bt{reinterpret_cast<const SwArgs*>(dev + l.args_at),
                    reinterpret_cast<const int64_t*>(dev + l.off_at), l.n, l.chunk, l.units};
     if (l.kern)
-      hipLaunchKernelGGL(l.kern, dim3((unsigned)l.grid), dim3(l.threads), 0, ctx->stream, bt);
+      hipLaunchKernelGGL(l.kern, dim3((unsigned)l.grid), dim3(l.threads), 0, st, bt);
     else if (l.kind == 1)
       hipLaunchKernelGGL((pivot_dense_kernel<BI, kPivE>), dim3((unsigned)l.grid), dim3(l.threads), 0,
-                         ctx->stream, bt, ctx->d_flags);
+                         st, bt, ctx->d_flags);
     else
-      hipLaunchKernelGGL(pivot_batched_kernel, dim3((unsigned)l.grid), dim3(l.threads), 0,
-                         ctx->stream, bt, ctx->d_flags);
+      hipLaunchKernelGGL(pivot_batched_kernel, dim3((unsigned)l.grid), dim3(l.threads), 0, st, bt,
+                         ctx->d_flags);
     GW_TRY(gw::launch_check(ctx, l.what));
   }
   return GW_OK;

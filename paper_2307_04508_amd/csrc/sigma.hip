@@ -47,12 +47,15 @@ struct BwbArgs {
   int64_t ldt;        // multiple of 4, >= rows
 };
 
-// Work-unit order: blocks of 8 frequencies outermost, then the column tile,
-// then the row tile with the frequency of the block fastest.  The 32 units
-// an XCD runs at once are then 4 row tiles x 8 frequencies of one column
-// tile: per k step they read 4 slices of R and 8 of W^ (12 distinct
-// slices per 32 units; row tile fastest gives 33), and every XCD's share
-// of the launch spans all column tiles, whose k ranges differ.
+// Work-unit order of the BF16x3 contraction: blocks of 8 frequencies
+// outermost, then the column tile, then the row tile with the frequency of
+// the block fastest.  The 32 units an XCD runs at once are then 4 row tiles
+// x 8 frequencies of one column tile: per k step they read 4 slices of R
+// and 8 of W^ (12 distinct slices per 32 units; row tile fastest gives 33),
+// and every XCD's share of the launch spans all column tiles, whose k
+// ranges differ.  (The FP32 and FP64 kernels keep the row tile fastest: the
+// blocked order made the FP32 contraction at the large workload slower,
+// 441 -> 500 ms.)
 __device__ __forceinline__ void bwb_unit(int64_t lid, int row_tiles, int col_tiles, int F, int& j,
                                          int& ct, int& rt) {
   constexpr int JB = 8;
@@ -68,7 +71,9 @@ __device__ __forceinline__ void bwb_unit(int64_t lid, int row_tiles, int col_til
 }
 
 __device__ __forceinline__ void decode(const BwbArgs& a, int64_t lid, int& j, int& ct, int& rt) {
-  bwb_unit(lid, a.row_tiles, a.col_tiles, a.F, j, ct, rt);
+  rt = (int)(lid % a.row_tiles);
+  ct = (int)((lid / a.row_tiles) % a.col_tiles);
+  j = (int)(lid / ((int64_t)a.row_tiles * a.col_tiles));
 }
 
 // ------------------------------------------------------------------ FP32
