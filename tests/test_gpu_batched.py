@@ -138,6 +138,43 @@ def test_screen_batched_matches_oracle(gw, ctx, prec, tol):
             assert np.array_equal(Wh[j], Wh[j].T)
 
 
+@pytest.mark.parametrize("width", [128, 256, 64])
+def test_screen_batched_each_width_matches_oracle(gw, ctx, width):
+    """The sweep at each outer width, pinned through gw_autotune_restrict, on
+    matrices whose 128-tile counts differ (6, 3, 2, 1), so their sweeps end
+    at different steps: at width 128 the update of each step is split over
+    two streams (the next panel's row and column, then the rest) and the
+    panel and pivot buffers alternate by step."""
+    _say(f"screen batched width {width}")
+    L = 3
+    shapes = [(700, 3), (300, 2), (129, 2), (1, 1), (640, 2)]
+    jobs, refs, Ws = [], [], []
+    for s, (N, F) in enumerate(shapes):
+        M = _spd_m(60 + s, L, N)
+        x = np.array([0.05, 0.5, 3.0]) * (1.0 + 0.1 * s)
+        om, _ = grids.modified_gauss_legendre(F, 0.5 + 0.1 * s)
+        refs.append(rpa.screen(rpa.pi_lt(M, x, om)))
+        W = torch.zeros((F, N, N), dtype=torch.float64, device="cuda")
+        Ws.append(W)
+        jobs.append(dict(n_naf=N, x_lt=x, M=dev(M, "fp64"), omega=om, W_hat=W))
+    gw.gw_autotune(ctx, 2)
+    gw.gw_autotune(ctx, 0)
+    gw.gw_autotune_restrict(ctx, "screen", 1024, width)
+    try:
+        gw.gw_screen_batched(ctx, "fp64", L, jobs)
+        gw.gw_sync(ctx)
+    finally:
+        gw.gw_autotune_restrict(ctx, "screen", 0)
+        gw.gw_autotune(ctx, 1)
+    for s, (W, ref) in enumerate(zip(Ws, refs)):
+        Wh = W.cpu().numpy()
+        for j in range(len(ref)):
+            d = np.linalg.norm(Wh[j] - ref[j])
+            bound = 1e-11 * np.linalg.norm(ref[j]) + 1e-13 * np.linalg.norm(ref[j] + np.eye(len(ref[j])))
+            assert d <= bound, (s, j, d, bound)
+            assert np.array_equal(Wh[j], Wh[j].T)
+
+
 def test_screen_batched_reports_non_spd(gw, ctx):
     good = _spd_m(5, 1, 40)
     bad = -np.eye(70)[None] * 10.0
