@@ -385,6 +385,7 @@ __device__ __forceinline__ double sum_column(const double* red, int G, int col, 
 }
 
 constexpr int HROWS = 128;        // rows per workgroup (n <= HROWS x workgroups)
+constexpr int HMLP = 16;          // loads in flight per lane in A22 v
 
 __global__ __launch_bounds__(HT) void tri_hbm_panel_kernel(HbmArgs a) {
   __shared__ double vch[HCH];
@@ -510,21 +511,31 @@ __global__ __launch_bounds__(HT) void tri_hbm_panel_kernel(HbmArgs a) {
         const int i = g + G * r;
         if (i < lo) continue;
         const double* row = a.K + (size_t)i * n;
-        // eight independent partial sums keep eight loads in flight per
-        // lane (the pass is bound by memory latency times the loads in flight)
-        double p[8];
+        // HMLP independent partial sums keep HMLP loads in flight per lane:
+        // the pass is bound by memory latency times the loads in flight, so
+        // a row costs ceil(len / (64 HMLP)) round trips.  Past the row's end
+        // a lane reloads its last element (clamped index, no branch) and
+        // multiplies it by zero, so the last pass is one round trip too.
+        double p[HMLP];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) p[u] = 0.0;
-        int l = c0 + lane;
-        for (; l + 7 * 64 < c1; l += 8 * 64) {
-          double x[8];
+        for (int u = 0; u < HMLP; ++u) p[u] = 0.0;
+        for (int l = c0 + lane; l < c1; l += HMLP * 64) {
+          double x[HMLP], vv[HMLP];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) x[u] = row[l + u * 64];
+          for (int u = 0; u < HMLP; ++u) {
+            const int li = l + u * 64;
+            const int lc = li < c1 ? li : c1 - 1;
+            x[u] = row[lc];
+            vv[u] = li < c1 ? vch[lc - c0] : 0.0;
+          }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) p[u] += x[u] * vch[l + u * 64 - c0];
+          for (int u = 0; u < HMLP; ++u) p[u] += x[u] * vv[u];
         }
-        for (; l < c1; l += 64) p[0] += row[l] * vch[l - c0];
-        double s = wave_total(((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
+#pragma unroll
+        for (int w = HMLP / 2; w > 0; w /= 2)
+#pragma unroll
+          for (int u = 0; u < w; ++u) p[u] += p[u + w];
+        double s = wave_total(p[0]);
         const double sr = __shfl(s, kLastLane);
         if (lane == r / (HT / 64)) yacc += sr;
       }
