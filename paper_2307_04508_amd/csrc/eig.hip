@@ -242,9 +242,27 @@ struct BisArgs {
 };
 
 // kBisLanes lanes per eigenvalue count at as many points of its bracket,
-// which shrinks (kBisLanes + 1)-fold per round.
-constexpr int kBisLanes = 32;
+// which shrinks (kBisLanes + 1)-fold per round.  The Sturm sequences are
+// bound by FP64 issue, not latency, so fewer points per round (more rounds,
+// less work) pay: 32 -> 16 lanes took A = 3000 from 2.23 to 1.65 ms, and
+// 8 lanes took A = 7000 from 10.4 to 5.6 ms.  SH: the workgroup first copies
+// d and e2 into LDS (dynamic, 2 n doubles), so the operand loads are LDS
+// reads instead of L2 round trips.
+constexpr int kBisShMax = 4096;     // orders whose d and e2 fit 64 KB of LDS
+template <bool SH, int kBisLanes>
 __global__ __launch_bounds__(256) void bisect_kernel(BisArgs a) {
+  extern __shared__ double bsh[];
+  const double* dd = a.d;
+  const double* ee = a.e2;
+  if (SH) {
+    for (int x = threadIdx.x; x < a.n; x += blockDim.x) {
+      bsh[x] = a.d[x];
+      bsh[a.n + x] = a.e2[x];
+    }
+    __syncthreads();
+    dd = bsh;
+    ee = bsh + a.n;
+  }
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int u = (int)(gt / kBisLanes), q = (int)(gt % kBisLanes);
   const int group = (threadIdx.x & 63) / kBisLanes;
@@ -264,7 +282,7 @@ __global__ __launch_bounds__(256) void bisect_kernel(BisArgs a) {
     if (!__ballot(!done)) break;
     const double h = (hi - lo) * (1.0 / (kBisLanes + 1));
     const double x = lo + (q + 1) * h;
-    const int c = done ? 0 : sturm_count(a.d + b.s, a.e2 + b.s, b.nb, x, a.pivmin);
+    const int c = done ? 0 : sturm_count(dd + b.s, ee + b.s, b.nb, x, a.pivmin);
     const uint64_t bal = __ballot(!done && c > j);
     if (!done) {
       const uint64_t gb = (bal >> (kBisLanes * group)) &
@@ -798,8 +816,12 @@ gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const d
   double* rest = ws + n;
   const int pb = prof_begin(ctx);
   const BisArgs ba{d_d, d_e2, d_blocks, (int)blocks.size(), n, pivmin, eps * tn, lam};
-  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)(((int64_t)kBisLanes * n + 255) / 256)),
-                     dim3(256), 0, ctx->stream, ba);
+  if (n <= kBisShMax)
+    hipLaunchKernelGGL((bisect_kernel<true, 16>), dim3((unsigned)((16 * (int64_t)n + 255) / 256)),
+                       dim3(256), 2 * (size_t)n * sizeof(double), ctx->stream, ba);
+  else
+    hipLaunchKernelGGL((bisect_kernel<false, 8>), dim3((unsigned)((8 * (int64_t)n + 255) / 256)),
+                       dim3(256), 0, ctx->stream, ba);
   GW_TRY(launch_check(ctx, "bisect_kernel"));
   prof_end(ctx, pb, "naf_bisect", 0.0, 0.0);
   std::vector<double> lh(n);
