@@ -298,10 +298,12 @@ __global__ __launch_bounds__(256) void bisect_kernel(BisArgs a) {
 }
 
 // One inverse-iteration vector per thread.  Per-thread arrays live in
-// scratch, interleaved over the threads ([array][i][thread]) so consecutive
-// threads touch consecutive addresses: 0 reciprocal pivot, 1 and 2 the two
-// superdiagonals of U, 3 the multiplier, 4 the vector, 5 the interchange
-// flag of row pair (k, k + 1).  The serial passes read their operands in
+// scratch, each thread's contiguous ([thread][array][i]): 0 reciprocal
+// pivot, 1 and 2 the two superdiagonals of U, 3 the multiplier, 4 the
+// vector, 5 the interchange flag of row pair (k, k + 1).  (Interleaved over
+// the threads, [array][i][thread], the loads coalesce, but every element's
+// address took its own 64-bit arithmetic: 523 spilled SGPRs, 3.7 ms at
+// A = 3000 against 3.2 ms.)  The serial passes read their operands in
 // chunks of kInvCh elements, the next chunk's loads issued before the current
 // chunk is computed, so memory latency overlaps the dependent arithmetic.
 constexpr int kInvArrays = 6;
@@ -323,7 +325,7 @@ struct InvArgs {
   double tiny;              // eps ||T||: smallest pivot magnitude
   double* Z;                // [rows][ldz]
   int64_t ldz;
-  double* scratch;          // [kInvArrays][n][n_jobs]
+  double* scratch;          // [n_jobs][kInvArrays][n]
 };
 
 __device__ __forceinline__ double rand_pm1(uint64_t key) {
@@ -353,9 +355,12 @@ __global__ __launch_bounds__(64) void invit_kernel(InvArgs a) {
   if (t >= a.n_jobs) return;
   const InvJob lead = a.jobs[t];
   if (lead.clen == 0) return;
-  const int64_t st = a.n_jobs;                     // element stride of one array
-  const int64_t plane = (int64_t)a.n * st;
-  double* rp = a.scratch + t;
+  // each thread's arrays are contiguous, [thread][array][i]: the addresses
+  // of a chunk are one base plus constant offsets (no per-element address
+  // arithmetic), at the cost of one cache line per lane per load
+  constexpr int64_t st = 1;
+  const int64_t plane = a.n;
+  double* rp = a.scratch + (int64_t)t * kInvArrays * a.n;
   double* u1 = rp + plane;
   double* u2 = u1 + plane;
   double* mm = u2 + plane;
