@@ -215,7 +215,8 @@ def run_streamed(args, cfg, gw, torch):
     n_naf = {}
     for m in metric_precs:
         n_naf[m], _ = timed(m, "naf_eig", lambda: gw.gw_naf_compress(
-            ctx, m, A, None, None, K[m], 1, 1, c.eps_naf, c.max_keep, U[m]))
+            ctx, m, A, None, None, K[m], 1, 1, c.eps_naf, c.max_keep, U[m],
+            want_eigvals=False))
         log(f"{m} NAF: {n_naf[m]} of {A} kept")
     del K
     om, wom = gw.gw_freq_grid_mgl(F, c.x0)

@@ -179,7 +179,7 @@ extern "C" gw_status gw_g0w0_batched(gw_ctx ctx, gw_precision prec, const gw_bat
     std::vector<gw::NafEigJob> ej;
     for (int d = 0; d < n; ++d)
       ej.push_back(gw::NafEigJob{U + mo[d].u_off, mo[d].A, U + mo[d].u_off, mo[d].eig.data(),
-                                 mols[d].eps_naf, mols[d].max_keep});
+                                 mols[d].eps_naf, mols[d].max_keep, false});
     st = gw::naf_eig_batched(ctx, ej);
     if (st != GW_OK) return fail_after(st);
   }

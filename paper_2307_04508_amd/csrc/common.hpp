@@ -206,6 +206,8 @@ struct NafEigJob {
   double* eig;          // host [A]: eigenvalues, descending
   double eps_naf;       // eigenvectors needed: eigenvalue > eps_naf,
   int max_keep;         // at most max_keep of them when > 0
+  bool all_eigs = true; // false: eigenvalues below eps_naf need not be computed
+                        // (eig then holds -infinity past the computed ones)
 };
 gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs);
 // FP32 transposes dst[c][r] = src[r][c] (c < cols, r < rows; rows up to

@@ -20,6 +20,7 @@
 // "NT" C[m][n] = sum_k A[m][k] B[n][k] and "TN" C[m][n] = sum_k A[k][m]
 // B[k][n], all row-major, split-K with a fixed-order reduction.
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <vector>
 
@@ -229,23 +230,27 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ d,
 struct BisBlock {
   int s, nb;                // rows s .. s + nb - 1 of T
   double gl, gu;            // a bracket of its eigenvalues
-  int out;                  // index of its first (smallest) eigenvalue in lam
+  int out;                  // index in lam of its first computed eigenvalue
+  int j0;                   // its first computed eigenvalue (ascending index)
 };
 
 struct BisArgs {
   const double* d;
   const double* e2;         // squared couplings, zero at the splits
   const BisBlock* blocks;
-  int n_blocks, n;
+  int n_blocks, n;          // n: eigenvalues computed
   double pivmin, abstol;
-  double* lam;              // [n]: each block's eigenvalues ascending from its out
+  double* lam;              // [n]: each block's computed eigenvalues ascending from its out
+  int rows;                 // order of T (d and e2 have rows entries)
 };
 
 // kBisLanes lanes per eigenvalue count at as many points of its bracket,
 // which shrinks (kBisLanes + 1)-fold per round.  The Sturm sequences are
 // bound by FP64 issue, not latency, so fewer points per round (more rounds,
-// less work) pay: 32 -> 16 lanes took A = 3000 from 2.23 to 1.65 ms, and
-// 8 lanes took A = 7000 from 10.4 to 5.6 ms.  SH: the workgroup first copies
+// less work) pay while the lanes fill the chip: 32 -> 16 lanes took all
+// 3000 eigenvalues from 2.23 to 1.65 ms, 8 lanes all 7000 from 10.4 to 5.6
+// ms; the launch picks the count from the number of eigenvalues it computes.
+// SH: the workgroup first copies
 // d and e2 into LDS (dynamic, 2 n doubles), so the operand loads are LDS
 // reads instead of L2 round trips.
 constexpr int kBisShMax = 4096;     // orders whose d and e2 fit 64 KB of LDS
@@ -255,13 +260,13 @@ __global__ __launch_bounds__(256) void bisect_kernel(BisArgs a) {
   const double* dd = a.d;
   const double* ee = a.e2;
   if (SH) {
-    for (int x = threadIdx.x; x < a.n; x += blockDim.x) {
+    for (int x = threadIdx.x; x < a.rows; x += blockDim.x) {
       bsh[x] = a.d[x];
-      bsh[a.n + x] = a.e2[x];
+      bsh[a.rows + x] = a.e2[x];
     }
     __syncthreads();
     dd = bsh;
-    ee = bsh + a.n;
+    ee = bsh + a.rows;
   }
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int u = (int)(gt / kBisLanes), q = (int)(gt % kBisLanes);
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(256) void bisect_kernel(BisArgs a) {
     if (a.blocks[mid].out <= u) lo_b = mid; else hi_b = mid - 1;
   }
   const BisBlock b = a.blocks[live ? lo_b : 0];
-  const int j = u - b.out;
+  const int j = b.j0 + (u - b.out);
   double lo = b.gl, hi = b.gu;
   const double eps = 1.1102230246251565e-16;
   for (int round = 0; round < 64; ++round) {
@@ -762,15 +767,33 @@ static gw_status tri_back_own(gw_ctx ctx, double* K, int n, const double* d_tau,
   return GW_OK;
 }
 
+// Number of eigenvalues of the block (d, e2 as in sturm_count) below x, on
+// the host.
+static int sturm_count_host(const double* d, const double* e2, int nb, double x,
+                            double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int c = q < 0.0;
+  for (int i = 1; i < nb; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
 // The eigenpairs of T (diagonal d_d, couplings d_e; device, order n) and the
 // kept eigenvectors of the original matrix.  K holds the reflectors of the
 // reduction (column k below the subdiagonal, tau in d_tau).  On return:
 // ev (host [n]) the eigenvalues in descending order, *keep_out the number
 // kept (> eps_naf, at most max_keep when > 0), U rows 0 .. keep-1 the kept
-// eigenvectors of the original matrix (descending), ld n.  Synchronises.
+// eigenvectors of the original matrix (descending), ld n.  With all_eigs
+// false only the eigenvalues above eps_naf (found by a Sturm count at it, one
+// below it for margin) are computed, and the rest of ev is -infinity.
+// Synchronises.
 gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const double* d_e,
                         const double* d_tau, double eps_naf, int max_keep, double* U,
-                        std::vector<double>& ev, int* keep_out) {
+                        std::vector<double>& ev, int* keep_out, bool all_eigs) {
   std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
   GW_HIP(ctx, hipMemcpyAsync(d.data(), d_d, n * sizeof(double), hipMemcpyDeviceToHost,
                              ctx->stream));
@@ -806,11 +829,23 @@ gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const d
         gu = std::max(gu, d[k] + r);
       }
       const double pad = 4.0 * eps * (i - s0 + 1) * tn;
-      blocks.push_back(BisBlock{s0, i - s0 + 1, gl - pad, gu + pad, s0});
+      blocks.push_back(BisBlock{s0, i - s0 + 1, gl - pad, gu + pad, s0, 0});
       s0 = i + 1;
     }
   }
   const double pivmin = 2.2250738585072014e-308 * std::max(1.0, emax2);
+  // the eigenvalues to compute: all, or per block those above eps_naf and
+  // one below (a Sturm count in FP64 at eps_naf; the filter below decides)
+  int m = n;
+  if (!all_eigs) {
+    m = 0;
+    for (BisBlock& b : blocks) {
+      const int c = sturm_count_host(d.data() + b.s, e2.data() + b.s, b.nb, eps_naf, pivmin);
+      b.j0 = std::max(0, c - 1);
+      b.out = m;
+      m += b.nb - b.j0;
+    }
+  }
   const double* d_e2 = stage_t(ctx, e2.data(), n);
   const double* d_ez = stage_t(ctx, ez.data(), n);
   const BisBlock* d_blocks = stage_t(ctx, blocks.data(), blocks.size());
@@ -820,29 +855,46 @@ gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const d
   double* lam = ws;                                   // [n]
   double* rest = ws + n;
   const int pb = prof_begin(ctx);
-  const BisArgs ba{d_d, d_e2, d_blocks, (int)blocks.size(), n, pivmin, eps * tn, lam};
-  if (n <= kBisShMax)
-    hipLaunchKernelGGL((bisect_kernel<true, 16>), dim3((unsigned)((16 * (int64_t)n + 255) / 256)),
-                       dim3(256), 2 * (size_t)n * sizeof(double), ctx->stream, ba);
-  else
-    hipLaunchKernelGGL((bisect_kernel<false, 8>), dim3((unsigned)((8 * (int64_t)n + 255) / 256)),
-                       dim3(256), 0, ctx->stream, ba);
+  // the number of computed eigenvalues is m, the bisection's "n"
+  const BisArgs ba{d_d, d_e2, d_blocks, (int)blocks.size(), m, pivmin, eps * tn, lam, n};
+  // points per eigenvalue: about 24k-48k lanes in all (fewer eigenvalues,
+  // more points and fewer rounds)
+  const int lanes = m <= 2048 ? 32 : (m <= 4096 ? 16 : 8);
+  const dim3 bg((unsigned)(((int64_t)lanes * m + 255) / 256));
+  const size_t sh = n <= kBisShMax ? 2 * (size_t)n * sizeof(double) : 0;
+  if (m > 0) {
+    if (sh && lanes == 32)
+      hipLaunchKernelGGL((bisect_kernel<true, 32>), bg, dim3(256), sh, ctx->stream, ba);
+    else if (sh && lanes == 16)
+      hipLaunchKernelGGL((bisect_kernel<true, 16>), bg, dim3(256), sh, ctx->stream, ba);
+    else if (sh)
+      hipLaunchKernelGGL((bisect_kernel<true, 8>), bg, dim3(256), sh, ctx->stream, ba);
+    else if (lanes == 32)
+      hipLaunchKernelGGL((bisect_kernel<false, 32>), bg, dim3(256), 0, ctx->stream, ba);
+    else if (lanes == 16)
+      hipLaunchKernelGGL((bisect_kernel<false, 16>), bg, dim3(256), 0, ctx->stream, ba);
+    else
+      hipLaunchKernelGGL((bisect_kernel<false, 8>), bg, dim3(256), 0, ctx->stream, ba);
+  }
   GW_TRY(launch_check(ctx, "bisect_kernel"));
   prof_end(ctx, pb, "naf_bisect", 0.0, 0.0);
-  std::vector<double> lh(n);
-  GW_HIP(ctx, hipMemcpyAsync(lh.data(), lam, n * sizeof(double), hipMemcpyDeviceToHost,
-                             ctx->stream));
+  std::vector<double> lh(std::max(m, 1));
+  if (m > 0)
+    GW_HIP(ctx, hipMemcpyAsync(lh.data(), lam, m * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
   // descending order over all blocks
-  std::vector<int> order(n), blk_of(n);
-  for (size_t b = 0; b < blocks.size(); ++b)
-    for (int j = 0; j < blocks[b].nb; ++j) blk_of[blocks[b].out + j] = (int)b;
-  for (int i = 0; i < n; ++i) order[i] = i;
+  std::vector<int> order(m), blk_of(std::max(m, 1));
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    const int cnt = all_eigs ? blocks[b].nb : blocks[b].nb - blocks[b].j0;
+    for (int j = 0; j < cnt; ++j) blk_of[blocks[b].out + j] = (int)b;
+  }
+  for (int i = 0; i < m; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return lh[x] > lh[y]; });
-  ev.resize(n);
-  for (int i = 0; i < n; ++i) ev[i] = lh[order[i]];
+  ev.assign(n, -std::numeric_limits<double>::infinity());
+  for (int i = 0; i < m; ++i) ev[i] = lh[order[i]];
   int keep = 0;
-  while (keep < n && ev[keep] > eps_naf) ++keep;
+  while (keep < m && ev[keep] > eps_naf) ++keep;
   if (max_keep > 0) keep = std::min(keep, max_keep);
   *keep_out = keep;
   if (keep == 0) return GW_OK;

@@ -24,7 +24,7 @@ namespace gw {
 // ev, the kept eigenvectors of the original matrix in U's first rows.
 gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const double* d_e,
                         const double* d_tau, double eps_naf, int max_keep, double* U,
-                        std::vector<double>& ev, int* keep_out);
+                        std::vector<double>& ev, int* keep_out, bool all_eigs);
 // Synchronises; GW_EDEVICE if a tridiagonalisation barrier timed out.
 gw_status check_tridiag(gw_ctx ctx);
 gw_status gemm_f32_direct(gw_ctx ctx, const std::vector<NafGemmJob>& jobs, const char* prof);
@@ -435,7 +435,8 @@ extern "C" gw_status gw_naf_compress(gw_ctx ctx, gw_precision prec, int n_aux,
     GW_TRY(gw::tridiag_blocked(ctx, tj));
   }
   GW_TRY(gw::check_tridiag(ctx));
-  GW_TRY(gw::naf_tri_solve(ctx, K, n_aux, d_eval, d_e, d_tau, eps_naf, max_keep, U, ev, &keep));
+  GW_TRY(gw::naf_tri_solve(ctx, K, n_aux, d_eval, d_e, d_tau, eps_naf, max_keep, U, ev, &keep,
+                           eigvals != nullptr));
   gw::prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
   *n_naf = keep;
   if (eigvals) std::copy(ev.begin(), ev.end(), eigvals);
@@ -536,7 +537,7 @@ gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs) {
     const NafEigJob& j = jobs[d];
     int keep = 0;
     GW_TRY(naf_tri_solve(ctx, tri[d].K, j.A, tri[d].d, tri[d].e, tri[d].tau, j.eps_naf,
-                         j.max_keep, j.U, ev, &keep));
+                         j.max_keep, j.U, ev, &keep, j.all_eigs));
     std::copy(ev.begin(), ev.end(), j.eig);
   }
   prof_end(ctx, pe, "naf_eig", 0.0, 0.0);
@@ -654,7 +655,7 @@ extern "C" gw_status gw_naf_compress_batched(gw_ctx ctx, gw_precision prec, int 
   for (int d = 0; d < n_jobs; ++d) {
     ev[d].resize(jobs[d].n_aux);
     ej.push_back(gw::NafEigJob{jobs[d].K, jobs[d].n_aux, jobs[d].U, ev[d].data(),
-                               jobs[d].eps_naf, jobs[d].max_keep});
+                               jobs[d].eps_naf, jobs[d].max_keep, jobs[d].eigvals != nullptr});
   }
   GW_TRY(gw::naf_eig_batched(ctx, ej));
   for (int d = 0; d < n_jobs; ++d) {

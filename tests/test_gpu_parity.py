@@ -486,6 +486,33 @@ def test_naf_eigensolver_orders(gw, ctx, n):
     assert np.abs(res).max() < 1e-12 * scale * max(1.0, np.sqrt(n) / 8)
 
 
+@pytest.mark.parametrize("n,eps", [(200, 1.0), (1030, 2.0), (3100, 0.5), (4700, 3.0)])
+def test_naf_kept_only_matches_full(gw, ctx, n, eps):
+    """Without the eigenvalue list the solver bisects only the eigenvalues
+    above eps_naf (and one below), with as many or more points per round
+    (the count follows the number of eigenvalues computed): the kept count
+    equals the full solve's and the kept eigenvectors agree to rounding, on
+    chip and (4700) after the blocked reduction."""
+    _say(f"naf kept-only n={n}")
+    rng = np.random.default_rng(300 + n)
+    m = n + 7
+    X = rng.standard_normal((m, n)) / np.sqrt(m)
+    out = []
+    for want in (True, False):
+        K = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        U = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        k, ev = gw.gw_naf_compress(ctx, "fp64", n, None, dev(X, "fp64"), K, 0, 1, eps, 0, U,
+                                   want_eigvals=want)
+        gw.gw_sync(ctx)
+        out.append((k, ev, U[:k].clone()))
+    (k1, ev1, U1), (k2, ev2, U2) = out
+    assert ev2 is None and 0 < k1 < n
+    assert k1 == k2 == int(np.sum(ev1 > eps))
+    # both eigenvalue sets are converged to a few ulps of ||T||; the vectors
+    # of the isolated eigenvalues of this spectrum follow to rounding
+    assert (U1 - U2).abs().max().item() < 1e-10
+
+
 @pytest.mark.parametrize("n", [300, 3350])
 def test_naf_eigensolver_degenerate_spectrum(gw, ctx, n):
     """A metric with one eigenvalue of multiplicity n (columns of R already
