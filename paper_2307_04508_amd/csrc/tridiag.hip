@@ -650,8 +650,14 @@ gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in) {
   std::vector<int> order(n_jobs);
   for (int d = 0; d < n_jobs; ++d) order[d] = d;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return all[x].n > all[y].n; });
+  // First fit decreasing: a launch takes the largest job left, then every
+  // smaller job left that still fits its resident workgroups (a launch lasts
+  // as long as its largest job, so the smaller ones ride along)
+  std::vector<char> done(n_jobs, 0);
   size_t pos = 0;
   while (pos < order.size()) {
+    while (pos < order.size() && done[order[pos]]) ++pos;
+    if (pos == order.size()) break;
     const int C = (all[order[pos]].n + TNT - 1) / TNT;
     void* fn = tridiag_fn_for(C);
     int per_cu = 0;
@@ -662,12 +668,14 @@ gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in) {
                   all[order[pos]].G);
     std::vector<TriJob> grp;
     int wg = 0;
-    while (pos < order.size() && wg + all[order[pos]].G <= cap) {
-      TriJob t = all[order[pos]];
+    for (size_t q = pos; q < order.size(); ++q) {
+      const int d = order[q];
+      if (done[d] || wg + all[d].G > cap) continue;
+      TriJob t = all[d];
       t.wg0 = wg;
       wg += t.G;
       grp.push_back(t);
-      ++pos;
+      done[d] = 1;
     }
     const TriJob* dj = static_cast<const TriJob*>(stage(ctx, grp.data(), grp.size() * sizeof(TriJob)));
     if (!dj) return GW_EINVAL;
