@@ -40,6 +40,10 @@ struct G64 {
   int64_t lda, ldb, ldc;
   double alpha, beta;       // C = alpha (A B) + beta C; beta == 0: C is not read
   int tm, tn;               // tiles along M and N
+  // split K in the kernel (a descriptor passed by value): unit u takes
+  // split u / (tm tn), k in [s kper, (s + 1) kper), C + s cstride
+  int splits, kper;
+  int64_t cstride;
 };
 
 // Register stage of one operand: 8 consecutive elements of one row.  A
@@ -80,12 +84,22 @@ __device__ __forceinline__ void dg_store(double (*S)[GLD], int tid, const double
 // (else [n][k]).  Operand tiles of 16 k are staged k-major in LDS from
 // registers loaded one stage ahead.
 template <bool AK, bool BK>
-__global__ __launch_bounds__(256, 2) void dgemm_kernel(Batch bt) {
+__global__ __launch_bounds__(256, 2) void dgemm_kernel(Batch bt, G64 a0) {
   __shared__ double As[2][GBK][GLD];
   __shared__ double Bs[2][GBK][GLD];
   G64 g;
   int64_t lid;
-  if (!unit_of(G64{}, bt, g, lid)) return;
+  if (!unit_of(a0, bt, g, lid)) return;
+  if (g.splits > 1) {
+    const int64_t per = (int64_t)g.tm * g.tn;
+    const int sp = (int)(lid / per);
+    lid -= sp * per;
+    const int k0 = min(g.K, sp * g.kper);
+    g.K = min(g.K - k0, g.kper);
+    g.A += AK ? (int64_t)k0 * g.lda : k0;
+    g.B += BK ? (int64_t)k0 * g.ldb : k0;
+    g.C += sp * g.cstride;
+  }
   const int tn_ = (int)(lid % g.tn), tm_ = (int)(lid / g.tn);
   const int m0 = tm_ * GBM, n0 = tn_ * GBM;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -302,7 +316,11 @@ __global__ __launch_bounds__(256) void bisect_kernel(BisArgs a) {
   if (live && q == 0) a.lam[u] = 0.5 * (lo + hi);
 }
 
-// One inverse-iteration vector per thread.  Per-thread arrays live in
+// Inverse iteration for what twisted_kernel leaves: clusters (each led by one
+// thread) and isolated eigenvalues it marked.  One vector per thread, only
+// kInvLanes lanes of each 64-thread workgroup active, so that the serial
+// passes' loads (one cache line per lane) spread over more compute units
+// (A = 3000: 3.19 ms with 64 lanes, 2.51 ms with 8).  Per-thread arrays live in
 // scratch, each thread's contiguous ([thread][array][i]): 0 reciprocal
 // pivot, 1 and 2 the two superdiagonals of U, 3 the multiplier, 4 the
 // vector, 5 the interchange flag of row pair (k, k + 1).  (Interleaved over
@@ -314,6 +332,8 @@ __global__ __launch_bounds__(256) void bisect_kernel(BisArgs a) {
 constexpr int kInvArrays = 6;
 
 constexpr int kInvCh = 8;           // prefetch chunk of the inverse-iteration passes
+constexpr int kInvStatus = 5;       // array whose element 0 holds twisted_kernel's status
+constexpr int kInvLanes = 8;        // active lanes per workgroup of invit_kernel
 
 struct InvJob {
   int s, nb;                // block rows
@@ -331,6 +351,7 @@ struct InvArgs {
   double* Z;                // [rows][ldz]
   int64_t ldz;
   double* scratch;          // [n_jobs][kInvArrays][n]
+  int lanes;                // active lanes per 64-thread workgroup (1..64)
 };
 
 __device__ __forceinline__ double rand_pm1(uint64_t key) {
@@ -356,10 +377,13 @@ __device__ __forceinline__ void ping_pong(int first, int step, M more, R& A, R& 
 }
 
 __global__ __launch_bounds__(64) void invit_kernel(InvArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int)threadIdx.x >= a.lanes) return;
+  const int t = blockIdx.x * a.lanes + threadIdx.x;
   if (t >= a.n_jobs) return;
   const InvJob lead = a.jobs[t];
   if (lead.clen == 0) return;
+  // an isolated eigenvalue whose vector twisted_kernel has written
+  if (lead.clen == 1 && a.scratch[(int64_t)t * kInvArrays * a.n + kInvStatus * a.n] == 0.0) return;
   // each thread's arrays are contiguous, [thread][array][i]: the addresses
   // of a chunk are one base plus constant offsets (no per-element address
   // arithmetic), at the cost of one cache line per lane per load
@@ -525,6 +549,156 @@ __global__ __launch_bounds__(64) void invit_kernel(InvArgs a) {
   }
 }
 
+// Eigenvector of an isolated eigenvalue lam from the twisted factorisation
+// of T - lam I (Fernando; Parlett and Dhillon): the top-down pivots
+// D+_i = d_i - lam - e_{i-1}^2 / D+_{i-1} and the bottom-up pivots
+// D-_i = d_i - lam - e_i^2 / D-_{i+1} give, for every twist index r,
+// gamma_r = D+_r + D-_r - (d_r - lam), the reciprocal of the r-th diagonal
+// entry of (T - lam I)^-1.  At r = argmin |gamma_r| the solution of
+// (T - lam I) z = gamma_r e_r with z_r = 1 is z_i = -(e_i / D+_i) z_{i+1}
+// above r and z_i = -(e_{i-1} / D-_i) z_{i-1} below it: one solve from the
+// best possible start vector, with residual |gamma_r| / ||z||.
+// One wave per job: lanes 0 and 1 run the two pivot recurrences side by
+// side (the only serial part), the wave takes the argmin, then builds z in
+// chunks of 64 by prefix products across the lanes, and normalises it (the
+// sign as below).
+// Pivots below eps ||T|| in magnitude are replaced by +-eps ||T||, as in the
+// Sturm counts.  A sum of squares out of range marks the job for
+// invit_kernel (status 1); status 0 means the row of Z is final.
+// Scratch per job: [kInvArrays][n], arrays 0-3 D+, e_i / D+_i, D-,
+// e_{i-1} / D-_i; element 0 of array kInvStatus the status.
+__global__ __launch_bounds__(64) void twisted_kernel(InvArgs a) {
+  const int t = blockIdx.x;
+  const InvJob jb = a.jobs[t];
+  if (jb.clen != 1) return;                         // clusters: invit_kernel
+  const int lane = threadIdx.x;
+  const int s = jb.s, nb = jb.nb;
+  const double* __restrict__ d = a.d + s;
+  const double* __restrict__ e = a.e + s;
+  const double lam = jb.lam, tiny = a.tiny;
+  const int64_t plane = a.n;
+  double* base = a.scratch + (int64_t)t * kInvArrays * plane;
+  double* piv_f = base;
+  double* mul_f = base + plane;
+  double* piv_b = base + 2 * plane;
+  double* mul_b = base + 3 * plane;
+  double* status = base + kInvStatus * plane;
+  if (lane < 2) {
+    // step k handles row k (top-down) or row nb - 1 - k (bottom-up); cn is
+    // the coupling to the row the next step handles
+    const bool fwd = lane == 0;
+    double* piv = fwd ? piv_f : piv_b;
+    double* mul = fwd ? mul_f : mul_b;
+    double g = 0.0, cprev = 0.0;
+    struct R { double dd[kInvCh], cn[kInvCh]; } A, B;
+    auto load = [&](int k0, R& r) {
+#pragma unroll
+      for (int j = 0; j < kInvCh; ++j) {
+        const int k = k0 + j;
+        const int i = fwd ? k : nb - 1 - k;
+        r.dd[j] = k < nb ? d[i] : 0.0;
+        r.cn[j] = k + 1 < nb ? (fwd ? e[i] : e[i - 1]) : 0.0;
+      }
+    };
+    load(0, A);
+    ping_pong(0, kInvCh, [&](int k0) { return k0 < nb; }, A, B, [&](int k0, R& cur, R& nxt) {
+      if (k0 + kInvCh < nb) load(k0 + kInvCh, nxt);
+#pragma unroll
+      for (int j = 0; j < kInvCh; ++j) {
+        const int k = k0 + j;
+        if (k < nb) {
+          const int i = fwd ? k : nb - 1 - k;
+          double x = (cur.dd[j] - lam) - cprev * g;
+          if (fabs(x) < tiny) x = copysign(tiny, x);
+          g = cur.cn[j] * rcp64(x);
+          piv[i] = x;
+          mul[i] = g;
+          cprev = cur.cn[j];
+        }
+      }
+    });
+  }
+  __syncthreads();
+  // twist index: the first i of least |gamma_i|
+  double best = HUGE_VAL;
+  int bi = nb;
+  for (int i = lane; i < nb; i += 64) {
+    const double gm = fabs(piv_f[i] + piv_b[i] - (d[i] - lam));
+    if (gm < best) {
+      best = gm;
+      bi = i;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ob < best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  const int r = bi;                                 // uniform; nb if no finite gamma
+  double* z = a.Z + (int64_t)jb.row * a.ldz;
+  // the sign makes z's projection on the counter-based random vector
+  // rand_pm1(key + i) positive, so that it does not follow the choice of r
+  const uint64_t key = (uint64_t)jb.row << 32;
+  double ss = 0.0, dot = 0.0;
+  if (r < nb) {
+    for (int i = lane; i < s; i += 64) z[i] = 0.0;
+    for (int i = s + nb + lane; i < a.n; i += 64) z[i] = 0.0;
+    if (lane == 0) {
+      z[s + r] = 1.0;
+      ss = 1.0;
+      dot = rand_pm1(key + (uint64_t)r);
+    }
+    // z_{r-k} = z_{r-k+1} (-e_{r-k} / D+_{r-k}), k = 1..nd (upwards) and
+    // z_{r+k} = z_{r+k-1} (-e_{r+k-1} / D-_{r+k}), k = 1..nu (downwards):
+    // lane l takes k = k0 + l + 1; inclusive prefix products across the
+    // lanes, times the carry (the chunk's last z) of the previous chunk
+    const int nd = r, nu = nb - 1 - r;
+    const int steps = nd > nu ? nd : nu;
+    double cd = 1.0, cu = 1.0;
+    for (int k0 = 0; k0 < steps; k0 += 64) {
+      const int k = k0 + lane + 1;
+      double md = k <= nd ? -mul_f[r - k] : 1.0;
+      double mu = k <= nu ? -mul_b[r + k] : 1.0;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const double pd = __shfl_up(md, off), pu = __shfl_up(mu, off);
+        if (lane >= off) {
+          md *= pd;
+          mu *= pu;
+        }
+      }
+      const double zd = cd * md, zu = cu * mu;
+      if (k <= nd) {
+        z[s + r - k] = zd;
+        ss += zd * zd;
+        dot += zd * rand_pm1(key + (uint64_t)(r - k));
+      }
+      if (k <= nu) {
+        z[s + r + k] = zu;
+        ss += zu * zu;
+        dot += zu * rand_pm1(key + (uint64_t)(r + k));
+      }
+      cd = __shfl(zd, 63);
+      cu = __shfl(zu, 63);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      ss += __shfl_xor(ss, off);
+      dot += __shfl_xor(dot, off);
+    }
+  }
+  if (!(ss > 0.0 && ss < 1e300)) {
+    if (lane == 0) status[0] = 1.0;
+    return;
+  }
+  __syncthreads();
+  const double f = (dot < 0.0 ? -1.0 : 1.0) / sqrt(ss);
+  for (int i = lane; i < nb; i += 64) z[s + i] *= f;
+  if (lane == 0) status[0] = 0.0;
+}
+
 __global__ void add_identity_kernel(double* G, int n, int64_t ld, double v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) G[(int64_t)i * ld + i] += v;
@@ -637,6 +811,9 @@ gw_status dgemm_run(gw_ctx ctx, const std::vector<DGemm>& v, int splits, double*
       d.alpha = g.alpha;
       d.tm = tm;
       d.tn = tnn;
+      d.splits = 1;
+      d.kper = 0;
+      d.cstride = 0;
       descs.push_back(d);
       off.push_back(off.back() + (int64_t)tm * tnn);
     }
@@ -646,15 +823,32 @@ gw_status dgemm_run(gw_ctx ctx, const std::vector<DGemm>& v, int splits, double*
     }
   }
   if (descs.empty()) return GW_OK;
-  Batch bt;
-  GW_TRY(stage_batch(ctx, descs, off, 1, bt));
-  const dim3 grid((unsigned)off.back()), block(256);
+  // one product (its K splits included): the descriptor goes by value with
+  // the launch, no staging copy; several: a staged descriptor array
+  Batch bt{nullptr, nullptr, 0, 1, 0};
+  G64 a0 = descs[0];
+  const int64_t units = off.back();
+  if (descs.size() == (size_t)S) {
+    // descs[0] is split 0 of the one product: widen it to the whole K
+    const DGemm* one = nullptr;
+    for (const DGemm& g : v)
+      if (g.M > 0 && g.N > 0) one = &g;
+    a0.A = one->A;
+    a0.B = one->B;
+    a0.K = one->K;
+    a0.splits = S;
+    a0.kper = ((one->K + S - 1) / S + GBK - 1) / GBK * GBK;
+    a0.cstride = (int64_t)one->M * one->N;
+  } else {
+    GW_TRY(stage_batch(ctx, descs, off, 1, bt));
+  }
+  const dim3 grid((unsigned)units), block(256);
   if (ak && bk)
-    hipLaunchKernelGGL((dgemm_kernel<true, true>), grid, block, 0, ctx->stream, bt);
+    hipLaunchKernelGGL((dgemm_kernel<true, true>), grid, block, 0, ctx->stream, bt, a0);
   else if (!ak && !bk)
-    hipLaunchKernelGGL((dgemm_kernel<false, false>), grid, block, 0, ctx->stream, bt);
+    hipLaunchKernelGGL((dgemm_kernel<false, false>), grid, block, 0, ctx->stream, bt, a0);
   else if (!ak && bk)
-    hipLaunchKernelGGL((dgemm_kernel<false, true>), grid, block, 0, ctx->stream, bt);
+    hipLaunchKernelGGL((dgemm_kernel<false, true>), grid, block, 0, ctx->stream, bt, a0);
   else
     return fail(ctx, GW_EINVAL, "dgemm_run: layout not built");
   GW_TRY(launch_check(ctx, "dgemm_kernel"));
@@ -667,15 +861,16 @@ gw_status dgemm_run(gw_ctx ctx, const std::vector<DGemm>& v, int splits, double*
 }
 
 constexpr int kBackSplits = 8;        // K splits of the V^T Z products
+constexpr int kGramSplits = 8;        // K splits of the Gram matrices V_b^T V_b
 
 // Back-transformation workspace at order n for `cols` vectors, in doubles.
 static size_t back_ws_elems(int n, int cols) {
   const int nb = kTriBackNb;
   const size_t blocks = n > 1 ? (size_t)(n - 1 + nb - 1) / nb : 0;
   const size_t nb2 = (size_t)nb * nb;
-  // T blocks, Gram partials (2 splits) or recursion temporaries, T V
+  // T blocks, Gram partials (kGramSplits) or recursion temporaries, T V
   // products, V^T Z partials and their sum
-  return blocks * nb2 + 2 * blocks * nb2 + blocks * nb * (size_t)n +
+  return blocks * nb2 + (size_t)kGramSplits * blocks * nb2 + blocks * nb * (size_t)n +
          (size_t)(kBackSplits + 1) * nb * cols;
 }
 
@@ -704,8 +899,8 @@ static gw_status tri_back_own(gw_ctx ctx, double* K, int n, const double* d_tau,
   const int n_blocks = (n_refl + nb - 1) / nb;
   const size_t nb2 = (size_t)nb * nb;
   double* Tm = ws;                                          // [n_blocks][nb][nb]
-  double* tmp = Tm + n_blocks * nb2;                        // [2 n_blocks][nb][nb]
-  double* P = tmp + 2 * n_blocks * nb2;                     // per block [w][n - r0]
+  double* tmp = Tm + n_blocks * nb2;                        // [kGramSplits n_blocks][nb][nb]
+  double* P = tmp + (size_t)kGramSplits * n_blocks * nb2;   // per block [w][n - r0]
   double* Wp = P + (size_t)n_blocks * nb * n;               // [kBackSplits][nb][cols]
   double* W = Wp + (size_t)kBackSplits * nb * cols;         // [nb][cols]
   hipLaunchKernelGGL(explicit_reflectors_kernel, dim3(n_refl), dim3(256), 0, ctx->stream, K, n,
@@ -718,7 +913,7 @@ static gw_status tri_back_own(gw_ctx ctx, double* K, int n, const double* d_tau,
     const double* Vb = K + (int64_t)k0 * n + r0;            // row j: reflector k0 + j, ld n
     g.push_back(DGemm{false, false, Vb, Vb, Tm + b * nb2, w, w, n - r0, n, n, nb, 1.0, 0.0});
   }
-  GW_TRY(dgemm_run(ctx, g, 2, tmp));
+  GW_TRY(dgemm_run(ctx, g, kGramSplits, tmp));
   hipLaunchKernelGGL(tinv_kernel, dim3(n_blocks), dim3(256), 0, ctx->stream, Tm, nb, n_refl,
                      d_tau);
   GW_TRY(launch_check(ctx, "tinv_kernel"));
@@ -918,11 +1113,14 @@ gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const d
   const InvJob* d_jobs = stage_t(ctx, jobs.data(), jobs.size());
   if (!d_jobs) return GW_EINVAL;
   double* Z = rest;                                   // [keep][n]
-  double* scratch = Z + (size_t)keep * n;             // [kInvArrays][n][keep]
+  double* scratch = Z + (size_t)keep * n;             // [keep][kInvArrays][n]
   const int pi = prof_begin(ctx);
-  const InvArgs ia{d_d, d_ez, d_jobs, (int)jobs.size(), n, eps * tn, Z, (int64_t)n, scratch};
-  hipLaunchKernelGGL(invit_kernel, dim3((unsigned)((jobs.size() + 63) / 64)), dim3(64), 0,
-                     ctx->stream, ia);
+  const int nj = (int)jobs.size();
+  const InvArgs ia{d_d, d_ez, d_jobs, nj, n, eps * tn, Z, (int64_t)n, scratch, kInvLanes};
+  hipLaunchKernelGGL(twisted_kernel, dim3((unsigned)nj), dim3(64), 0, ctx->stream, ia);
+  GW_TRY(launch_check(ctx, "twisted_kernel"));
+  hipLaunchKernelGGL(invit_kernel, dim3((unsigned)((nj + kInvLanes - 1) / kInvLanes)), dim3(64),
+                     0, ctx->stream, ia);
   GW_TRY(launch_check(ctx, "invit_kernel"));
   prof_end(ctx, pi, "naf_invit", 0.0, 0.0);
   // Newton-Schulz: G = -Z Z^T / 2 + 3 I / 2, U = G Z (G symmetric: TN)
