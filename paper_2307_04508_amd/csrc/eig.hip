@@ -2,16 +2,17 @@
 // tridiagonal form (tridiag.hip), with no library calls:
 //
 //  * eigenvalues by multisection on Sturm counts, per unreduced block of the
-//    tridiagonal matrix T: 16 lanes evaluate 16 points of the eigenvalue's
-//    bracket, the bracket shrinks 17-fold per round (~14 rounds to FP64);
-//  * the kept eigenvectors by inverse iteration, one thread per vector: an
-//    LU factorisation of T - lambda I with partial pivoting (tiny pivots
-//    replaced by eps ||T||), two solves from a pseudo-random start; vectors
-//    of eigenvalues closer than 1e-10 ||T|| inside one block are computed by
-//    one thread and Gram-Schmidt-orthogonalised against each other;
+//    tridiagonal matrix T: 8 to 32 lanes per eigenvalue evaluate as many
+//    points of its bracket per round;
+//  * the kept eigenvectors of isolated eigenvalues from the twisted
+//    factorisation of T - lambda I, one wave per vector; clusters (gaps
+//    below 1e-10 ||T|| inside one block) by inverse iteration, one thread
+//    per cluster: an LU factorisation with partial pivoting (tiny pivots
+//    replaced by eps ||T||), two solves from a pseudo-random start, the
+//    cluster's vectors Gram-Schmidt-orthogonalised against each other;
 //  * one Newton-Schulz step Z <- (3 I - Z Z^T) Z / 2 on the kept vectors
-//    (rows of Z): inverse iteration leaves inner products of order
-//    eps ||T|| / gap between neighbours, the step squares them away;
+//    (rows of Z): the solves leave inner products of order eps ||T|| / gap
+//    between neighbours, the step squares them away;
 //  * the back-transformation with the Householder reflectors in blocks of
 //    256 in compact WY form, Z <- Z (I - V T V^T)^T block by block.
 //
@@ -699,9 +700,33 @@ __global__ __launch_bounds__(64) void twisted_kernel(InvArgs a) {
   if (lane == 0) status[0] = 0.0;
 }
 
-__global__ void add_identity_kernel(double* G, int n, int64_t ld, double v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) G[(int64_t)i * ld + i] += v;
+// G (n x n, ld) with its lower triangle computed: the strictly upper part
+// <- the transpose of the strictly lower part, and v added on the diagonal.
+// One 32 x 32 tile per workgroup of 32 x 8 threads, tiles on or below the
+// diagonal only: the lower tile is read through LDS, written transposed.
+__global__ void mirror_lower_kernel(double* __restrict__ G, int n, int64_t ld, double v) {
+  __shared__ double t[32][33];
+  // blockIdx.x enumerates the lower tiles (ti >= tj) row by row
+  const int b = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+  while (ti * (ti + 1) / 2 > b) --ti;
+  const int tj = b - ti * (ti + 1) / 2;
+  const int r0 = ti * 32, c0 = tj * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int y = ty; y < 32; y += 8) {
+    const int i = r0 + y, j = c0 + tx;
+    t[y][tx] = (i < n && j < n) ? G[(int64_t)i * ld + j] : 0.0;
+  }
+  __syncthreads();
+  // element (c0 + y, r0 + tx) of the upper triangle <- t[tx][y]
+  for (int y = ty; y < 32; y += 8) {
+    const int i = c0 + y, j = r0 + tx;
+    if (i < n && j < n) {
+      if (j > i) G[(int64_t)i * ld + j] = t[tx][y];
+      else if (j == i) G[(int64_t)i * ld + j] = t[tx][y] + v;
+    }
+  }
 }
 
 // Reflector k of the reduction as an explicit vector in column k of K
@@ -862,6 +887,7 @@ gw_status dgemm_run(gw_ctx ctx, const std::vector<DGemm>& v, int splits, double*
 
 constexpr int kBackSplits = 8;        // K splits of the V^T Z products
 constexpr int kGramSplits = 8;        // K splits of the Gram matrices V_b^T V_b
+constexpr int kOrthSplits = 4;        // K splits of the Newton-Schulz Z Z^T
 
 // Back-transformation workspace at order n for `cols` vectors, in doubles.
 static size_t back_ws_elems(int n, int cols) {
@@ -878,7 +904,10 @@ static size_t back_ws_elems(int n, int cols) {
 size_t tri_solve_ws_elems(int n) {
   const size_t nn = (size_t)n * n;
   const size_t invit = nn + (size_t)kInvArrays * nn;                 // Z + per-thread arrays
-  const size_t orth = nn + 3 * nn;                                    // Z + G + G partials
+  // Z + G + kOrthSplits partials of G's lower bands (band i: at most GBM rows
+  // by GBM (i + 1) columns, so at most (n + GBM)(n + 2 GBM) / 2 per split)
+  const size_t orth =
+      nn + nn + (size_t)kOrthSplits * (((size_t)n + GBM) * ((size_t)n + 2 * GBM) / 2);
   return (size_t)n + std::max(std::max(invit, orth), back_ws_elems(n, n));
 }
 
@@ -958,7 +987,13 @@ static gw_status tri_back_own(gw_ctx ctx, double* K, int n, const double* d_tau,
     GW_TRY(dgemm_run(ctx, {DGemm{true, true, W, Pb[b], U + r0, cols, m, w, cols, m, n, -1.0, 1.0}},
                      1, nullptr));
   }
-  prof_end(ctx, pt, "naf_back", 4.0 * (double)n * n * cols, 0.0);
+  // per block 2 w cols m for V^T Z and as much for the update
+  double fl = 0.0;
+  for (int b = 0; b < n_blocks; ++b) {
+    const int k0 = b * nb;
+    fl += 4.0 * std::min(nb, n_refl - k0) * (double)cols * (n - k0 - 1);
+  }
+  prof_end(ctx, pt, "naf_back", fl, 0.0);
   return GW_OK;
 }
 
@@ -1123,18 +1158,28 @@ gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const d
                      0, ctx->stream, ia);
   GW_TRY(launch_check(ctx, "invit_kernel"));
   prof_end(ctx, pi, "naf_invit", 0.0, 0.0);
-  // Newton-Schulz: G = -Z Z^T / 2 + 3 I / 2, U = G Z (G symmetric: TN)
+  // Newton-Schulz: G = -Z Z^T / 2 + 3 I / 2, U = G Z (G symmetric: TN).
+  // Only the tile rows' lower parts of Z Z^T are multiplied (one product per
+  // 128-row band, columns up to the band's end), then mirrored.
   double* G = scratch;                                // [keep][keep]
   double* gws = G + (size_t)keep * keep;              // split-K partials of G
   const int pn = prof_begin(ctx);
-  GW_TRY(dgemm_run(ctx, {DGemm{false, false, Z, Z, G, keep, keep, n, n, n, keep, -0.5, 0.0}}, 2,
-                   gws));
-  hipLaunchKernelGGL(add_identity_kernel, dim3((keep + 255) / 256), dim3(256), 0, ctx->stream, G,
-                     keep, (int64_t)keep, 1.5);
-  GW_TRY(launch_check(ctx, "add_identity_kernel"));
+  std::vector<DGemm> gl;
+  for (int i0 = 0; i0 < keep; i0 += GBM)
+    gl.push_back(DGemm{false, false, Z + (int64_t)i0 * n, Z, G + (int64_t)i0 * keep,
+                       std::min(GBM, keep - i0), std::min(keep, i0 + GBM), n, n, n, keep, -0.5,
+                       0.0});
+  GW_TRY(dgemm_run(ctx, gl, kOrthSplits, gws));
+  {
+    const int nt = (keep + 31) / 32;
+    hipLaunchKernelGGL(mirror_lower_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(32, 8), 0,
+                       ctx->stream, G, keep, (int64_t)keep, 1.5);
+    GW_TRY(launch_check(ctx, "mirror_lower_kernel"));
+  }
   GW_TRY(dgemm_run(ctx, {DGemm{true, true, G, Z, U, keep, n, keep, keep, n, n, 1.0, 0.0}}, 1,
                    nullptr));
-  prof_end(ctx, pn, "naf_orth", 4.0 * (double)keep * keep * n, 0.0);
+  // Z Z^T counted once (symmetric) and G Z
+  prof_end(ctx, pn, "naf_orth", 3.0 * (double)keep * keep * n, 0.0);
   return tri_back_own(ctx, K, n, d_tau, U, keep, rest);
 }
 
