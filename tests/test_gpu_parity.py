@@ -486,6 +486,39 @@ def test_naf_eigensolver_orders(gw, ctx, n):
     assert np.abs(res).max() < 1e-12 * scale * max(1.0, np.sqrt(n) / 8)
 
 
+@pytest.mark.parametrize("n", [600, 3400])
+def test_naf_eigensolver_close_pairs(gw, ctx, n):
+    """A designed metric spectrum whose eigenvalue pairs sit at relative gaps
+    1e-9 ... 1e-6 of ||K|| (just above the 1e-10 ||T|| cluster threshold, so
+    each vector comes from its own twisted factorisation), plus an exact
+    triple and a pair 1e-12 apart (clusters: inverse iteration with
+    Gram-Schmidt): eigenvalues, orthonormality and residuals to the bounds of
+    the general eigensolver test, on chip (600) and in HBM (3400)."""
+    _say(f"naf eigensolver close pairs n={n}")
+    rng = np.random.default_rng(900 + n)
+    lam = 2.0 * np.exp(-np.arange(n) / (n / 10.0))
+    for j, g in ((10, 1e-9), (40, 1e-8), (90, 1e-7), (200, 1e-6)):
+        lam[j + 1] = lam[j] - g * lam[0]
+    lam[300:303] = lam[300]
+    lam[400] = lam[399] - 1e-12 * lam[0]
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    X = np.sqrt(lam / 4.0)[:, None] * Q.T        # K = 4 X^T X = Q diag(lam) Q^T
+    lam_ref = np.sort(lam)[::-1]
+    K_ref = (Q * lam) @ Q.T
+    K = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    U = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    k, ev = gw.gw_naf_compress(ctx, "fp64", n, None, dev(X, "fp64"), K, 0, 1, -1.0, 0, U)
+    gw.gw_sync(ctx)
+    assert k == n
+    scale = lam_ref[0]
+    tol = 1e-12 * max(1.0, np.sqrt(n) / 8)
+    assert np.max(np.abs(ev - lam_ref)) <= tol * scale
+    Uh = U.cpu().numpy()
+    assert np.abs(Uh @ Uh.T - np.eye(n)).max() < tol
+    res = K_ref @ Uh.T - Uh.T * ev[None, :]
+    assert np.abs(res).max() < tol * scale
+
+
 @pytest.mark.parametrize("n,eps", [(200, 1.0), (1030, 2.0), (3100, 0.5), (4700, 3.0)])
 def test_naf_kept_only_matches_full(gw, ctx, n, eps):
     """Without the eigenvalue list the solver bisects only the eigenvalues
