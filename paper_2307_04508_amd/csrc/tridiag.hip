@@ -83,7 +83,10 @@ __device__ __forceinline__ void st_dev(double* p, double v) {
 // completed stores are visible to the loads that follow the barrier without
 // a release / acquire pair: those would add an L2 write-back and an L2
 // invalidate per step (~2 us of a ~17 us step at order 3000) for plain data
-// that no other workgroup reads before the kernel ends.  The group's last
+// that no other workgroup reads before the kernel ends.  This visibility
+// argument rests on how gfx950 performs agent-scope atomics (past the
+// per-XCD L2 caches); the HIP memory model by itself orders relaxed atomics
+// only through a release / acquire pair.  The group's last
 // arrival sees the group count in the value its own increment returns, and
 // only then increments the top counter, so every arrival of the group has
 // been performed before the top counter moves.  Returns false after
