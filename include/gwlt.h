@@ -384,6 +384,9 @@ gw_status gw_autotune(gw_ctx ctx, int enable, int* n_tuned);
  *   "syrk"   FP32 / FP64 polarizability SYRK: the split-K factor S
  *   "screen", "screen_sos"  screening sweep: outer pivot width (64, 128, 256)
  *   "bwb3"   BF16x3 B W B contraction: waves per workgroup
+ *   "eigvec" NAF eigenvectors (not timed by the autotuner): 0 the twisted
+ *            factorisation for isolated eigenvalues and inverse iteration
+ *            for clusters; 1 LU inverse iteration for every vector
  * Errors: GW_EINVAL for a NULL ctx or family, modulus < 0, or a residue
  * outside [0, modulus). */
 gw_status gw_autotune_restrict(gw_ctx ctx, const char* family, int modulus, int residue);

@@ -318,7 +318,8 @@ __global__ __launch_bounds__(256) void bisect_kernel(BisArgs a) {
 }
 
 // Inverse iteration for what twisted_kernel leaves: clusters (each led by one
-// thread) and isolated eigenvalues it marked.  One vector per thread, only
+// thread) and isolated eigenvalues it marked (every vector when lu_all is
+// set and twisted_kernel does not run).  One vector per thread, only
 // kInvLanes lanes of each 64-thread workgroup active, so that the serial
 // passes' loads (one cache line per lane) spread over more compute units
 // (A = 3000: 3.19 ms with 64 lanes, 2.51 ms with 8).  Per-thread arrays live in
@@ -353,6 +354,7 @@ struct InvArgs {
   int64_t ldz;
   double* scratch;          // [n_jobs][kInvArrays][n]
   int lanes;                // active lanes per 64-thread workgroup (1..64)
+  int lu_all;               // every vector by inverse iteration (twisted_kernel not run)
 };
 
 __device__ __forceinline__ double rand_pm1(uint64_t key) {
@@ -384,7 +386,9 @@ __global__ __launch_bounds__(64) void invit_kernel(InvArgs a) {
   const InvJob lead = a.jobs[t];
   if (lead.clen == 0) return;
   // an isolated eigenvalue whose vector twisted_kernel has written
-  if (lead.clen == 1 && a.scratch[(int64_t)t * kInvArrays * a.n + kInvStatus * a.n] == 0.0) return;
+  if (lead.clen == 1 && !a.lu_all &&
+      a.scratch[(int64_t)t * kInvArrays * a.n + kInvStatus * a.n] == 0.0)
+    return;
   // each thread's arrays are contiguous, [thread][array][i]: the addresses
   // of a chunk are one base plus constant offsets (no per-element address
   // arithmetic), at the cost of one cache line per lane per load
@@ -997,6 +1001,15 @@ static gw_status tri_back_own(gw_ctx ctx, double* K, int n, const double* d_tau,
   return GW_OK;
 }
 
+// The "eigvec" family of gw_autotune_restrict allows code 1 and not code 0:
+// every eigenvector by LU inverse iteration.
+static bool eigvec_lu_only(gw_ctx ctx) {
+  const auto f = ctx->tune_filter.find("eigvec");
+  if (f == ctx->tune_filter.end()) return false;
+  const int mod = f->second.first, res = f->second.second;
+  return 0 % mod != res && 1 % mod == res;
+}
+
 // Number of eigenvalues of the block (d, e2 as in sturm_count) below x, on
 // the host.
 static int sturm_count_host(const double* d, const double* e2, int nb, double x,
@@ -1151,9 +1164,13 @@ gw_status naf_tri_solve(gw_ctx ctx, double* K, int n, const double* d_d, const d
   double* scratch = Z + (size_t)keep * n;             // [keep][kInvArrays][n]
   const int pi = prof_begin(ctx);
   const int nj = (int)jobs.size();
-  const InvArgs ia{d_d, d_ez, d_jobs, nj, n, eps * tn, Z, (int64_t)n, scratch, kInvLanes};
-  hipLaunchKernelGGL(twisted_kernel, dim3((unsigned)nj), dim3(64), 0, ctx->stream, ia);
-  GW_TRY(launch_check(ctx, "twisted_kernel"));
+  const bool lu_all = eigvec_lu_only(ctx);
+  const InvArgs ia{d_d,  d_ez, d_jobs, nj, n, eps * tn, Z, (int64_t)n, scratch, kInvLanes,
+                   lu_all ? 1 : 0};
+  if (!lu_all) {
+    hipLaunchKernelGGL(twisted_kernel, dim3((unsigned)nj), dim3(64), 0, ctx->stream, ia);
+    GW_TRY(launch_check(ctx, "twisted_kernel"));
+  }
   hipLaunchKernelGGL(invit_kernel, dim3((unsigned)((nj + kInvLanes - 1) / kInvLanes)), dim3(64),
                      0, ctx->stream, ia);
   GW_TRY(launch_check(ctx, "invit_kernel"));

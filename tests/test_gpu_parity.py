@@ -519,6 +519,34 @@ def test_naf_eigensolver_close_pairs(gw, ctx, n):
     assert np.abs(res).max() < tol * scale
 
 
+@pytest.mark.parametrize("n", [1030, 3400])
+def test_naf_eigvec_methods_agree(gw, ctx, n):
+    """The twisted-factorisation eigenvectors against LU inverse iteration for
+    every vector (gw_autotune_restrict family "eigvec", code 1; also the path
+    an isolated eigenvalue takes when its twisted vector is out of range).
+    Both take the sign of the projection on the same counter-based random
+    vector, so the kept rows of U agree to rounding; on chip and in HBM."""
+    _say(f"naf eigvec methods n={n}")
+    rng = np.random.default_rng(1200 + n)
+    m = n + 7
+    X = rng.standard_normal((m, n)) / np.sqrt(m)
+    out = []
+    for code in (0, 1):
+        gw.gw_autotune_restrict(ctx, "eigvec", 2, code)
+        try:
+            K = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+            U = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+            k, ev = gw.gw_naf_compress(ctx, "fp64", n, None, dev(X, "fp64"), K, 0, 1, 1.0, 0, U)
+            gw.gw_sync(ctx)
+        finally:
+            gw.gw_autotune_restrict(ctx, "eigvec", 0, 0)
+        out.append((k, ev, U[:k].clone()))
+    (k0, ev0, U0), (k1, ev1, U1) = out
+    assert 0 < k0 == k1 < n
+    assert np.array_equal(ev0, ev1)
+    assert (U0 - U1).abs().max().item() < 1e-10
+
+
 @pytest.mark.parametrize("n,eps", [(200, 1.0), (1030, 2.0), (3100, 0.5), (4700, 3.0)])
 def test_naf_kept_only_matches_full(gw, ctx, n, eps):
     """Without the eigenvalue list the solver bisects only the eigenvalues
