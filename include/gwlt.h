@@ -391,6 +391,22 @@ gw_status gw_autotune(gw_ctx ctx, int enable, int* n_tuned);
  * outside [0, modulus). */
 gw_status gw_autotune_restrict(gw_ctx ctx, const char* family, int modulus, int residue);
 
+/* Keep the autotuner's choices across processes.  gw_autotune_save writes
+ * the choices kept on this context to the text file `path` (overwritten):
+ * a first line naming the format and the device (architecture and
+ * compute-unit count), then one line "<choice> <shape key>" per tuned
+ * shape.  gw_autotune_load reads such a file into the context's kept
+ * choices (replacing those of the same shapes; *n_loaded, may be NULL,
+ * receives the number read).  A loaded choice is used like one timed on
+ * the context: only while it is among the shape's current candidates (see
+ * gw_autotune_restrict), otherwise the shape is tuned or defaulted as
+ * usual.  Errors: GW_EINVAL for a NULL ctx or path, a file that cannot be
+ * opened or written, a file saved on another kind of device, or a
+ * malformed line (the context is then left unchanged); GW_EDEVICE when
+ * the device properties cannot be read. */
+gw_status gw_autotune_save(gw_ctx ctx, const char* path);
+gw_status gw_autotune_load(gw_ctx ctx, const char* path, int* n_loaded);
+
 /* ----------------------------------------------------------- workspace */
 
 /* Largest sizes the per-step calls will see on a context. */

@@ -1,6 +1,9 @@
 // Context lifetime, workspace, staging and error reporting.
 #include <algorithm>
 #include <cstdarg>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
 
 #include "common.hpp"
 
@@ -308,6 +311,65 @@ gw_status gw_autotune(gw_ctx ctx, int enable, int* n_tuned) {
   if (enable >= 0) ctx->autotune = enable != 0;
   if (enable == 2) ctx->tuned.clear();
   if (n_tuned) *n_tuned = (int)ctx->tuned.size();
+  return GW_OK;
+}
+
+// First line of a saved choice file: the format and the device the choices
+// were timed on (architecture and compute-unit count).
+static gw_status tune_file_header(gw_ctx ctx, std::string& out) {
+  hipDeviceProp_t prop;
+  GW_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "# gwlt autotune 1 arch=%s cus=%d", prop.gcnArchName,
+                prop.multiProcessorCount);
+  out = buf;
+  return GW_OK;
+}
+
+gw_status gw_autotune_save(gw_ctx ctx, const char* path) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_autotune_save: ctx is NULL");
+  gw::clear_error(ctx);
+  if (!path) return gw::fail(ctx, GW_EINVAL, "gw_autotune_save: path is NULL");
+  std::string hdr;
+  GW_TRY(tune_file_header(ctx, hdr));
+  std::ofstream f(path, std::ios::out | std::ios::trunc);
+  if (!f) return gw::fail(ctx, GW_EINVAL, "gw_autotune_save: cannot open %s", path);
+  f << hdr << "\n";
+  for (const auto& kv : ctx->tuned) f << kv.second << " " << kv.first << "\n";
+  f.close();
+  if (!f) return gw::fail(ctx, GW_EINVAL, "gw_autotune_save: writing %s failed", path);
+  return GW_OK;
+}
+
+gw_status gw_autotune_load(gw_ctx ctx, const char* path, int* n_loaded) {
+  if (!ctx) return gw::fail(nullptr, GW_EINVAL, "gw_autotune_load: ctx is NULL");
+  gw::clear_error(ctx);
+  if (n_loaded) *n_loaded = 0;
+  if (!path) return gw::fail(ctx, GW_EINVAL, "gw_autotune_load: path is NULL");
+  std::string hdr;
+  GW_TRY(tune_file_header(ctx, hdr));
+  std::ifstream f(path);
+  if (!f) return gw::fail(ctx, GW_EINVAL, "gw_autotune_load: cannot open %s", path);
+  std::string line;
+  if (!std::getline(f, line) || line != hdr)
+    return gw::fail(ctx, GW_EINVAL, "gw_autotune_load: %s was not saved on this device (%s)",
+                    path, hdr.c_str());
+  // parse everything first: a malformed file changes nothing
+  std::map<std::string, int> got;
+  int lineno = 1;
+  while (std::getline(f, line)) {
+    ++lineno;
+    if (line.empty()) continue;
+    std::istringstream ls(line);
+    int choice = 0;
+    std::string key;
+    if (!(ls >> choice) || ls.get() != ' ' || !std::getline(ls, key) || key.empty() ||
+        key.find(' ') != std::string::npos)
+      return gw::fail(ctx, GW_EINVAL, "gw_autotune_load: %s line %d is malformed", path, lineno);
+    got[key] = choice;
+  }
+  for (const auto& kv : got) ctx->tuned[kv.first] = kv.second;
+  if (n_loaded) *n_loaded = (int)got.size();
   return GW_OK;
 }
 

@@ -39,7 +39,8 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_set_stream", "gw_sync", "gw_last_error
            "gw_polarizability_lt_batched", "gw_screen_batched", "gw_sigma_diag_batched",
            "gw_qp_solve_batched", "gw_g0w0_batched", "gw_reserve", "gw_naf_compress_batched",
            "gw_naf_apply_batched", "gw_autotune", "gw_evgw", "gw_polarizability_sos",
-           "gw_screen_sos", "gw_lt_grid_auto", "gw_sigma_diag_noalloc", "gw_autotune_restrict"]
+           "gw_screen_sos", "gw_lt_grid_auto", "gw_sigma_diag_noalloc", "gw_autotune_restrict",
+           "gw_autotune_save", "gw_autotune_load"]
 
 c_int, c_i64, c_dbl, c_vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_DBL = ctypes.POINTER(ctypes.c_double)
@@ -155,6 +156,8 @@ _sig = {
                 c_vp, P_DBL, P_DBL, P_INT, P_DBL, ctypes.POINTER(GwStats)],
     "gw_autotune": [c_vp, c_int, P_INT],
     "gw_autotune_restrict": [c_vp, ctypes.c_char_p, c_int, c_int],
+    "gw_autotune_save": [c_vp, ctypes.c_char_p],
+    "gw_autotune_load": [c_vp, ctypes.c_char_p, P_INT],
     "gw_naf_compress_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafJob)],
     "gw_naf_apply_batched": [c_vp, c_int, c_int, ctypes.POINTER(NafApplyJob)],
     "gw_graph_begin": [c_vp],
@@ -632,6 +635,18 @@ def gw_autotune_restrict(ctx, family: str, modulus: int, residue: int = 0) -> No
     residue (modulus 0 lifts the restriction)."""
     _check(_lib.gw_autotune_restrict(ctx.handle, family.encode(), int(modulus), int(residue)),
            ctx)
+
+
+def gw_autotune_save(ctx, path) -> None:
+    """Write the context's kept autotuner choices to a text file."""
+    _check(_lib.gw_autotune_save(ctx.handle, str(path).encode()), ctx)
+
+
+def gw_autotune_load(ctx, path) -> int:
+    """Read saved autotuner choices into the context; returns their number."""
+    n = ctypes.c_int(0)
+    _check(_lib.gw_autotune_load(ctx.handle, str(path).encode(), ctypes.byref(n)), ctx)
+    return n.value
 
 
 def gw_autotune(ctx, enable: int = -1) -> int:

@@ -921,3 +921,48 @@ def test_screen_outer_level_ragged_last_block(gw, ctx, N, F):
     for j in range(F):
         assert rel_fro(Wh[j], ref[j]) < 1e-11, (j, rel_fro(Wh[j], ref[j]))
         assert np.array_equal(Wh[j], Wh[j].T)
+
+
+def test_autotune_choices_persist(gw, tmp_path):
+    """Choices kept by one context, saved, and loaded by a fresh one with
+    tuning off give the same launches (the screening result bitwise); a file
+    from another device or with a malformed line is rejected and leaves the
+    context's choices as they were."""
+    N, F, L = 520, 2, 3
+    M = _spd_m(43, L, N)
+    x = np.array([0.05, 0.5, 3.0])
+    om, _ = grids.modified_gauss_legendre(F, 0.5)
+    Md = dev(M, "fp64")
+    path = tmp_path / "tune.txt"
+    c1 = gw.gw_create(0)
+    try:
+        gw.gw_autotune(c1, 2)
+        W1 = torch.zeros((F, N, N), dtype=torch.float64, device="cuda")
+        gw.gw_screen(c1, "fp64", N, x, Md, om, W1)
+        gw.gw_sync(c1)
+        n1 = gw.gw_autotune(c1)
+        assert n1 >= 1
+        gw.gw_autotune_save(c1, path)
+    finally:
+        gw.gw_destroy(c1)
+    lines = path.read_text().splitlines()
+    assert lines[0].startswith("# gwlt autotune 1 arch=") and len(lines) == 1 + n1
+    c2 = gw.gw_create(0)
+    try:
+        gw.gw_autotune(c2, 0)
+        assert gw.gw_autotune_load(c2, path) == n1
+        assert gw.gw_autotune(c2) == n1
+        W2 = torch.zeros((F, N, N), dtype=torch.float64, device="cuda")
+        gw.gw_screen(c2, "fp64", N, x, Md, om, W2)
+        gw.gw_sync(c2)
+        assert torch.equal(W1, W2)
+        bad = tmp_path / "bad.txt"
+        for text in ("# gwlt autotune 1 arch=gfx000 cus=1\n128 screen:1x1\n",
+                     lines[0] + "\n128 screen:1x1\nnot a line\n"):
+            bad.write_text(text)
+            with pytest.raises(gw.GwError) as ei:
+                gw.gw_autotune_load(c2, bad)
+            assert ei.value.status == gw.GW_EINVAL
+        assert gw.gw_autotune(c2) == n1
+    finally:
+        gw.gw_destroy(c2)
