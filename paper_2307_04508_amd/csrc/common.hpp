@@ -48,6 +48,8 @@ enum WsSlot {
   WS_B3_CHI,        // BF16x3 polarizability: split scaled rows (hi, lo) of a chunk
   WS_B3_R,          // BF16x3 contraction: split QP rows (hi, lo)
   WS_B3_W,          // BF16x3 contraction: split screened interactions (hi, lo)
+  WS_TRI_SUB,       // HBM reduction: exchange buffers of its on-chip trailing part
+  WS_TRI_COPY,      // HBM reduction: contiguous copy of the trailing block
   WS_COUNT
 };
 
@@ -233,7 +235,8 @@ struct TriIn {
 int tridiag_max_order(gw_ctx ctx);
 // Householder reduction to tridiagonal form (same outputs as tridiag_jobs)
 // of one matrix of any order, held in HBM: panels of columns, each one
-// cooperative launch, and a rank-2·panel trailing update on FP64 MFMA.
+// cooperative launch, and a rank-2·panel trailing update on FP64 MFMA, until
+// the trailing block fits the on-chip reduction, which finishes it.
 // Asynchronous; a barrier timeout raises ctx->d_flags[1].
 gw_status tridiag_blocked(gw_ctx ctx, const TriIn& job);
 // C (+)= alpha op(A) op(B) in FP64 on MFMA (eig.hip): ak, A stored [k][m]
@@ -254,7 +257,7 @@ struct DGemm {
 gw_status dgemm_run(gw_ctx ctx, const std::vector<DGemm>& v, int splits, double* ws);
 // Workspace (WS_EIG_Y, doubles) of naf_tri_solve at order n.
 size_t tri_solve_ws_elems(int n);
-gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& jobs);
+gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& jobs, WsSlot slot = WS_TRI);
 struct NafGemmJob {
   const void* A;        // [rows][K]
   const double* U;      // [>= ncols][K]

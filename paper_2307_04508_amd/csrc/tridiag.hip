@@ -613,7 +613,7 @@ int tridiag_max_order(gw_ctx ctx) {
 // first, into cooperative launches whose workgroups are all resident; each
 // launch uses the column-slot count of its largest job.  Asynchronous on the
 // context's stream; a barrier timeout raises ctx->d_flags[1].
-gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in) {
+gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in, WsSlot slot) {
   const int n_jobs = (int)in.size();
   if (n_jobs == 0) return GW_OK;
   int n_cu = 0;
@@ -626,7 +626,7 @@ gw_status tridiag_jobs(gw_ctx ctx, const std::vector<TriIn>& in) {
   };
   size_t sc = 0;
   for (const TriIn& j : in) sc += 4 * (size_t)std::max(j.n, 1) + ctr_doubles(j.n);
-  double* ws = static_cast<double*>(ws_get(ctx, WS_TRI, sc * sizeof(double)));
+  double* ws = static_cast<double*>(ws_get(ctx, slot, sc * sizeof(double)));
   if (!ws) return GW_ENOMEM;
   GW_TRY(fill_zero(ctx, ws, (int64_t)sc));
   std::vector<TriJob> all(n_jobs);
@@ -716,9 +716,16 @@ gw_status tridiag_blocked(gw_ctx ctx, const TriIn& job) {
   double* red = ybuf + n;
   unsigned* count = reinterpret_cast<unsigned*>(red + (size_t)G * HRED);
   GW_TRY(fill_zero(ctx, reinterpret_cast<double*>(count), (int64_t)ctr));
+  // Panels run up to the first panel boundary kend whose trailing block
+  // (order n - kend) the on-chip reduction takes: per column it costs a few
+  // microseconds of latency instead of a pass over the block in HBM plus two
+  // device-wide exchanges (A = 7000: the last 3300 columns ~52 ms in panels).
+  const int lim = tridiag_max_order(ctx);
+  int kend = n - 1;
+  if (lim >= 2 && n > lim) kend = (n - lim + HB - 1) / HB * HB;
   const int pt = prof_begin(ctx);
   unsigned pass0 = 0;
-  for (int k0 = 0; k0 < n - 1; k0 += HB) {
+  for (int k0 = 0; k0 < kend; k0 += HB) {
     const int jb = std::min(HB, n - 1 - k0);
     HbmArgs a{job.K, n, k0, jb, k0 + jb == n - 1 ? 1 : 0, job.d, job.e, job.tau, VW, WV, abuf,
               ybuf, red, count, pass0, ctx->d_flags + 1, 1 << 21};
@@ -728,12 +735,30 @@ gw_status tridiag_blocked(gw_ctx ctx, const TriIn& job) {
     pass0 += 2u * (unsigned)jb;
     if (!a.last) {
       // A22 -= [V W] [W V]^T over the rows and columns past the panel
-      const int kend = k0 + jb, m = n - kend;
-      GW_TRY(dgemm_run(ctx, {DGemm{false, false, VW + (size_t)kend * HB2, WV + (size_t)kend * HB2,
-                                   job.K + (size_t)kend * n + kend, m, m, HB2, HB2, HB2, n, -1.0,
+      const int ke = k0 + jb, m = n - ke;
+      GW_TRY(dgemm_run(ctx, {DGemm{false, false, VW + (size_t)ke * HB2, WV + (size_t)ke * HB2,
+                                   job.K + (size_t)ke * n + ke, m, m, HB2, HB2, HB2, n, -1.0,
                                    1.0}},
                        1, nullptr));
     }
+  }
+  if (kend < n - 1) {
+    // The updated trailing block A(kend:, kend:) is an ordinary symmetric
+    // matrix of order m: reduce it on chip (its d, e, tau land at offset
+    // kend, its reflectors in its rows in the same convention), then put the
+    // block with the reflectors back for the back-transformation.
+    const int m = n - kend;
+    double* Kc = static_cast<double*>(ws_get(ctx, WS_TRI_COPY, (size_t)m * m * sizeof(double)));
+    if (!Kc) return GW_ENOMEM;
+    double* blk = job.K + (size_t)kend * n + kend;
+    GW_HIP(ctx, hipMemcpy2DAsync(Kc, (size_t)m * sizeof(double), blk, (size_t)n * sizeof(double),
+                                 (size_t)m * sizeof(double), (size_t)m, hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+    GW_TRY(tridiag_jobs(ctx, {TriIn{Kc, m, job.d + kend, job.e + kend, job.tau + kend}},
+                        WS_TRI_SUB));
+    GW_HIP(ctx, hipMemcpy2DAsync(blk, (size_t)n * sizeof(double), Kc, (size_t)m * sizeof(double),
+                                 (size_t)m * sizeof(double), (size_t)m, hipMemcpyDeviceToDevice,
+                                 ctx->stream));
   }
   prof_end(ctx, pt, "naf_tridiag", 0.0, 0.0);
   return GW_OK;
