@@ -491,7 +491,13 @@ __global__ __launch_bounds__(HT) void tri_hbm_panel_kernel(HbmArgs a) {
     }
     // A22 v over rows and columns >= k + 1, v staged in LDS chunk by chunk;
     // row r of the workgroup's own rows is summed by wave r % (HT / 64) and
-    // kept in lane r / (HT / 64) of it
+    // kept in lane r / (HT / 64) of it.  Successive columns visit the rows
+    // in opposite directions: the passes over A22 (up to a few hundred MB)
+    // then begin with the rows the previous pass read last, which the
+    // memory-side cache still holds.  Each row's sum does not depend on
+    // the order in which the rows are visited.
+    const bool rows_down = (k & 1) != 0;
+    const int my_rows = R > wave ? (R - 1 - wave) / (HT / 64) + 1 : 0;
     double yacc = 0.0;
     for (int c0 = lo; c0 < n; c0 += HCH) {
       const int c1 = min(n, c0 + HCH);
@@ -510,7 +516,8 @@ __global__ __launch_bounds__(HT) void tri_hbm_panel_kernel(HbmArgs a) {
         }
       }
       __syncthreads();
-      for (int r = wave; r < R; r += HT / 64) {
+      for (int q = 0; q < my_rows; ++q) {
+        const int r = wave + (HT / 64) * (rows_down ? my_rows - 1 - q : q);
         const int i = g + G * r;
         if (i < lo) continue;
         const double* row = a.K + (size_t)i * n;
