@@ -594,34 +594,55 @@ __global__ __launch_bounds__(64) void twisted_kernel(InvArgs a) {
     const bool fwd = lane == 0;
     double* piv = fwd ? piv_f : piv_b;
     double* mul = fwd ? mul_f : mul_b;
+    // coupling of row i to the next row in this direction: e[i] top-down,
+    // e[i - 1] bottom-up
+    const double* ep = fwd ? e : e - 1;
     double g = 0.0, cprev = 0.0;
     struct R { double dd[kInvCh], cn[kInvCh]; } A, B;
+    // Loads without branches or selects (indices clamped into the block;
+    // e + s has at least one entry), so that the compiler can leave the
+    // prefetched chunk in flight: a load in a branch, or a select on its
+    // value, costs a wait for every outstanding access, the prefetch too.
     auto load = [&](int k0, R& r) {
 #pragma unroll
       for (int j = 0; j < kInvCh; ++j) {
-        const int k = k0 + j;
+        const int k = min(k0 + j, nb - 1);
         const int i = fwd ? k : nb - 1 - k;
-        r.dd[j] = k < nb ? d[i] : 0.0;
-        r.cn[j] = k + 1 < nb ? (fwd ? e[i] : e[i - 1]) : 0.0;
+        r.dd[j] = d[i];
+        r.cn[j] = ep[fwd ? i : max(i, 1)];
       }
     };
+    auto step = [&](int k, double dd, double craw) {
+      const int i = fwd ? k : nb - 1 - k;
+      const double cn = k + 1 < nb ? craw : 0.0;
+      double x = (dd - lam) - cprev * g;
+      if (fabs(x) < tiny) x = copysign(tiny, x);
+      g = cn * rcp64(x);
+      piv[i] = x;
+      mul[i] = g;
+      cprev = cn;
+    };
+    // two whole chunks per trip with no guard, then at most two guarded
+    // chunks; the next chunk is always in flight while one is computed
     load(0, A);
-    ping_pong(0, kInvCh, [&](int k0) { return k0 < nb; }, A, B, [&](int k0, R& cur, R& nxt) {
-      if (k0 + kInvCh < nb) load(k0 + kInvCh, nxt);
+    int k0 = 0;
+    for (; k0 + 2 * kInvCh <= nb; k0 += 2 * kInvCh) {
+      load(k0 + kInvCh, B);
 #pragma unroll
-      for (int j = 0; j < kInvCh; ++j) {
-        const int k = k0 + j;
-        if (k < nb) {
-          const int i = fwd ? k : nb - 1 - k;
-          double x = (cur.dd[j] - lam) - cprev * g;
-          if (fabs(x) < tiny) x = copysign(tiny, x);
-          g = cur.cn[j] * rcp64(x);
-          piv[i] = x;
-          mul[i] = g;
-          cprev = cur.cn[j];
-        }
-      }
-    });
+      for (int j = 0; j < kInvCh; ++j) step(k0 + j, A.dd[j], A.cn[j]);
+      load(k0 + 2 * kInvCh, A);
+#pragma unroll
+      for (int j = 0; j < kInvCh; ++j) step(k0 + kInvCh + j, B.dd[j], B.cn[j]);
+    }
+    if (k0 < nb) {
+      load(k0 + kInvCh, B);
+#pragma unroll
+      for (int j = 0; j < kInvCh; ++j)
+        if (k0 + j < nb) step(k0 + j, A.dd[j], A.cn[j]);
+#pragma unroll
+      for (int j = 0; j < kInvCh; ++j)
+        if (k0 + kInvCh + j < nb) step(k0 + kInvCh + j, B.dd[j], B.cn[j]);
+    }
   }
   __syncthreads();
   // twist index: the first i of least |gamma_i|
@@ -663,10 +684,16 @@ __global__ __launch_bounds__(64) void twisted_kernel(InvArgs a) {
     const int nd = r, nu = nb - 1 - r;
     const int steps = nd > nu ? nd : nu;
     double cd = 1.0, cu = 1.0;
+    // multipliers of the chunk at k0, clamped loads (the next chunk's are in
+    // flight while one chunk is scanned; selects at use)
+    double fd = mul_f[max(r - lane - 1, 0)], fu = mul_b[min(r + lane + 1, nb - 1)];
     for (int k0 = 0; k0 < steps; k0 += 64) {
       const int k = k0 + lane + 1;
-      double md = k <= nd ? -mul_f[r - k] : 1.0;
-      double mu = k <= nu ? -mul_b[r + k] : 1.0;
+      const double nfd = mul_f[max(r - k - 64, 0)], nfu = mul_b[min(r + k + 64, nb - 1)];
+      double md = k <= nd ? -fd : 1.0;
+      double mu = k <= nu ? -fu : 1.0;
+      fd = nfd;
+      fu = nfu;
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         const double pd = __shfl_up(md, off), pu = __shfl_up(mu, off);
