@@ -4,10 +4,12 @@
 //    virtual block omitted (Sec. 2), on the scaled-SYRK kernels with a
 //    constant scale.
 //  * Eigendecomposition of K in FP64 on the device: Householder reduction to
-//    tridiagonal form held on chip (tridiag.hip), then bisection, inverse
-//    iteration and the back-transformation of the kept eigenvectors in
-//    blocks of reflectors (eig.hip); past the on-chip limit the reduction
-//    runs in HBM by panels (tridiag.hip).  The kept
+//    tridiagonal form held on chip (tridiag.hip), then bisection, the
+//    twisted factorisation (inverse iteration for clusters), one
+//    Newton-Schulz step and the back-transformation of the kept eigenvectors
+//    in blocks of reflectors (eig.hip); past the on-chip limit the reduction
+//    runs in HBM by panels until the trailing block fits on chip
+//    (tridiag.hip).  The kept
 //    eigenvectors (eigenvalue > eps_NAF, at most max_keep) are copied in
 //    descending order into U (row p = p-th eigenvector).
 //  * Transform R~ = R U (Eq. 13): a GEMM with both operands contiguous along
@@ -491,10 +493,12 @@ gw_status check_tridiag(gw_ctx ctx) {
 
 // Eigendecompositions of several metrics.  K[d] (lower triangle) is read;
 // U[d] receives the needed eigenvectors as rows, descending (at least those
-// above eps_naf, up to max_keep); eig[d] (host, descending) all eigenvalues.
-// Every metric is copied and mirrored; those within the on-chip limit are
-// reduced to tridiagonal form together (packed cooperative launches), the
-// larger ones one by one in HBM; then bisection, inverse iteration and the
+// above eps_naf, up to max_keep); eig[d] (host, descending) the eigenvalues:
+// all of them with all_eigs, else those above eps_naf and one below, the
+// rest -inf.  Every metric is copied and mirrored; those within the on-chip
+// limit are reduced to tridiagonal form together (packed cooperative
+// launches), the larger ones one by one by panels in HBM with their
+// trailing block on chip; then bisection, the twisted eigenvectors and the
 // back-transformation per metric.  Synchronises.
 gw_status naf_eig_batched(gw_ctx ctx, const std::vector<NafEigJob>& jobs) {
   if (jobs.empty()) return GW_OK;
