@@ -115,6 +115,10 @@ def test_argument_errors_are_status_codes():
                                     None) == gwlt.GW_EINVAL
     assert lib.gw_screen(None, 0, 1, 1, None, None, 1, None, None) == gwlt.GW_EINVAL
     assert lib.gw_sync(None) == gwlt.GW_EINVAL
+    assert lib.gw_autotune_save(None, b"/nonexistent/t.txt") == gwlt.GW_EINVAL
+    n = ctypes.c_int(7)
+    assert lib.gw_autotune_load(None, b"/nonexistent/t.txt", ctypes.byref(n)) == gwlt.GW_EINVAL
+    assert lib.gw_autotune_restrict(None, b"syrk", 2, 0) == gwlt.GW_EINVAL
     assert b"NULL" in lib.gw_last_error(None) or lib.gw_last_error(None) != b""
 
 
